@@ -1,0 +1,735 @@
+// Recursion engine and the C ABI of the single-product path.
+//
+// The paper's recursion (Section 3.1) splits every operand into the four
+// quadrants of equation (1) and recurses until the operands are small enough
+// for a leaf (Table 2); its leaf call copies A and B to the device, runs the
+// kernel, copies C back and returns (the three-step call of Section 3.3).
+// Here the recursion is Winograd's 7-product form and it runs level by level
+// (breadth first): every level is one pre-addition launch per operand, all
+// 7^d leaves are one grouped MFMA launch, and every level is one
+// post-addition launch, so a depth-d product costs 2d + d + 1 launches
+// instead of thousands.  Quadrants that are plain sub-blocks (A11, A12, A22,
+// B11, B21, B22) are strided views, never copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+
+namespace fastmm {
+
+namespace {
+thread_local std::string t_last_error;
+
+constexpr size_t kAlignFloats = 64;  // 256-byte alignment of every buffer
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// A strided operand view with a valid extent (outside: zero).
+struct View {
+  const float* p;
+  int64_t ld;
+  int64_t vrows, vcols;
+};
+
+// Quadrant (qr, qc) of a view whose quadrants are h_r x h_c (equation (1)).
+View quadrant(const View& v, int qr, int qc, int64_t h_r, int64_t h_c) {
+  View q;
+  q.p = v.p + (int64_t)qr * h_r * v.ld + (int64_t)qc * h_c;
+  q.ld = v.ld;
+  q.vrows = std::min(std::max<int64_t>(v.vrows - qr * h_r, 0), h_r);
+  q.vcols = std::min(std::max<int64_t>(v.vcols - qc * h_c, 0), h_c);
+  return q;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+}  // namespace
+
+void set_error(const std::string& msg) { t_last_error = msg; }
+
+Library& lib() {
+  static Library L;
+  return L;
+}
+
+void ensure_init(Library& L) {
+  if (L.initialised) return;
+  FASTMM_HIP(hipGetDevice(&L.device));
+  hipDeviceProp_t prop;
+  FASTMM_HIP(hipGetDeviceProperties(&prop, L.device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    throw Error(kNotSupported, std::string("fastmm is built for gfx950; device is ") +
+                                   prop.gcnArchName);
+  FASTMM_HIP(hipStreamCreateWithFlags(&L.own_stream, hipStreamNonBlocking));
+  if (!L.stream) L.stream = L.own_stream;
+  for (auto& e : L.ev) FASTMM_HIP(hipEventCreate(&e));
+  L.initialised = true;
+}
+
+char* ensure_arena(Library& L, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 1);
+  // Debug/test controls, read on every call: a cap on the workspace, and
+  // NaN-poisoning of the workspace so that a read of a temporary that was
+  // never written shows up in the result.
+  L.limit = 0;
+  if (const char* s = std::getenv("FASTMM_WORKSPACE_LIMIT")) L.limit = std::strtoull(s, nullptr, 10);
+  const char* poison = std::getenv("FASTMM_POISON");
+  if (poison && poison[0] == '1' && L.arena && bytes <= L.arena_bytes)
+    FASTMM_HIP(hipMemsetAsync(L.arena, 0xFF, L.arena_bytes, L.stream));
+  if (L.limit && bytes > L.limit)
+    throw Error(kOutOfMemory, "workspace of " + std::to_string(bytes) +
+                                  " bytes exceeds FASTMM_WORKSPACE_LIMIT=" + std::to_string(L.limit));
+  if (bytes <= L.arena_bytes) return L.arena;
+  FASTMM_HIP(hipStreamSynchronize(L.stream));
+  size_t free_b = 0, total_b = 0;
+  FASTMM_HIP(hipMemGetInfo(&free_b, &total_b));
+  if (bytes > free_b + L.arena_bytes)
+    throw Error(kOutOfMemory, "workspace of " + std::to_string(bytes) + " bytes exceeds free device memory (" +
+                                  std::to_string(free_b + L.arena_bytes) + ")");
+  if (L.arena) {
+    FASTMM_HIP(hipFree(L.arena));
+    L.arena = nullptr;
+    L.arena_bytes = 0;
+  }
+  // Grow geometrically to avoid reallocating on every slightly larger call.
+  size_t want = std::max(bytes, std::min(bytes + bytes / 4, free_b));
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    want = bytes;
+    FASTMM_HIP(hipMalloc(&p, want));
+  }
+  L.arena = static_cast<char*>(p);
+  L.arena_bytes = want;
+  if (poison && poison[0] == '1') FASTMM_HIP(hipMemsetAsync(L.arena, 0xFF, L.arena_bytes, L.stream));
+  return L.arena;
+}
+
+char* ensure_pinned(Library& L, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 4096);
+  if (bytes <= L.pinned_bytes) return L.pinned;
+  FASTMM_HIP(hipStreamSynchronize(L.stream));
+  if (L.pinned) FASTMM_HIP(hipHostFree(L.pinned));
+  L.pinned = nullptr;
+  L.pinned_bytes = 0;
+  void* p = nullptr;
+  FASTMM_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+  L.pinned = static_cast<char*>(p);
+  L.pinned_bytes = bytes;
+  return L.pinned;
+}
+
+int effective_depth(int64_t M, int64_t N, int64_t K, int depth, int64_t leaf) {
+  int d = 0;
+  int64_t m = M, k = K, n = N;
+  while (splits(m, k, n, depth - d, leaf)) {
+    m = half_up(m);
+    k = half_up(k);
+    n = half_up(n);
+    ++d;
+  }
+  return d;
+}
+
+namespace {
+
+std::vector<Dims> level_dims(const Problem& p) {
+  std::vector<Dims> dims{{p.M, p.K, p.N}};
+  for (int l = 0; l < p.depth; ++l) {
+    const Dims& d = dims.back();
+    dims.push_back({half_up(d.m), half_up(d.k), half_up(d.n)});
+  }
+  return dims;
+}
+
+int64_t pow7(int l) {
+  int64_t r = 1;
+  for (int i = 0; i < l; ++i) r *= 7;
+  return r;
+}
+
+}  // namespace
+
+size_t problem_temp_bytes(const Problem& p) {
+  const auto dims = level_dims(p);
+  size_t floats = 0;
+  for (int l = 0; l < p.depth; ++l) {
+    const Dims& c = dims[l + 1];
+    floats += align_up((size_t)pow7(l) * 4 * c.m * c.k, kAlignFloats);
+    floats += align_up((size_t)pow7(l) * 4 * c.k * c.n, kAlignFloats);
+  }
+  for (int l = 1; l <= p.depth; ++l)
+    floats += align_up((size_t)pow7(l) * dims[l].m * dims[l].n, kAlignFloats);
+  return floats * sizeof(float);
+}
+
+void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
+  s = Schedule();
+  int maxd = 0;
+  for (const auto& p : probs) maxd = std::max(maxd, p.depth);
+  s.max_depth = maxd;
+  s.preA.resize(maxd);
+  s.preB.resize(maxd);
+  s.post.resize(maxd);
+  float* base = reinterpret_cast<float*>(ws);
+  size_t off = 0;  // floats
+  auto carve = [&](size_t nfloats) {
+    float* p = base + off;
+    off += align_up(nfloats, kAlignFloats);
+    return p;
+  };
+
+  for (const auto& p : probs) {
+    const auto dims = level_dims(p);
+    const int d = p.depth;
+    std::vector<View> Av{{p.A, p.lda, p.M, p.K}}, Bv{{p.B, p.ldb, p.K, p.N}};
+    // Pre-additions, level by level; the next level's operands are views
+    // of this level's operands or of the new S / T blocks.
+    for (int l = 0; l < d; ++l) {
+      const Dims c = dims[l + 1];
+      const int64_t nodes = pow7(l);
+      float* S = carve((size_t)nodes * 4 * c.m * c.k);
+      float* T = carve((size_t)nodes * 4 * c.k * c.n);
+      std::vector<View> nA(7 * nodes), nB(7 * nodes);
+      const int64_t sa = c.m * c.k, tb = c.k * c.n;
+      for (int64_t x = 0; x < nodes; ++x) {
+        const View& a = Av[x];
+        const View& b = Bv[x];
+        PreAddNode na{a.p, S + x * 4 * sa, a.ld, (int32_t)a.vrows, (int32_t)a.vcols,
+                      (int32_t)c.m, (int32_t)c.k, 0, 0};
+        PreAddNode nb{b.p, T + x * 4 * tb, b.ld, (int32_t)b.vrows, (int32_t)b.vcols,
+                      (int32_t)c.k, (int32_t)c.n, 0, 0};
+        s.preA[l].push_back(na);
+        s.preB[l].push_back(nb);
+        const View a11 = quadrant(a, 0, 0, c.m, c.k), a12 = quadrant(a, 0, 1, c.m, c.k),
+                   a22 = quadrant(a, 1, 1, c.m, c.k);
+        const View b11 = quadrant(b, 0, 0, c.k, c.n), b21 = quadrant(b, 1, 0, c.k, c.n),
+                   b22 = quadrant(b, 1, 1, c.k, c.n);
+        auto sv = [&](int i) { return View{S + (x * 4 + i) * sa, c.k, c.m, c.k}; };
+        auto tv = [&](int i) { return View{T + (x * 4 + i) * tb, c.n, c.k, c.n}; };
+        // P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4,
+        // P5 = S1 T1,   P6 = S2 T2,   P7 = S3 T3
+        const View ca[7] = {a11, a12, sv(3), a22, sv(0), sv(1), sv(2)};
+        const View cb[7] = {b11, b21, b22, tv(3), tv(0), tv(1), tv(2)};
+        for (int i = 0; i < 7; ++i) {
+          nA[7 * x + i] = ca[i];
+          nB[7 * x + i] = cb[i];
+        }
+      }
+      Av.swap(nA);
+      Bv.swap(nB);
+      s.add_bytes += (double)nodes * (32.0 * c.m * c.k + 32.0 * c.k * c.n);
+    }
+    // Product buffers P[l] (l = 1..d), 7^l blocks of m_l x n_l.
+    std::vector<float*> P(d + 1, nullptr);
+    for (int l = 1; l <= d; ++l) P[l] = carve((size_t)pow7(l) * dims[l].m * dims[l].n);
+    // Leaves.
+    const Dims lf = dims[d];
+    const int64_t nleaves = pow7(d);
+    const TileShape ts = tile_shape(p.tile);
+    for (int64_t x = 0; x < nleaves; ++x) {
+      GemmDesc g{};
+      g.A = Av[x].p;
+      g.lda = Av[x].ld;
+      g.B = Bv[x].p;
+      g.ldb = Bv[x].ld;
+      g.a_rows = (int32_t)Av[x].vrows;
+      g.b_cols = (int32_t)Bv[x].vcols;
+      g.kmax = (int32_t)std::min(Av[x].vcols, Bv[x].vrows);
+      if (d == 0) {
+        g.C = p.C;
+        g.ldc = p.ldc;
+        g.c_rows = (int32_t)p.M;
+        g.c_cols = (int32_t)p.N;
+      } else {
+        g.C = P[d] + x * lf.m * lf.n;
+        g.ldc = lf.n;
+        g.c_rows = (int32_t)lf.m;
+        g.c_cols = (int32_t)lf.n;
+      }
+      g.tiles_n = (g.c_cols + ts.bn - 1) / ts.bn;
+      s.leaf[p.tile].push_back(g);
+    }
+    s.leaves += nleaves;
+    s.leaf_flops += (double)nleaves * 2.0 * lf.m * lf.n * lf.k;
+    s.leaf_dims = lf;
+    // Post-additions, deepest level first.
+    for (int l = d - 1; l >= 0; --l) {
+      const Dims c = dims[l + 1];
+      const int64_t nodes = pow7(l);
+      for (int64_t x = 0; x < nodes; ++x) {
+        PostAddNode pn{};
+        pn.P = P[l + 1] + x * 7 * c.m * c.n;
+        if (l == 0) {
+          pn.dst = p.C;
+          pn.ld = p.ldc;
+          pn.rows = (int32_t)p.M;
+          pn.cols = (int32_t)p.N;
+        } else {
+          pn.dst = P[l] + x * dims[l].m * dims[l].n;
+          pn.ld = dims[l].n;
+          pn.rows = (int32_t)dims[l].m;
+          pn.cols = (int32_t)dims[l].n;
+        }
+        pn.h_r = (int32_t)c.m;
+        pn.h_c = (int32_t)c.n;
+        s.post[l].push_back(pn);
+      }
+      s.add_bytes += (double)nodes * 44.0 * c.m * c.n;
+    }
+  }
+  s.temp_bytes = off * sizeof(float);
+
+  // Block / tile prefixes and the vector-path flags of every launch.
+  s.vec_preA.assign(maxd, 1);
+  s.vec_preB.assign(maxd, 1);
+  s.vec_post.assign(maxd, 1);
+  auto fix_pre = [](std::vector<PreAddNode>& v, char& vec) {
+    int64_t b = 0;
+    for (auto& n : v) {
+      n.block_begin = (int32_t)b;
+      b += add_blocks_for(n.h_r, n.h_c);
+      if (!(aligned16(n.src) && aligned16(n.dst) && n.ld % 4 == 0 && n.h_c % 4 == 0)) vec = 0;
+    }
+    if (b > INT32_MAX) throw Error(kNotSupported, "pre-addition launch too large");
+    return (int)b;
+  };
+  for (int l = 0; l < maxd; ++l) {
+    fix_pre(s.preA[l], s.vec_preA[l]);
+    fix_pre(s.preB[l], s.vec_preB[l]);
+    int64_t b = 0;
+    for (auto& n : s.post[l]) {
+      n.block_begin = (int32_t)b;
+      b += add_blocks_for(n.h_r, n.h_c);
+      if (!(aligned16(n.P) && aligned16(n.dst) && n.ld % 4 == 0 && n.h_c % 4 == 0))
+        s.vec_post[l] = 0;
+    }
+    if (b > INT32_MAX) throw Error(kNotSupported, "post-addition launch too large");
+  }
+  s.leaf_tiles_total.assign(kNumTiles, 0);
+  for (int t = 0; t < kNumTiles; ++t) {
+    const TileShape ts = tile_shape(t);
+    int64_t total = 0;
+    for (auto& g : s.leaf[t]) {
+      g.tile_begin = (int32_t)total;
+      total += (int64_t)((g.c_rows + ts.bm - 1) / ts.bm) * g.tiles_n;
+      if (!(aligned16(g.A) && aligned16(g.B) && g.lda % 4 == 0 && g.ldb % 4 == 0))
+        s.vec_leaf[t] = false;
+    }
+    if (total > INT32_MAX) throw Error(kNotSupported, "leaf launch too large");
+    s.leaf_tiles_total[t] = (int)total;
+  }
+}
+
+size_t schedule_desc_bytes(const Schedule& s) {
+  size_t b = 0;
+  for (int l = 0; l < s.max_depth; ++l) {
+    b += align_up(s.preA[l].size() * sizeof(PreAddNode), 256);
+    b += align_up(s.preB[l].size() * sizeof(PreAddNode), 256);
+    b += align_up(s.post[l].size() * sizeof(PostAddNode), 256);
+  }
+  for (int t = 0; t < kNumTiles; ++t) b += align_up(s.leaf[t].size() * sizeof(GemmDesc), 256);
+  return b;
+}
+
+namespace {
+int add_total_blocks(const std::vector<PreAddNode>& v) {
+  if (v.empty()) return 0;
+  return v.back().block_begin + (int)add_blocks_for(v.back().h_r, v.back().h_c);
+}
+int add_total_blocks(const std::vector<PostAddNode>& v) {
+  if (v.empty()) return 0;
+  return v.back().block_begin + (int)add_blocks_for(v.back().h_r, v.back().h_c);
+}
+}  // namespace
+
+int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host) {
+  // Pack every descriptor array into one host block, upload it once.
+  size_t off = 0;
+  auto put = [&](const void* src, size_t bytes) {
+    std::memcpy(desc_host + off, src, bytes);
+    char* dev = desc_dev + off;
+    off += align_up(bytes, 256);
+    return dev;
+  };
+  std::vector<const PreAddNode*> dA(s.max_depth), dB(s.max_depth);
+  std::vector<const PostAddNode*> dP(s.max_depth);
+  const GemmDesc* dL[kNumTiles] = {};
+  for (int l = 0; l < s.max_depth; ++l) {
+    dA[l] = reinterpret_cast<const PreAddNode*>(put(s.preA[l].data(), s.preA[l].size() * sizeof(PreAddNode)));
+    dB[l] = reinterpret_cast<const PreAddNode*>(put(s.preB[l].data(), s.preB[l].size() * sizeof(PreAddNode)));
+    dP[l] = reinterpret_cast<const PostAddNode*>(put(s.post[l].data(), s.post[l].size() * sizeof(PostAddNode)));
+  }
+  for (int t = 0; t < kNumTiles; ++t)
+    dL[t] = reinterpret_cast<const GemmDesc*>(put(s.leaf[t].data(), s.leaf[t].size() * sizeof(GemmDesc)));
+  if (off) FASTMM_HIP(hipMemcpyAsync(desc_dev, desc_host, off, hipMemcpyHostToDevice, L.stream));
+
+  int launches = 0;
+  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[1], L.stream));
+  for (int l = 0; l < s.max_depth; ++l) {
+    const int ba = add_total_blocks(s.preA[l]);
+    const int bb = add_total_blocks(s.preB[l]);
+    if (ba) { launch_preadd(0, dA[l], (int)s.preA[l].size(), ba, s.vec_preA[l], L.stream); ++launches; }
+    if (bb) { launch_preadd(1, dB[l], (int)s.preB[l].size(), bb, s.vec_preB[l], L.stream); ++launches; }
+  }
+  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[2], L.stream));
+  for (int t = 0; t < kNumTiles; ++t) {
+    if (s.leaf_tiles_total[t] > 0) {
+      launch_leaf_gemm(t, dL[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t], L.stream);
+      ++launches;
+    }
+  }
+  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[3], L.stream));
+  for (int l = s.max_depth - 1; l >= 0; --l) {
+    const int bp = add_total_blocks(s.post[l]);
+    if (bp) { launch_postadd(dP[l], (int)s.post[l].size(), bp, s.vec_post[l], L.stream); ++launches; }
+  }
+  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[4], L.stream));
+  s.launches = launches;
+  return launches;
+}
+
+// ---------------------------------------------------------------------------
+// Argument checks shared by the single and batched paths.
+
+namespace {
+
+enum Residency { kHost = 0, kDevice = 1 };
+
+Residency classify(const void* p) {
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof(attr));
+  hipError_t e = hipPointerGetAttributes(&attr, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return kHost;  // unknown to HIP: pageable host memory
+  }
+  if (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged) return kDevice;
+  return kHost;
+}
+
+struct Range {
+  uintptr_t lo, hi;
+};
+
+Range span(const void* p, int64_t rows, int64_t cols, int64_t ld) {
+  if (rows <= 0 || cols <= 0 || p == nullptr) return {0, 0};
+  const uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+  return {lo, lo + (uintptr_t)(((rows - 1) * ld + cols) * (int64_t)sizeof(float))};
+}
+
+bool overlaps(Range a, Range b) { return a.lo < a.hi && b.lo < b.hi && a.lo < b.hi && b.lo < a.hi; }
+
+}  // namespace
+
+void validate_gemm_args(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                        const float* B, int64_t ldb, const float* C, int64_t ldc, int depth) {
+  if (M < 0 || N < 0 || K < 0) throw Error(kInvalidValue, "negative dimension");
+  if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
+    throw Error(kNotSupported, "dimension above 2^31-1");
+  if (lda < std::max<int64_t>(1, K)) throw Error(kInvalidValue, "lda < max(1, K)");
+  if (ldb < std::max<int64_t>(1, N)) throw Error(kInvalidValue, "ldb < max(1, N)");
+  if (ldc < std::max<int64_t>(1, N)) throw Error(kInvalidValue, "ldc < max(1, N)");
+  if (depth > 16) throw Error(kInvalidValue, "depth > 16");
+  if (M > 0 && N > 0 && C == nullptr) throw Error(kInvalidValue, "C is NULL");
+  if (M > 0 && K > 0 && A == nullptr) throw Error(kInvalidValue, "A is NULL");
+  if (K > 0 && N > 0 && B == nullptr) throw Error(kInvalidValue, "B is NULL");
+  const Range rc = span(C, M, N, ldc);
+  if (overlaps(rc, span(A, M, K, lda)) || overlaps(rc, span(B, K, N, ldb)))
+    throw Error(kInvalidValue, "C overlaps A or B");
+}
+
+// Residency of a product's operands: true = device.  Mixed -> error.
+bool operands_on_device(int64_t M, int64_t N, int64_t K, const float* A, const float* B,
+                        const float* C) {
+  int dev = 0, host = 0;
+  auto see = [&](const void* p, bool used) {
+    if (!used) return;
+    if (classify(p) == kDevice) ++dev; else ++host;
+  };
+  see(C, M > 0 && N > 0);
+  see(A, M > 0 && K > 0);
+  see(B, K > 0 && N > 0);
+  if (dev && host)
+    throw Error(kNotSupported, "A, B and C must be all device memory or all host memory");
+  return dev > 0;
+}
+
+namespace {
+
+double ev_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return -1.0;
+  }
+  return ms;
+}
+
+void do_gemm(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+             const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
+             int tile) {
+  validate_gemm_args(M, N, K, A, lda, B, ldb, C, ldc, depth);
+  if (tile >= kNumTiles) throw Error(kInvalidValue, "unknown tile id");
+  ensure_init(L);
+  fastmm_stats_t st{};
+  st.h2d_ms = st.preadd_ms = st.leaf_ms = st.postadd_ms = st.d2h_ms = st.total_ms = -1.0;
+  if (M == 0 || N == 0) {
+    L.stats = st;
+    return;
+  }
+  const bool on_dev = operands_on_device(M, N, K, A, B, C);
+
+  if (depth < 0 || tile < 0) {
+    fastmm_plan_t pl{};
+    int rc = plan_choose(L, M, N, K, L.plan_mode, &pl);
+    if (rc != kSuccess) throw Error(rc, "planner failed");
+    if (depth < 0) {
+      depth = pl.depth;
+      leaf = pl.leaf;
+    }
+    if (tile < 0) tile = pl.tile;
+  }
+
+  Problem p;
+  p.M = M;
+  p.N = N;
+  p.K = K;
+  p.depth = (K == 0) ? 0 : effective_depth(M, N, K, depth, leaf);
+  p.tile = tile;
+
+  // Workspace: [staged A | staged B | staged C | temporaries | descriptors].
+  const size_t a_bytes = on_dev ? 0 : align_up((size_t)M * K * 4, 256);
+  const size_t b_bytes = on_dev ? 0 : align_up((size_t)K * N * 4, 256);
+  const size_t c_bytes = on_dev ? 0 : align_up((size_t)M * N * 4, 256);
+  const size_t t_bytes = align_up(problem_temp_bytes(p), 256);
+
+  // Schedule with temporaries at a placeholder base to size the descriptors.
+  Schedule s;
+  {
+    Problem q = p;
+    q.A = reinterpret_cast<const float*>(256);
+    q.B = q.A;
+    q.C = const_cast<float*>(q.A);
+    q.lda = on_dev ? lda : K;
+    q.ldb = on_dev ? ldb : N;
+    q.ldc = on_dev ? ldc : N;
+    build_schedule({q}, reinterpret_cast<char*>(256), s);
+  }
+  const size_t d_bytes = align_up(schedule_desc_bytes(s), 256) + 256;
+  char* ws = ensure_arena(L, a_bytes + b_bytes + c_bytes + t_bytes + d_bytes);
+  char* desc_host = ensure_pinned(L, d_bytes);
+
+  float* dA = on_dev ? const_cast<float*>(A) : reinterpret_cast<float*>(ws);
+  float* dB = on_dev ? const_cast<float*>(B) : reinterpret_cast<float*>(ws + a_bytes);
+  float* dC = on_dev ? C : reinterpret_cast<float*>(ws + a_bytes + b_bytes);
+  p.A = dA;
+  p.B = dB;
+  p.C = dC;
+  p.lda = on_dev ? lda : K;
+  p.ldb = on_dev ? ldb : N;
+  p.ldc = on_dev ? ldc : N;
+  char* temps = ws + a_bytes + b_bytes + c_bytes;
+  char* desc_dev = temps + t_bytes;
+
+  hipStream_t sm = L.stream;
+  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[0], sm));
+  if (!on_dev) {
+    // Step (1) of the paper's leaf call: operands to the device.
+    if (K > 0) {
+      FASTMM_HIP(hipMemcpy2DAsync(dA, K * 4, A, lda * 4, K * 4, M, hipMemcpyHostToDevice, sm));
+      FASTMM_HIP(hipMemcpy2DAsync(dB, N * 4, B, ldb * 4, N * 4, K, hipMemcpyHostToDevice, sm));
+    }
+  }
+  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[5], sm));
+  int launches = 0;
+  if (K == 0) {
+    FASTMM_HIP(hipMemset2DAsync(dC, p.ldc * 4, 0, N * 4, M, sm));
+  } else {
+    build_schedule({p}, temps, s);
+    launches = enqueue_schedule(L, s, desc_dev, desc_host);
+  }
+  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[6], sm));
+  if (!on_dev) {
+    // Step (3): the result back to the host.
+    FASTMM_HIP(hipMemcpy2DAsync(C, ldc * 4, dC, N * 4, N * 4, M, hipMemcpyDeviceToHost, sm));
+  }
+  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[7], sm));
+  FASTMM_HIP(hipStreamSynchronize(sm));
+
+  st.depth = p.depth;
+  st.tile = tile;
+  st.leaves = s.leaves;
+  st.leaf_m = s.leaf_dims.m;
+  st.leaf_k = s.leaf_dims.k;
+  st.leaf_n = s.leaf_dims.n;
+  st.leaf_flops = s.leaf_flops;
+  st.add_bytes = s.add_bytes;
+  st.transfer_bytes = on_dev ? 0.0 : 4.0 * ((double)M * K + (double)K * N + (double)M * N);
+  st.launches = launches;
+  st.workspace_bytes = L.arena_bytes;
+  if (L.profiling && K > 0) {
+    st.h2d_ms = ev_ms(L.ev[0], L.ev[5]);
+    st.preadd_ms = ev_ms(L.ev[1], L.ev[2]);
+    st.leaf_ms = ev_ms(L.ev[2], L.ev[3]);
+    st.postadd_ms = ev_ms(L.ev[3], L.ev[4]);
+    st.d2h_ms = ev_ms(L.ev[6], L.ev[7]);
+    st.total_ms = ev_ms(L.ev[0], L.ev[7]);
+  }
+  L.stats = st;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    t_last_error.clear();
+    f();
+    return kSuccess;
+  } catch (const Error& e) {
+    t_last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    t_last_error = "host allocation failed";
+    return kOutOfMemory;
+  } catch (const std::exception& e) {
+    t_last_error = e.what();
+    return kDeviceError;
+  } catch (...) {
+    t_last_error = "unknown error";
+    return kDeviceError;
+  }
+}
+
+}  // namespace
+
+int run_guarded(const std::function<void()>& f) { return guarded(f); }
+
+}  // namespace fastmm
+
+using namespace fastmm;
+
+extern "C" {
+
+int fastmm_gemm_ex(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                   int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf, int tile) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  return guarded([&] { do_gemm(L, M, N, K, A, lda, B, ldb, C, ldc, depth, leaf, tile); });
+}
+
+int fastmm_gemm(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf) {
+  const int tile = depth < 0 ? -1 : kTile128x128;
+  return fastmm_gemm_ex(M, N, K, A, lda, B, ldb, C, ldc, depth, leaf, tile);
+}
+
+int fastmm_set_stream(void* hip_stream) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  return guarded([&] {
+    ensure_init(L);
+    FASTMM_HIP(hipStreamSynchronize(L.stream));
+    L.stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : L.own_stream;
+  });
+}
+
+int fastmm_set_profiling(int on) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  L.profiling = (on != 0);
+  return kSuccess;
+}
+
+int fastmm_get_stats(fastmm_stats_t* out) {
+  if (!out) {
+    t_last_error = "out is NULL";
+    return kInvalidValue;
+  }
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  *out = L.stats;
+  return kSuccess;
+}
+
+const char* fastmm_get_last_error(void) { return t_last_error.c_str(); }
+
+int fastmm_preadd(int side, int64_t rows, int64_t cols, const float* X, int64_t ldx, float* out) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  return guarded([&] {
+    if (side != 0 && side != 1) throw Error(kInvalidValue, "side must be 0 (A) or 1 (B)");
+    if (rows < 0 || cols < 0 || rows > INT32_MAX || cols > INT32_MAX)
+      throw Error(kInvalidValue, "bad extent");
+    if (ldx < std::max<int64_t>(1, cols)) throw Error(kInvalidValue, "ldx < max(1, cols)");
+    if (rows == 0 || cols == 0) return;
+    if (!X || !out) throw Error(kInvalidValue, "NULL pointer");
+    ensure_init(L);
+    if (classify(X) != kDevice || classify(out) != kDevice)
+      throw Error(kNotSupported, "fastmm_preadd takes device pointers");
+    PreAddNode n{X, out, ldx, (int32_t)rows, (int32_t)cols, (int32_t)half_up(rows),
+                 (int32_t)half_up(cols), 0, 0};
+    const bool vec = aligned16(X) && aligned16(out) && ldx % 4 == 0 && n.h_c % 4 == 0;
+    char* dev = ensure_arena(L, 256);
+    char* host = ensure_pinned(L, sizeof(n));
+    std::memcpy(host, &n, sizeof(n));
+    FASTMM_HIP(hipMemcpyAsync(dev, host, sizeof(n), hipMemcpyHostToDevice, L.stream));
+    launch_preadd(side, reinterpret_cast<const PreAddNode*>(dev), 1,
+                  (int)add_blocks_for(n.h_r, n.h_c), vec, L.stream);
+    FASTMM_HIP(hipStreamSynchronize(L.stream));
+  });
+}
+
+int fastmm_postadd(int64_t h_r, int64_t h_c, const float* P, float* C, int64_t ldc, int64_t rows,
+                   int64_t cols) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  return guarded([&] {
+    if (h_r < 0 || h_c < 0 || h_r > INT32_MAX / 2 || h_c > INT32_MAX / 2)
+      throw Error(kInvalidValue, "bad extent");
+    if (rows < 0 || cols < 0 || rows > 2 * h_r || cols > 2 * h_c)
+      throw Error(kInvalidValue, "rows/cols must lie in [0, 2 h]");
+    if (ldc < std::max<int64_t>(1, cols)) throw Error(kInvalidValue, "ldc < max(1, cols)");
+    if (h_r == 0 || h_c == 0 || rows == 0 || cols == 0) return;
+    if (!P || !C) throw Error(kInvalidValue, "NULL pointer");
+    ensure_init(L);
+    if (classify(P) != kDevice || classify(C) != kDevice)
+      throw Error(kNotSupported, "fastmm_postadd takes device pointers");
+    PostAddNode n{P, C, ldc, (int32_t)rows, (int32_t)cols, (int32_t)h_r, (int32_t)h_c, 0, 0};
+    const bool vec = aligned16(P) && aligned16(C) && ldc % 4 == 0 && h_c % 4 == 0;
+    char* dev = ensure_arena(L, 256);
+    char* host = ensure_pinned(L, sizeof(n));
+    std::memcpy(host, &n, sizeof(n));
+    FASTMM_HIP(hipMemcpyAsync(dev, host, sizeof(n), hipMemcpyHostToDevice, L.stream));
+    launch_postadd(reinterpret_cast<const PostAddNode*>(dev), 1, (int)add_blocks_for(h_r, h_c), vec,
+                   L.stream);
+    FASTMM_HIP(hipStreamSynchronize(L.stream));
+  });
+}
+
+void fastmm_finalize(void) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  if (!L.initialised) return;
+  (void)hipStreamSynchronize(L.stream);
+  if (L.arena) (void)hipFree(L.arena);
+  if (L.pinned) (void)hipHostFree(L.pinned);
+  for (auto& e : L.ev)
+    if (e) (void)hipEventDestroy(e);
+  if (L.own_stream) (void)hipStreamDestroy(L.own_stream);
+  L.arena = nullptr;
+  L.arena_bytes = 0;
+  L.pinned = nullptr;
+  L.pinned_bytes = 0;
+  L.own_stream = nullptr;
+  L.stream = nullptr;
+  for (auto& e : L.ev) e = nullptr;
+  L.initialised = false;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// Recursion engine: turns one or many products into a level-wise schedule of
+// grouped launches (pre-additions per level, one grouped leaf launch per tile
+// shape, post-additions per level) over a single device workspace.
+#pragma once
+
+#include <functional>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fastmm.h"
+#include "common.h"
+
+namespace fastmm {
+
+// Extents (m, k, n) of the nodes of one recursion level.
+struct Dims {
+  int64_t m, k, n;
+};
+
+// Half extent of equation (1): quadrant 0 takes ceil(m/2).
+inline int64_t half_up(int64_t m) { return (m + 1) / 2; }
+
+// Stop rule: split iff levels remain and floor(min(m,k,n)/2) >= max(leaf,1).
+inline bool splits(int64_t m, int64_t k, int64_t n, int levels_left, int64_t leaf) {
+  int64_t mn = m < k ? m : k;
+  mn = mn < n ? mn : n;
+  return levels_left > 0 && mn / 2 >= (leaf > 1 ? leaf : 1);
+}
+
+int effective_depth(int64_t M, int64_t N, int64_t K, int depth, int64_t leaf);
+
+// One product as the engine sees it, operands already device-resident.
+struct Problem {
+  int64_t M = 0, N = 0, K = 0;
+  const float* A = nullptr;
+  int64_t lda = 0;
+  const float* B = nullptr;
+  int64_t ldb = 0;
+  float* C = nullptr;
+  int64_t ldc = 0;
+  int depth = 0;  // effective depth
+  int tile = 0;
+};
+
+// A level-wise schedule over a set of problems.
+struct Schedule {
+  std::vector<std::vector<PreAddNode>> preA, preB;  // per level
+  std::vector<std::vector<PostAddNode>> post;       // per level
+  std::vector<GemmDesc> leaf[kNumTiles];
+  std::vector<int> leaf_tiles_total;                // per tile id
+  std::vector<char> vec_preA, vec_preB, vec_post;   // per level
+  bool vec_leaf[kNumTiles] = {true, true, true, true};
+  int max_depth = 0;
+  size_t temp_bytes = 0;  // bytes of S, T and P temporaries
+  // statistics
+  int64_t leaves = 0;
+  double leaf_flops = 0.0;
+  double add_bytes = 0.0;
+  int launches = 0;
+  Dims leaf_dims{0, 0, 0};
+};
+
+// Bytes of temporaries a problem needs (no allocation).
+size_t problem_temp_bytes(const Problem& p);
+
+// Builds the schedule; temporaries are carved from `ws` (device), which must
+// hold at least the sum of problem_temp_bytes.
+void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s);
+
+// Library state (one per process).
+struct Library {
+  std::mutex mu;
+  bool initialised = false;
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;  // stream in use
+  char* arena = nullptr;         // device workspace
+  size_t arena_bytes = 0;
+  char* pinned = nullptr;        // host staging for descriptors
+  size_t pinned_bytes = 0;
+  bool profiling = false;
+  hipEvent_t ev[8] = {};
+  fastmm_stats_t stats{};
+  size_t limit = 0;              // workspace cap (0: none)
+  int plan_mode = FASTMM_PLAN_DEFAULT;
+};
+
+Library& lib();
+void ensure_init(Library& L);
+char* ensure_arena(Library& L, size_t bytes);
+char* ensure_pinned(Library& L, size_t bytes);
+
+// Uploads every descriptor array of `s` (one copy) and enqueues all launches
+// on L.stream.  Returns the number of launches.  Events ev[1..4] bracket
+// pre-additions, leaves and post-additions when profiling is on.
+int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host);
+size_t schedule_desc_bytes(const Schedule& s);
+
+// Planner hooks (planner.cpp).
+int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out);
+int64_t default_leaf();
+
+void set_error(const std::string& msg);
+
+// Runs f, turning exceptions into a status code and the thread's last error.
+int run_guarded(const std::function<void()>& f);
+
+// Argument checks (throw Error before anything is written).
+void validate_gemm_args(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                        const float* B, int64_t ldb, const float* C, int64_t ldc, int depth);
+// true: all used operands are device memory; false: all host; mixed: throws.
+bool operands_on_device(int64_t M, int64_t N, int64_t K, const float* A, const float* B,
+                        const float* C);
+
+}  // namespace fastmm

@@ -1,0 +1,174 @@
+// Fused quadrant additions of Winograd's variant of Strassen's recursion.
+//
+// The paper leaves the fast recursion with GPU leaves as future work
+// (Section 4.3, closing remarks) and never prints the schedule; the one used
+// here is Winograd's standard 7-product form with 8 pre-additions and 7
+// post-additions per level:
+//   S1 = A21 + A22, S2 = S1 - A11, S3 = A11 - A21, S4 = A12 - S2
+//   T1 = B12 - B11, T2 = B22 - T1, T3 = B22 - B12, T4 = T2 - B21
+//   C11 = P1 + P2,  U2 = P1 + P6,  U3 = U2 + P7,   U4 = U2 + P5
+//   C12 = U4 + P3,  C21 = U3 - P4, C22 = U3 + P5
+// Each output element is one fixed chain of FP32 operations in exactly this
+// order (no fused multiply-add can form: there are no products), so results
+// are reproducible bit for bit against any IEEE FP32 evaluation of the chain.
+//
+// The kernels are HBM-bound streams: every launch covers all nodes of one
+// recursion level, every input quadrant is read once and every output written
+// once, four consecutive floats per thread (16-byte accesses, consecutive
+// threads on consecutive addresses).  Quadrants use the split of equation (1)
+// with virtual zero padding: reads outside a parent's valid extent give 0.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace fastmm {
+
+constexpr int kAddThreads = kAddThreadsPerBlock;
+constexpr int kItems = kAddChunk / kAddThreads;  // float4 groups per thread
+
+__device__ __forceinline__ float4 load4(const float* p, bool vec, bool rv, int c, int vcols) {
+  float4 v;
+  if (vec && rv && c + 3 < vcols) {
+    v = *reinterpret_cast<const float4*>(p);
+  } else {
+    v.x = (rv && c + 0 < vcols) ? p[0] : 0.f;
+    v.y = (rv && c + 1 < vcols) ? p[1] : 0.f;
+    v.z = (rv && c + 2 < vcols) ? p[2] : 0.f;
+    v.w = (rv && c + 3 < vcols) ? p[3] : 0.f;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void store4(float* p, float4 v, bool vec, bool rv, int c, int cols) {
+  if (!rv) return;
+  if (vec && c + 3 < cols) {
+    *reinterpret_cast<float4*>(p) = v;
+  } else {
+    if (c + 0 < cols) p[0] = v.x;
+    if (c + 1 < cols) p[1] = v.y;
+    if (c + 2 < cols) p[2] = v.z;
+    if (c + 3 < cols) p[3] = v.w;
+  }
+}
+
+// Node owning workgroup b (block_begin ascending; one search per workgroup).
+template <typename Node>
+__device__ __forceinline__ int find_node(const Node* __restrict__ nodes, int nnodes, int b) {
+  int lo = 0, hi = nnodes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (nodes[mid].block_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// side 0: A operand -> S1..S4.  side 1: B operand -> T1..T4.
+template <int SIDE, bool VEC>
+__global__ void __launch_bounds__(kAddThreads)
+preadd_kernel(const PreAddNode* __restrict__ nodes, int nnodes) {
+  const PreAddNode nd = nodes[find_node(nodes, nnodes, blockIdx.x)];
+  const int h_r = nd.h_r, h_c = nd.h_c;
+  const int c4n = (h_c + 3) >> 2;
+  const int64_t groups = (int64_t)h_r * c4n;
+  const int64_t q_elems = (int64_t)h_r * h_c;
+  const int64_t g0 = (int64_t)(blockIdx.x - nd.block_begin) * kAddChunk;
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int64_t gidx = g0 + it * kAddThreads + threadIdx.x;
+    if (gidx >= groups) break;
+    const int r = (int)(gidx / c4n);
+    const int c = (int)(gidx - (int64_t)r * c4n) * 4;
+    const float* top = nd.src + (int64_t)r * nd.ld;
+    const float* bot = nd.src + (int64_t)(r + h_r) * nd.ld;
+    const bool rt = r < nd.vrows;
+    const bool rb = (r + h_r) < nd.vrows;
+    const float4 x11 = load4(top + c, VEC, rt, c, nd.vcols);
+    const float4 x12 = load4(top + h_c + c, VEC, rt, c + h_c, nd.vcols);
+    const float4 x21 = load4(bot + c, VEC, rb, c, nd.vcols);
+    const float4 x22 = load4(bot + h_c + c, VEC, rb, c + h_c, nd.vcols);
+    float4 o1, o2, o3, o4;
+    if (SIDE == 0) {
+      // S1 = A21 + A22; S2 = S1 - A11; S3 = A11 - A21; S4 = A12 - S2
+      o1.x = x21.x + x22.x; o1.y = x21.y + x22.y; o1.z = x21.z + x22.z; o1.w = x21.w + x22.w;
+      o2.x = o1.x - x11.x;  o2.y = o1.y - x11.y;  o2.z = o1.z - x11.z;  o2.w = o1.w - x11.w;
+      o3.x = x11.x - x21.x; o3.y = x11.y - x21.y; o3.z = x11.z - x21.z; o3.w = x11.w - x21.w;
+      o4.x = x12.x - o2.x;  o4.y = x12.y - o2.y;  o4.z = x12.z - o2.z;  o4.w = x12.w - o2.w;
+    } else {
+      // T1 = B12 - B11; T2 = B22 - T1; T3 = B22 - B12; T4 = T2 - B21
+      o1.x = x12.x - x11.x; o1.y = x12.y - x11.y; o1.z = x12.z - x11.z; o1.w = x12.w - x11.w;
+      o2.x = x22.x - o1.x;  o2.y = x22.y - o1.y;  o2.z = x22.z - o1.z;  o2.w = x22.w - o1.w;
+      o3.x = x22.x - x12.x; o3.y = x22.y - x12.y; o3.z = x22.z - x12.z; o3.w = x22.w - x12.w;
+      o4.x = o2.x - x21.x;  o4.y = o2.y - x21.y;  o4.z = o2.z - x21.z;  o4.w = o2.w - x21.w;
+    }
+    float* out = nd.dst + (int64_t)r * h_c + c;
+    store4(out, o1, VEC, true, c, h_c);
+    store4(out + q_elems, o2, VEC, true, c, h_c);
+    store4(out + 2 * q_elems, o3, VEC, true, c, h_c);
+    store4(out + 3 * q_elems, o4, VEC, true, c, h_c);
+  }
+}
+
+template <bool VEC>
+__global__ void __launch_bounds__(kAddThreads)
+postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
+  const PostAddNode nd = nodes[find_node(nodes, nnodes, blockIdx.x)];
+  const int h_r = nd.h_r, h_c = nd.h_c;
+  const int c4n = (h_c + 3) >> 2;
+  const int64_t groups = (int64_t)h_r * c4n;
+  const int64_t q_elems = (int64_t)h_r * h_c;
+  const int64_t g0 = (int64_t)(blockIdx.x - nd.block_begin) * kAddChunk;
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int64_t gidx = g0 + it * kAddThreads + threadIdx.x;
+    if (gidx >= groups) break;
+    const int r = (int)(gidx / c4n);
+    const int c = (int)(gidx - (int64_t)r * c4n) * 4;
+    const float* p = nd.P + (int64_t)r * h_c + c;
+    float4 P[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) P[i] = load4(p + i * q_elems, VEC, true, c, h_c);
+    float4 c11, c12, c21, c22, u2, u3, u4;
+    // C11 = P1 + P2; U2 = P1 + P6; U3 = U2 + P7; U4 = U2 + P5
+    // C12 = U4 + P3; C21 = U3 - P4; C22 = U3 + P5
+    c11.x = P[0].x + P[1].x; c11.y = P[0].y + P[1].y; c11.z = P[0].z + P[1].z; c11.w = P[0].w + P[1].w;
+    u2.x = P[0].x + P[5].x;  u2.y = P[0].y + P[5].y;  u2.z = P[0].z + P[5].z;  u2.w = P[0].w + P[5].w;
+    u3.x = u2.x + P[6].x;    u3.y = u2.y + P[6].y;    u3.z = u2.z + P[6].z;    u3.w = u2.w + P[6].w;
+    u4.x = u2.x + P[4].x;    u4.y = u2.y + P[4].y;    u4.z = u2.z + P[4].z;    u4.w = u2.w + P[4].w;
+    c12.x = u4.x + P[2].x;   c12.y = u4.y + P[2].y;   c12.z = u4.z + P[2].z;   c12.w = u4.w + P[2].w;
+    c21.x = u3.x - P[3].x;   c21.y = u3.y - P[3].y;   c21.z = u3.z - P[3].z;   c21.w = u3.w - P[3].w;
+    c22.x = u3.x + P[4].x;   c22.y = u3.y + P[4].y;   c22.z = u3.z + P[4].z;   c22.w = u3.w + P[4].w;
+    float* top = nd.dst + (int64_t)r * nd.ld;
+    float* bot = nd.dst + (int64_t)(r + h_r) * nd.ld;
+    const bool rt = r < nd.rows;
+    const bool rb = (r + h_r) < nd.rows;
+    store4(top + c, c11, VEC, rt, c, nd.cols);
+    store4(top + h_c + c, c12, VEC, rt, c + h_c, nd.cols);
+    store4(bot + c, c21, VEC, rb, c, nd.cols);
+    store4(bot + h_c + c, c22, VEC, rb, c + h_c, nd.cols);
+  }
+}
+
+void launch_preadd(int side, const PreAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
+                   hipStream_t stream) {
+  if (nnodes <= 0 || total_blocks <= 0) return;
+  dim3 grid(total_blocks), block(kAddThreads);
+  if (side == 0) {
+    if (vec) hipLaunchKernelGGL((preadd_kernel<0, true>), grid, block, 0, stream, d_nodes, nnodes);
+    else hipLaunchKernelGGL((preadd_kernel<0, false>), grid, block, 0, stream, d_nodes, nnodes);
+  } else {
+    if (vec) hipLaunchKernelGGL((preadd_kernel<1, true>), grid, block, 0, stream, d_nodes, nnodes);
+    else hipLaunchKernelGGL((preadd_kernel<1, false>), grid, block, 0, stream, d_nodes, nnodes);
+  }
+  FASTMM_HIP(hipGetLastError());
+}
+
+void launch_postadd(const PostAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
+                    hipStream_t stream) {
+  if (nnodes <= 0 || total_blocks <= 0) return;
+  dim3 grid(total_blocks), block(kAddThreads);
+  if (vec) hipLaunchKernelGGL((postadd_kernel<true>), grid, block, 0, stream, d_nodes, nnodes);
+  else hipLaunchKernelGGL((postadd_kernel<false>), grid, block, 0, stream, d_nodes, nnodes);
+  FASTMM_HIP(hipGetLastError());
+}
+
+}  // namespace fastmm

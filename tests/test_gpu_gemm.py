@@ -1,0 +1,213 @@
+"""End-to-end parity of fastmm_gemm (Winograd recursion + MFMA leaves)
+against the oracle, through the C ABI.
+
+Tolerances (relative Frobenius against the FP64-accumulated classic product):
+2e-6 for depth 0 at n = 512, 1e-4 for Winograd depth <= 4.  Bit-exact where
+the oracle's integer certificate shows every FP32 intermediate is an exact
+integer below 2**24."""
+import numpy as np
+import pytest
+
+import synthgen
+from oracle import checks, classic
+from oracle import winograd as W
+from tests.gpu_util import dev, empty_dev, host, ints, say, uniform
+
+pytestmark = pytest.mark.gpu
+
+TOL_WINOGRAD = 1e-4
+
+
+@pytest.mark.parametrize("n,depth,leaf", [(512, 1, 64), (512, 2, 64), (512, 3, 32), (1024, 4, 32),
+                                          (768, 2, 128)])
+def test_winograd_uniform_square(fastmm, n, depth, leaf):
+    say(f"winograd n={n} depth={depth} leaf={leaf}")
+    A = uniform(1001 + 2, n, n)
+    B = uniform(2001 + 2, n, n)
+    C = empty_dev(n, n)
+    fastmm.gemm(n, n, n, dev(A), dev(B), C, depth=depth, leaf=leaf)
+    st = fastmm.get_stats()
+    assert st["depth"] == W.effective_depth(n, n, n, depth, leaf)
+    err = checks.rel_frob(host(C), classic.gemm(A, B))
+    say(f"  depth={st['depth']} rel_frob={err:.3e}")
+    assert err <= TOL_WINOGRAD
+
+
+@pytest.mark.parametrize("m,k,n,depth", [(257, 131, 383, 2), (33, 65, 17, 3), (101, 99, 103, 4),
+                                         (200, 64, 130, 1), (97, 301, 45, 3), (3, 3, 3, 1)])
+@pytest.mark.parametrize("tile", [0, 3])
+def test_winograd_ragged_certified_exact(fastmm, m, k, n, depth, tile):
+    say(f"winograd ragged {m}x{k}x{n} depth={depth} tile={tile}")
+    A = ints(71 + m, m, k)
+    B = ints(72 + n, k, n)
+    cert = W.Certificate()
+    ref = W.winograd(A.astype(np.int64), B.astype(np.int64), depth, 1, cert)
+    assert cert.exact_in_fp32
+    assert np.array_equal(ref, classic.gemm(A.astype(np.int64), B.astype(np.int64)))
+    C = empty_dev(m, n)
+    fastmm.gemm(m, n, k, dev(A), dev(B), C, depth=depth, leaf=1, tile=tile)
+    assert fastmm.get_stats()["depth"] == W.effective_depth(m, k, n, depth, 1)
+    assert np.array_equal(host(C).astype(np.int64), ref)
+
+
+def test_winograd_all_ones_equals_k(fastmm):
+    m, k, n = 640, 576, 704
+    A = np.ones((m, k), np.float32)
+    B = np.ones((k, n), np.float32)
+    C = empty_dev(m, n)
+    fastmm.gemm(m, n, k, dev(A), dev(B), C, depth=3, leaf=32)
+    assert fastmm.get_stats()["depth"] == 3
+    assert np.all(host(C) == k)
+
+
+def test_structure_counts_match_closed_forms(fastmm):
+    M, N, K = 1536, 1024, 1280
+    A = uniform(81, M, K)
+    B = uniform(82, K, N)
+    C = empty_dev(M, N)
+    fastmm.gemm(M, N, K, dev(A), dev(B), C, depth=3, leaf=64)
+    st = fastmm.get_stats()
+    s = W.structure(M, N, K, 3, 64)
+    assert st["depth"] == s["depth"] == 3
+    assert st["leaves"] == s["leaves"] == 343
+    assert (st["leaf_m"], st["leaf_k"], st["leaf_n"]) == s["leaf_dims"]
+    assert st["leaf_flops"] == s["leaf_flops"]
+    assert st["add_bytes"] == s["add_bytes"]
+    assert st["launches"] == 3 * 3 + 1
+
+
+def test_host_pinned_and_pageable_match_device(fastmm):
+    import torch
+    n, depth, leaf = 640, 2, 64
+    A = uniform(91, n, n)
+    B = uniform(92, n, n)
+    Cd = empty_dev(n, n)
+    fastmm.gemm(n, n, n, dev(A), dev(B), Cd, depth=depth, leaf=leaf)
+    ref = host(Cd)
+    # pinned host
+    Ap = torch.from_numpy(A).pin_memory()
+    Bp = torch.from_numpy(B).pin_memory()
+    Cp = torch.empty((n, n), dtype=torch.float32).pin_memory()
+    fastmm.gemm(n, n, n, Ap, Bp, Cp, depth=depth, leaf=leaf)
+    assert np.array_equal(Cp.numpy(), ref)
+    assert fastmm.get_stats()["transfer_bytes"] == 4.0 * 3 * n * n
+    # pageable host
+    Ch = torch.zeros((n, n), dtype=torch.float32)
+    fastmm.gemm(n, n, n, torch.from_numpy(A), torch.from_numpy(B), Ch, depth=depth, leaf=leaf)
+    assert np.array_equal(Ch.numpy(), ref)
+
+
+def test_host_strided_operands(fastmm):
+    import torch
+    m, k, n = 300, 260, 280
+    Abig = uniform(93, m, k + 12)
+    Bbig = uniform(94, k, n + 4)
+    Cbig = torch.full((m, n + 8), -3.0)
+    At = torch.from_numpy(Abig)
+    Bt = torch.from_numpy(Bbig)
+    fastmm.gemm(m, n, k, At.data_ptr(), Bt.data_ptr(), Cbig.data_ptr(), depth=2, leaf=32,
+                lda=k + 12, ldb=n + 4, ldc=n + 8)
+    got = Cbig.numpy()
+    assert checks.rel_frob(got[:, :n], classic.gemm(Abig[:, :k], Bbig[:, :n])) < TOL_WINOGRAD
+    assert np.all(got[:, n:] == -3.0)
+
+
+def test_deterministic(fastmm):
+    n = 896
+    A = dev(uniform(95, n, n))
+    B = dev(uniform(96, n, n))
+    C1 = empty_dev(n, n)
+    C2 = empty_dev(n, n)
+    fastmm.gemm(n, n, n, A, B, C1, depth=3, leaf=64)
+    fastmm.gemm(n, n, n, A, B, C2, depth=3, leaf=64)
+    assert np.array_equal(host(C1), host(C2))
+
+
+def test_poisoned_workspace(fastmm, monkeypatch):
+    # Workspace filled with NaN before the call: any read of a temporary the
+    # schedule did not write would put NaN into C.
+    monkeypatch.setenv("FASTMM_POISON", "1")
+    for (m, k, n, d) in [(512, 512, 512, 3), (333, 201, 257, 3)]:
+        A = uniform(97, m, k)
+        B = uniform(98, k, n)
+        C = empty_dev(m, n)
+        fastmm.gemm(m, n, k, dev(A), dev(B), C, depth=d, leaf=16)
+        got = host(C)
+        assert np.isfinite(got).all()
+        assert checks.rel_frob(got, classic.gemm(A, B)) < TOL_WINOGRAD
+
+
+def test_empty_and_k0(fastmm):
+    import torch
+    C = torch.full((4, 5), 9.0, device="cuda")
+    A = torch.zeros((4, 1), device="cuda")
+    B = torch.zeros((1, 5), device="cuda")
+    fastmm.gemm(4, 5, 0, A.data_ptr(), B.data_ptr(), C.data_ptr(), depth=2, leaf=1,
+                lda=1, ldb=5, ldc=5)
+    assert torch.all(C == 0).item()
+    C.fill_(9.0)
+    fastmm.gemm(0, 5, 3, 0, B.data_ptr(), C.data_ptr(), depth=2, leaf=1, lda=3, ldb=5, ldc=5)
+    assert torch.all(C == 9.0).item()
+
+
+def test_invalid_arguments_leave_c_untouched(fastmm):
+    import torch
+    A = torch.ones((8, 8), device="cuda")
+    B = torch.ones((8, 8), device="cuda")
+    C = torch.full((8, 8), 5.0, device="cuda")
+    a, b, c = A.data_ptr(), B.data_ptr(), C.data_ptr()
+    cases = [
+        (-1, 8, 8, a, 8, b, 8, c, 8, 0, 1),      # negative M
+        (8, 8, 8, a, 7, b, 8, c, 8, 0, 1),       # lda < K
+        (8, 8, 8, a, 8, b, 7, c, 8, 0, 1),       # ldb < N
+        (8, 8, 8, a, 8, b, 8, c, 7, 0, 1),       # ldc < N
+        (8, 8, 8, a, 8, b, 8, c, 8, 17, 1),      # depth > 16
+        (8, 8, 8, 0, 8, b, 8, c, 8, 0, 1),       # NULL A
+        (8, 8, 8, a, 8, b, 8, a, 8, 0, 1),       # C aliases A
+    ]
+    for args in cases:
+        rc = fastmm.gemm_raw(*args)
+        assert rc == fastmm.ERROR_INVALID_VALUE, args
+        assert fastmm.last_error() != ""
+        assert torch.all(C == 5.0).item()
+    assert fastmm.gemm_raw(8, 8, 8, a, 8, b, 8, c, 8, 0, 1, 9) == fastmm.ERROR_INVALID_VALUE
+
+
+def test_mixed_residency_not_supported(fastmm):
+    import torch
+    A = torch.ones((8, 8), device="cuda")
+    B = torch.ones((8, 8))
+    C = torch.full((8, 8), 5.0, device="cuda")
+    rc = fastmm.gemm_raw(8, 8, 8, A.data_ptr(), 8, B.data_ptr(), 8, C.data_ptr(), 8, 1, 1)
+    assert rc == fastmm.ERROR_NOT_SUPPORTED
+    assert torch.all(C == 5.0).item()
+
+
+def test_workspace_limit_gives_out_of_memory(fastmm, monkeypatch):
+    import torch
+    n = 512
+    A = dev(uniform(99, n, n))
+    B = dev(uniform(100, n, n))
+    C = torch.full((n, n), 5.0, device="cuda")
+    monkeypatch.setenv("FASTMM_WORKSPACE_LIMIT", "4096")
+    rc = fastmm.gemm_raw(n, n, n, A.data_ptr(), n, B.data_ptr(), n, C.data_ptr(), n, 2, 64)
+    assert rc == fastmm.ERROR_OUT_OF_MEMORY
+    assert "FASTMM_WORKSPACE_LIMIT" in fastmm.last_error()
+    monkeypatch.delenv("FASTMM_WORKSPACE_LIMIT")
+    fastmm.gemm(n, n, n, A, B, C, depth=2, leaf=64)
+    assert torch.isfinite(C).all().item()
+
+
+@pytest.mark.parametrize("n,depth,leaf", [(4096, 2, 1024), (4096, 3, 512), (8192, 3, 1024)])
+def test_config2_sampled_rows_and_freivalds(fastmm, n, depth, leaf):
+    say(f"config n={n} depth={depth} leaf={leaf}")
+    A = uniform(1001 + 2, n, n)
+    B = uniform(2001 + 2, n, n)
+    C = empty_dev(n, n)
+    fastmm.gemm(n, n, n, dev(A), dev(B), C, depth=depth, leaf=leaf)
+    got = host(C)
+    rows = synthgen.row_sample(7002, n, 48)
+    e_rows = checks.sampled_rows_rel(got, A, B, rows)
+    e_fv = checks.freivalds_rel(got, A, B, synthgen.signs_pm1(7003, n))
+    say(f"  depth={fastmm.get_stats()['depth']} rows={e_rows:.3e} freivalds={e_fv:.3e}")
+    assert e_rows <= TOL_WINOGRAD and e_fv <= TOL_WINOGRAD
