@@ -76,6 +76,13 @@ def load(path: str | None = None):
     path = path or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1205_2927_amd.build`")
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes the library bind to that one runtime instead of bringing a
+    # second copy into the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     i64, i32, vp, f32 = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_float
     P64 = ctypes.POINTER(ctypes.c_int64)
