@@ -65,7 +65,10 @@ void ensure_init(Library& L) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     throw Error(kNotSupported, std::string("fastmm is built for gfx950; device is ") +
                                    prop.gcnArchName);
-  FASTMM_HIP(hipStreamCreateWithFlags(&L.own_stream, hipStreamNonBlocking));
+  // A blocking stream: it waits for work the caller queued on the legacy
+  // default stream (e.g. the copies that produced A and B) and the default
+  // stream waits for it.
+  FASTMM_HIP(hipStreamCreate(&L.own_stream));
   if (!L.stream) L.stream = L.own_stream;
   for (auto& e : L.ev) FASTMM_HIP(hipEventCreate(&e));
   L.initialised = true;
