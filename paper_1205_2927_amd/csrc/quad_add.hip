@@ -141,9 +141,12 @@ postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
     float* bot = nd.dst + (int64_t)(r + h_r) * nd.ld;
     const bool rt = r < nd.rows;
     const bool rb = (r + h_r) < nd.rows;
-    store4(top + c, c11, VEC, rt, c, nd.cols);
+    // Left quadrants end at column h_c: a partial last group must not spill
+    // into the right quadrants, which other threads own.
+    const int lcols = min(nd.cols, h_c);
+    store4(top + c, c11, VEC, rt, c, lcols);
     store4(top + h_c + c, c12, VEC, rt, c + h_c, nd.cols);
-    store4(bot + c, c21, VEC, rb, c, nd.cols);
+    store4(bot + c, c21, VEC, rb, c, lcols);
     store4(bot + h_c + c, c22, VEC, rb, c + h_c, nd.cols);
   }
 }

@@ -46,7 +46,11 @@ def test_preadd_strided_view(fastmm):
 
 
 @pytest.mark.parametrize("h_r,h_c,rows,cols", [(32, 32, 64, 64), (17, 9, 33, 17), (17, 9, 34, 18),
-                                               (64, 128, 128, 256), (1, 1, 1, 1), (5, 12, 9, 23)])
+                                               (64, 128, 128, 256), (1, 1, 1, 1), (5, 12, 9, 23),
+                                               # odd h_c with many rows: the last partial group of
+                                               # a left quadrant and the first group of the right
+                                               # one fall in different wavefronts
+                                               (100, 65, 200, 130), (50, 33, 99, 65), (301, 7, 602, 13)])
 def test_postadd_bit_exact(fastmm, h_r, h_c, rows, cols):
     say(f"postadd {h_r}x{h_c} -> {rows}x{cols}")
     P = uniform(31 + h_r, 7 * h_r, h_c)
