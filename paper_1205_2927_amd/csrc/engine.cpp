@@ -322,8 +322,13 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     for (auto& g : s.leaf[t]) {
       g.tile_begin = (int32_t)total;
       total += (int64_t)((g.c_rows + ts.bm - 1) / ts.bm) * g.tiles_n;
-      if (!(aligned16(g.A) && aligned16(g.B) && g.lda % 4 == 0 && g.ldb % 4 == 0))
+      // 16-byte loads need aligned rows and float4 groups that are either
+      // wholly inside or wholly outside the valid extent.
+      if (!(aligned16(g.A) && aligned16(g.B) && g.lda % 4 == 0 && g.ldb % 4 == 0 &&
+            g.kmax % 4 == 0 && g.b_cols % 4 == 0))
         s.vec_leaf[t] = false;
+      if (g.lda > kMaxLeadingDimA || g.ldb > kMaxLeadingDimB)
+        throw Error(kNotSupported, "leading dimension too large for the leaf kernel");
     }
     if (total > INT32_MAX) throw Error(kNotSupported, "leaf launch too large");
     s.leaf_tiles_total[t] = (int)total;
@@ -440,6 +445,8 @@ void validate_gemm_args(int64_t M, int64_t N, int64_t K, const float* A, int64_t
   if (ldb < std::max<int64_t>(1, N)) throw Error(kInvalidValue, "ldb < max(1, N)");
   if (ldc < std::max<int64_t>(1, N)) throw Error(kInvalidValue, "ldc < max(1, N)");
   if (depth > 16) throw Error(kInvalidValue, "depth > 16");
+  if (lda > kMaxLeadingDimA || ldb > kMaxLeadingDimB)
+    throw Error(kNotSupported, "lda above 2^21 or ldb above 2^26 is not supported");
   if (M > 0 && N > 0 && C == nullptr) throw Error(kInvalidValue, "C is NULL");
   if (M > 0 && K > 0 && A == nullptr) throw Error(kInvalidValue, "A is NULL");
   if (K > 0 && N > 0 && B == nullptr) throw Error(kInvalidValue, "B is NULL");

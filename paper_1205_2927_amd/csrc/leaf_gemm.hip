@@ -30,6 +30,18 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kThreads = 256;  // 4 wavefronts of 64
 
+// Buffer resource over [p, p + bytes).  Both values are the same in every
+// lane; readfirstlane states that, so the resource lives in scalar registers
+// (a resource the compiler thinks may differ per lane costs a loop per load).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* p, int bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  float* q = reinterpret_cast<float*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, __builtin_amdgcn_readfirstlane(bytes),
+                                           0x00020000);
+}
+
 __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   // Blocks bid, bid+8, ... run on XCD bid%8; give each XCD a contiguous run
   // of logical tiles.
@@ -92,7 +104,7 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles)
   const int lr = lane & 31;
   const int lh = lane >> 5;
 
-  // Global -> register mapping.
+  // Global -> register mapping (fixed per thread).
   int a_r[A_F4], a_c[A_F4], b_r[B_F4], b_c[B_F4];
 #pragma unroll
   for (int i = 0; i < A_F4; ++i) {
@@ -107,44 +119,59 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles)
     b_c[i] = (f % (BN / 4)) * 4;
   }
 
+  // Loads are branch-free raw buffer loads: a slab's resource covers exactly
+  // its valid extent, and lanes outside it use an out-of-range offset, for
+  // which the hardware returns zero.  This is the zero padding of the
+  // recursion's odd quadrants and of ragged tiles, with no divergent code
+  // around the loads (which would force a wait right after each one).
+  const int rv = min(BM, a_rows - tm);  // valid rows of A in this tile
+  const int cv = min(BN, b_cols - tn);  // valid columns of B in this tile
+  const float* a_tile = A + (int64_t)tm * lda;
+  const float* b_tile = B + tn;
+  constexpr int kOOB = 0x7FFFFFF0;
+
   float4 ra[A_F4], rb[B_F4];
-  const bool rows_in = (tm + BM <= a_rows);
-  const bool cols_in = (tn + BN <= b_cols);
 
   auto load_slab = [&](int k0) {
-    const bool k_in = (k0 + BK <= kmax);
+    const int kv = min(BK, kmax - k0);  // valid k in this slab
+    const uint32_t a_bytes =
+        (rv > 0 && kv > 0) ? (uint32_t)(((int64_t)(rv - 1) * lda + kv) * 4) : 0u;
+    const uint32_t b_bytes =
+        (cv > 0 && kv > 0) ? (uint32_t)(((int64_t)(kv - 1) * ldb + cv) * 4) : 0u;
+    const __amdgpu_buffer_rsrc_t ar = make_rsrc(a_tile + k0, (int)a_bytes);
+    const __amdgpu_buffer_rsrc_t br = make_rsrc(b_tile + (int64_t)k0 * ldb, (int)b_bytes);
 #pragma unroll
     for (int i = 0; i < A_F4; ++i) {
-      const int r = tm + a_r[i];
-      const int c = k0 + a_c[i];
-      const float* p = A + (int64_t)r * lda + c;
-      if (VEC && rows_in && k_in) {
-        ra[i] = *reinterpret_cast<const float4*>(p);
-      } else if (VEC && r < a_rows && c + 3 < kmax) {
-        ra[i] = *reinterpret_cast<const float4*>(p);
+      const int base = (a_r[i] * (int)lda + a_c[i]) * 4;
+      const bool rok = a_r[i] < rv;
+      if (VEC) {
+        const int off = (rok && a_c[i] < kv) ? base : kOOB;
+        ra[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(ar, off, 0, 0));
       } else {
-        const bool rv = r < a_rows;
-        ra[i].x = (rv && c + 0 < kmax) ? p[0] : 0.f;
-        ra[i].y = (rv && c + 1 < kmax) ? p[1] : 0.f;
-        ra[i].z = (rv && c + 2 < kmax) ? p[2] : 0.f;
-        ra[i].w = (rv && c + 3 < kmax) ? p[3] : 0.f;
+        float e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int off = (rok && a_c[i] + q < kv) ? base + 4 * q : kOOB;
+          e[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ar, off, 0, 0));
+        }
+        ra[i] = make_float4(e[0], e[1], e[2], e[3]);
       }
     }
 #pragma unroll
     for (int i = 0; i < B_F4; ++i) {
-      const int r = k0 + b_r[i];
-      const int c = tn + b_c[i];
-      const float* p = B + (int64_t)r * ldb + c;
-      if (VEC && cols_in && k_in) {
-        rb[i] = *reinterpret_cast<const float4*>(p);
-      } else if (VEC && r < kmax && c + 3 < b_cols) {
-        rb[i] = *reinterpret_cast<const float4*>(p);
+      const int base = (b_r[i] * (int)ldb + b_c[i]) * 4;
+      const bool kok = b_r[i] < kv;
+      if (VEC) {
+        const int off = (kok && b_c[i] < cv) ? base : kOOB;
+        rb[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(br, off, 0, 0));
       } else {
-        const bool rv = r < kmax;
-        rb[i].x = (rv && c + 0 < b_cols) ? p[0] : 0.f;
-        rb[i].y = (rv && c + 1 < b_cols) ? p[1] : 0.f;
-        rb[i].z = (rv && c + 2 < b_cols) ? p[2] : 0.f;
-        rb[i].w = (rv && c + 3 < b_cols) ? p[3] : 0.f;
+        float e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int off = (kok && b_c[i] + q < cv) ? base + 4 * q : kOOB;
+          e[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(br, off, 0, 0));
+        }
+        rb[i] = make_float4(e[0], e[1], e[2], e[3]);
       }
     }
   };
