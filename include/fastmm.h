@@ -21,7 +21,11 @@
  *     FASTMM_ERROR_INVALID_VALUE or FASTMM_ERROR_NOT_SUPPORTED the outputs are
  *     untouched.
  *   - Every call is synchronous: it is enqueued on the library stream
- *     (fastmm_set_stream) and returns after that stream has drained.
+ *     (fastmm_set_stream) and returns after that stream has drained.  With
+ *     host operands the top recursion level runs product by product while
+ *     two copy streams move operand quadrants in and result quadrants out
+ *     (set FASTMM_PIPELINE=0 to copy everything first instead); the result
+ *     is bit for bit the same either way.
  *   - The caller owns A, B and C; the library never keeps them.  The library
  *     owns its workspace (device memory for the recursion's temporaries and
  *     for staging host operands), which grows on demand and is released by
@@ -86,6 +90,7 @@ typedef struct {
   /* Phase times of the last call from HIP events on the library stream, in
    * milliseconds; -1 when profiling is off (fastmm_set_profiling). */
   double h2d_ms, preadd_ms, leaf_ms, postadd_ms, d2h_ms, total_ms;
+  int leaf_launches;       /* grouped leaf launches leaf_ms is summed over */
 } fastmm_stats_t;
 
 /* C = A*B.  M, N, K >= 0.  lda >= max(1,K), ldb >= max(1,N), ldc >= max(1,N).

@@ -121,7 +121,9 @@ void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_ti
                       hipStream_t stream);
 void launch_preadd(int side, const PreAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
                    hipStream_t stream);
+// quad < 0: all four result quadrants; 0..3: only C11, C12, C21 or C22
+// (each by the same chain of operations as in the fused form).
 void launch_postadd(const PostAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
-                    hipStream_t stream);
+                    hipStream_t stream, int quad = -1);
 
 }  // namespace fastmm

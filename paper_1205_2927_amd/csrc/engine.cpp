@@ -71,6 +71,12 @@ void ensure_init(Library& L) {
   FASTMM_HIP(hipStreamCreate(&L.own_stream));
   if (!L.stream) L.stream = L.own_stream;
   for (auto& e : L.ev) FASTMM_HIP(hipEventCreate(&e));
+  // Copy streams for the staged path (default priority, ordered against the
+  // compute stream by events).
+  FASTMM_HIP(hipStreamCreateWithFlags(&L.h2d_stream, hipStreamNonBlocking));
+  FASTMM_HIP(hipStreamCreateWithFlags(&L.d2h_stream, hipStreamNonBlocking));
+  for (auto& e : L.sync_ev) FASTMM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto& e : L.leaf_ev) FASTMM_HIP(hipEventCreate(&e));
   L.initialised = true;
 }
 
@@ -191,7 +197,7 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
   for (const auto& p : probs) {
     const auto dims = level_dims(p);
     const int d = p.depth;
-    std::vector<View> Av{{p.A, p.lda, p.M, p.K}}, Bv{{p.B, p.ldb, p.K, p.N}};
+    std::vector<View> Av{{p.A, p.lda, p.ar(), p.ac()}}, Bv{{p.B, p.ldb, p.br(), p.bc()}};
     // Pre-additions, level by level; the next level's operands are views
     // of this level's operands or of the new S / T blocks.
     for (int l = 0; l < d; ++l) {
@@ -248,8 +254,8 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
       if (d == 0) {
         g.C = p.C;
         g.ldc = p.ldc;
-        g.c_rows = (int32_t)p.M;
-        g.c_cols = (int32_t)p.N;
+        g.c_rows = (int32_t)p.cr();
+        g.c_cols = (int32_t)p.cc();
       } else {
         g.C = P[d] + x * lf.m * lf.n;
         g.ldc = lf.n;
@@ -272,8 +278,8 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
         if (l == 0) {
           pn.dst = p.C;
           pn.ld = p.ldc;
-          pn.rows = (int32_t)p.M;
-          pn.cols = (int32_t)p.N;
+          pn.rows = (int32_t)p.cr();
+          pn.cols = (int32_t)p.cc();
         } else {
           pn.dst = P[l] + x * dims[l].m * dims[l].n;
           pn.ld = dims[l].n;
@@ -357,7 +363,8 @@ int add_total_blocks(const std::vector<PostAddNode>& v) {
 }
 }  // namespace
 
-int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host) {
+int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host,
+                     hipEvent_t leaf_begin, hipEvent_t leaf_end) {
   // Pack every descriptor array into one host block, upload it once.
   size_t off = 0;
   auto put = [&](const void* src, size_t bytes) {
@@ -387,12 +394,14 @@ int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host) {
     if (bb) { launch_preadd(1, dB[l], (int)s.preB[l].size(), bb, s.vec_preB[l], L.stream); ++launches; }
   }
   if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[2], L.stream));
+  if (leaf_begin) FASTMM_HIP(hipEventRecord(leaf_begin, L.stream));
   for (int t = 0; t < kNumTiles; ++t) {
     if (s.leaf_tiles_total[t] > 0) {
       launch_leaf_gemm(t, dL[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t], L.stream);
       ++launches;
     }
   }
+  if (leaf_end) FASTMM_HIP(hipEventRecord(leaf_end, L.stream));
   if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[3], L.stream));
   for (int l = s.max_depth - 1; l >= 0; --l) {
     const int bp = add_total_blocks(s.post[l]);
@@ -514,6 +523,17 @@ void do_gemm(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_
   p.depth = (K == 0) ? 0 : effective_depth(M, N, K, depth, leaf);
   p.tile = tile;
 
+  const char* pipe = std::getenv("FASTMM_PIPELINE");
+  const bool pipelined = !(pipe && pipe[0] == '0');
+  if (!on_dev && pipelined && std::min(std::min(M, N), K) >= 2) {
+    gemm_host_pipelined(L, M, N, K, A, lda, B, ldb, C, ldc, p.depth, tile, st);
+    if (!L.profiling) {
+      st.h2d_ms = st.preadd_ms = st.leaf_ms = st.postadd_ms = st.d2h_ms = st.total_ms = -1.0;
+    }
+    L.stats = st;
+    return;
+  }
+
   // Workspace: [staged A | staged B | staged C | temporaries | descriptors].
   const size_t a_bytes = on_dev ? 0 : align_up((size_t)M * K * 4, 256);
   const size_t b_bytes = on_dev ? 0 : align_up((size_t)K * N * 4, 256);
@@ -584,6 +604,8 @@ void do_gemm(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_
   st.transfer_bytes = on_dev ? 0.0 : 4.0 * ((double)M * K + (double)K * N + (double)M * N);
   st.launches = launches;
   st.workspace_bytes = L.arena_bytes;
+  st.leaf_launches = 0;
+  for (int t = 0; t < kNumTiles; ++t) st.leaf_launches += s.leaf_tiles_total[t] > 0 ? 1 : 0;
   if (L.profiling && K > 0) {
     st.h2d_ms = ev_ms(L.ev[0], L.ev[5]);
     st.preadd_ms = ev_ms(L.ev[1], L.ev[2]);
@@ -731,6 +753,17 @@ void fastmm_finalize(void) {
   if (L.pinned) (void)hipHostFree(L.pinned);
   for (auto& e : L.ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : L.sync_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : L.leaf_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (L.h2d_stream) (void)hipStreamSynchronize(L.h2d_stream);
+  if (L.d2h_stream) (void)hipStreamSynchronize(L.d2h_stream);
+  if (L.h2d_stream) (void)hipStreamDestroy(L.h2d_stream);
+  if (L.d2h_stream) (void)hipStreamDestroy(L.d2h_stream);
+  L.h2d_stream = L.d2h_stream = nullptr;
+  for (auto& e : L.sync_ev) e = nullptr;
+  for (auto& e : L.leaf_ev) e = nullptr;
   if (L.own_stream) (void)hipStreamDestroy(L.own_stream);
   L.arena = nullptr;
   L.arena_bytes = 0;

@@ -31,16 +31,28 @@ inline bool splits(int64_t m, int64_t k, int64_t n, int levels_left, int64_t lea
 int effective_depth(int64_t M, int64_t N, int64_t K, int depth, int64_t leaf);
 
 // One product as the engine sees it, operands already device-resident.
+// M, N, K are the (virtual) extents; each operand may hold fewer valid rows
+// or columns (the rest reads as zero), which is how a quadrant of an odd
+// extent enters the recursion.  C is written over c_rows x c_cols.
 struct Problem {
   int64_t M = 0, N = 0, K = 0;
   const float* A = nullptr;
   int64_t lda = 0;
+  int64_t a_rows = -1, a_cols = -1;  // -1: M, K
   const float* B = nullptr;
   int64_t ldb = 0;
+  int64_t b_rows = -1, b_cols = -1;  // -1: K, N
   float* C = nullptr;
   int64_t ldc = 0;
+  int64_t c_rows = -1, c_cols = -1;  // -1: M, N
   int depth = 0;  // effective depth
   int tile = 0;
+  int64_t ar() const { return a_rows < 0 ? M : a_rows; }
+  int64_t ac() const { return a_cols < 0 ? K : a_cols; }
+  int64_t br() const { return b_rows < 0 ? K : b_rows; }
+  int64_t bc() const { return b_cols < 0 ? N : b_cols; }
+  int64_t cr() const { return c_rows < 0 ? M : c_rows; }
+  int64_t cc() const { return c_cols < 0 ? N : c_cols; }
 };
 
 // A level-wise schedule over a set of problems.
@@ -81,6 +93,12 @@ struct Library {
   size_t pinned_bytes = 0;
   bool profiling = false;
   hipEvent_t ev[8] = {};
+  hipStream_t h2d_stream = nullptr;  // host->device staging copies
+  hipStream_t d2h_stream = nullptr;  // device->host result copies
+  static constexpr int kSyncEvents = 16;
+  hipEvent_t sync_ev[kSyncEvents] = {};  // ordering between the streams
+  static constexpr int kLeafEvents = 16;
+  hipEvent_t leaf_ev[kLeafEvents] = {};  // timing of leaf launches
   fastmm_stats_t stats{};
   size_t limit = 0;              // workspace cap (0: none)
   int plan_mode = FASTMM_PLAN_DEFAULT;
@@ -94,8 +112,16 @@ char* ensure_pinned(Library& L, size_t bytes);
 // Uploads every descriptor array of `s` (one copy) and enqueues all launches
 // on L.stream.  Returns the number of launches.  Events ev[1..4] bracket
 // pre-additions, leaves and post-additions when profiling is on.
-int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host);
+int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host,
+                     hipEvent_t leaf_begin = nullptr, hipEvent_t leaf_end = nullptr);
 size_t schedule_desc_bytes(const Schedule& s);
+
+// Host-resident operands: stage quadrants in, run the top level of the
+// recursion product by product as the quadrants arrive, and stream result
+// quadrants out as they complete (pipeline.cpp).
+void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const float* A,
+                         int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
+                         int depth, int tile, fastmm_stats_t& st);
 
 // Planner hooks (planner.cpp).
 int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out);

@@ -108,7 +108,7 @@ preadd_kernel(const PreAddNode* __restrict__ nodes, int nnodes) {
   }
 }
 
-template <bool VEC>
+template <bool VEC, int QUAD>
 __global__ void __launch_bounds__(kAddThreads)
 postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
   const PostAddNode nd = nodes[find_node(nodes, nnodes, blockIdx.x)];
@@ -117,6 +117,12 @@ postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
   const int64_t groups = (int64_t)h_r * c4n;
   const int64_t q_elems = (int64_t)h_r * h_c;
   const int64_t g0 = (int64_t)(blockIdx.x - nd.block_begin) * kAddChunk;
+  // Products each quadrant reads (P1..P7 = bit 0..6).
+  constexpr unsigned kNeed = QUAD < 0 ? 0x7Fu
+                           : QUAD == 0 ? 0x03u                 // C11: P1 P2
+                           : QUAD == 1 ? (0x01u | 0x20u | 0x10u | 0x04u)  // C12: P1 P6 P5 P3
+                           : QUAD == 2 ? (0x01u | 0x20u | 0x40u | 0x08u)  // C21: P1 P6 P7 P4
+                                       : (0x01u | 0x20u | 0x40u | 0x10u); // C22: P1 P6 P7 P5
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
     const int64_t gidx = g0 + it * kAddThreads + threadIdx.x;
@@ -126,7 +132,8 @@ postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
     const float* p = nd.P + (int64_t)r * h_c + c;
     float4 P[7];
 #pragma unroll
-    for (int i = 0; i < 7; ++i) P[i] = load4(p + i * q_elems, VEC, true, c, h_c);
+    for (int i = 0; i < 7; ++i)
+      P[i] = (kNeed >> i) & 1u ? load4(p + i * q_elems, VEC, true, c, h_c) : make_float4(0.f, 0.f, 0.f, 0.f);
     float4 c11, c12, c21, c22, u2, u3, u4;
     // C11 = P1 + P2; U2 = P1 + P6; U3 = U2 + P7; U4 = U2 + P5
     // C12 = U4 + P3; C21 = U3 - P4; C22 = U3 + P5
@@ -144,10 +151,10 @@ postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
     // Left quadrants end at column h_c: a partial last group must not spill
     // into the right quadrants, which other threads own.
     const int lcols = min(nd.cols, h_c);
-    store4(top + c, c11, VEC, rt, c, lcols);
-    store4(top + h_c + c, c12, VEC, rt, c + h_c, nd.cols);
-    store4(bot + c, c21, VEC, rb, c, lcols);
-    store4(bot + h_c + c, c22, VEC, rb, c + h_c, nd.cols);
+    if (QUAD < 0 || QUAD == 0) store4(top + c, c11, VEC, rt, c, lcols);
+    if (QUAD < 0 || QUAD == 1) store4(top + h_c + c, c12, VEC, rt, c + h_c, nd.cols);
+    if (QUAD < 0 || QUAD == 2) store4(bot + c, c21, VEC, rb, c, lcols);
+    if (QUAD < 0 || QUAD == 3) store4(bot + h_c + c, c22, VEC, rb, c + h_c, nd.cols);
   }
 }
 
@@ -165,12 +172,24 @@ void launch_preadd(int side, const PreAddNode* d_nodes, int nnodes, int total_bl
   FASTMM_HIP(hipGetLastError());
 }
 
+template <int QUAD>
+static void launch_post_q(const PostAddNode* d, int n, int blocks, bool vec, hipStream_t s) {
+  dim3 grid(blocks), block(kAddThreads);
+  if (vec) hipLaunchKernelGGL((postadd_kernel<true, QUAD>), grid, block, 0, s, d, n);
+  else hipLaunchKernelGGL((postadd_kernel<false, QUAD>), grid, block, 0, s, d, n);
+}
+
 void launch_postadd(const PostAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
-                    hipStream_t stream) {
+                    hipStream_t stream, int quad) {
   if (nnodes <= 0 || total_blocks <= 0) return;
-  dim3 grid(total_blocks), block(kAddThreads);
-  if (vec) hipLaunchKernelGGL((postadd_kernel<true>), grid, block, 0, stream, d_nodes, nnodes);
-  else hipLaunchKernelGGL((postadd_kernel<false>), grid, block, 0, stream, d_nodes, nnodes);
+  switch (quad) {
+    case -1: launch_post_q<-1>(d_nodes, nnodes, total_blocks, vec, stream); break;
+    case 0: launch_post_q<0>(d_nodes, nnodes, total_blocks, vec, stream); break;
+    case 1: launch_post_q<1>(d_nodes, nnodes, total_blocks, vec, stream); break;
+    case 2: launch_post_q<2>(d_nodes, nnodes, total_blocks, vec, stream); break;
+    case 3: launch_post_q<3>(d_nodes, nnodes, total_blocks, vec, stream); break;
+    default: throw Error(kInvalidValue, "bad quadrant");
+  }
   FASTMM_HIP(hipGetLastError());
 }
 

@@ -47,7 +47,7 @@ def test_struct_layouts_match_header():
     from paper_1205_2927_amd import fastmm
     # fastmm_plan_t: int, int64, int, size_t, double, int -> 48 bytes on LP64
     assert ctypes.sizeof(fastmm.Plan) == 48
-    assert ctypes.sizeof(fastmm.Stats) == 4 + 4 + 8 * 4 + 8 * 3 + 4 + 4 + 8 + 8 * 6
+    assert ctypes.sizeof(fastmm.Stats) == 4 + 4 + 8 * 4 + 8 * 3 + 4 + 4 + 8 + 8 * 6 + 8
 
 
 def test_oracle_is_not_linked_by_the_library():

@@ -211,3 +211,28 @@ def test_config2_sampled_rows_and_freivalds(fastmm, n, depth, leaf):
     e_fv = checks.freivalds_rel(got, A, B, synthgen.signs_pm1(7003, n))
     say(f"  depth={fastmm.get_stats()['depth']} rows={e_rows:.3e} freivalds={e_fv:.3e}")
     assert e_rows <= TOL_WINOGRAD and e_fv <= TOL_WINOGRAD
+
+
+@pytest.mark.parametrize("m,k,n,depth", [(640, 640, 640, 2), (333, 201, 257, 3), (300, 260, 280, 0),
+                                         (97, 301, 45, 1), (2, 3, 2, 1), (1024, 512, 768, 3)])
+@pytest.mark.parametrize("pipeline", ["1", "0"])
+def test_host_paths_bitwise_equal_device(fastmm, monkeypatch, m, k, n, depth, pipeline):
+    # Host operands go through the staged path (pipelined: quadrants in, top
+    # level product by product, result quadrants out; or copy-all-first).
+    # Either way the result must be bit for bit the device-resident one.
+    import torch
+    say(f"host path {m}x{k}x{n} depth={depth} pipeline={pipeline}")
+    monkeypatch.setenv("FASTMM_PIPELINE", pipeline)
+    A = uniform(111 + m, m, k)
+    B = uniform(112 + n, k, n)
+    Cd = empty_dev(m, n)
+    fastmm.gemm(m, n, k, dev(A), dev(B), Cd, depth=depth, leaf=1)
+    ref = host(Cd)
+    Ap = torch.from_numpy(A).pin_memory()
+    Bp = torch.from_numpy(B).pin_memory()
+    Cp = torch.full((m, n), float("nan")).pin_memory()
+    fastmm.gemm(m, n, k, Ap, Bp, Cp, depth=depth, leaf=1)
+    assert np.array_equal(Cp.numpy(), ref)
+    st = fastmm.get_stats()
+    assert st["depth"] == W.effective_depth(m, k, n, depth, 1)
+    assert checks.rel_frob(ref, classic.gemm(A, B)) < TOL_WINOGRAD
