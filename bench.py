@@ -24,6 +24,12 @@ sys.path.insert(0, ROOT)
 METRIC = "effective GFLOPS (2MNK/wall-clock) n=19456 FP32 Winograd vs plain MFMA SGEMM"
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per leaf launch (pipelined depth-3 launch of 49 leaves of
+# 2432^3) from the FETCH_SIZE and WRITE_SIZE counter runs, each scaled by the
+# reading of a 1 GiB calibration copy (fetch x2.000, write x1.000); see
+# profiles/leaf_gemm_n19456_d3_pinned_hbm_traffic.md.  Valid for
+# leaf_gemm_kernel<128,128,16> at that configuration only.
+TRAFFIC_BYTES_PER_LAUNCH = 5063520.5 * 1024 * 2.000 + 1132096.0 * 1024 * 1.000
 
 
 def log(msg):
@@ -54,9 +60,12 @@ def main():
     ap.add_argument("--depth", type=int, default=-1, help="-1: pick the best of 2, 3, 4")
     ap.add_argument("--leaf", type=int, default=1024)
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-device-context", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="first run one plain 1 GiB device copy (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the sharded "
@@ -70,6 +79,13 @@ def main():
     from paper_1205_2927_amd import fastmm
 
     fastmm.load()
+    if args.traffic_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     n = args.n
     M = N = K = n
     log(f"bench: n={n} allocating pinned host operands")
@@ -86,7 +102,6 @@ def main():
     def run(depth, tile=args.tile, leaf=args.leaf):
         return lambda: fastmm.gemm(M, N, K, A, B, C, depth=depth, leaf=leaf, tile=tile)
 
-    result = {}
     # Plain MFMA SGEMM (depth 0), same staging path.
     plain = None
     if not args.no_plain:
@@ -94,7 +109,7 @@ def main():
         tot, ts = time_calls(run(0), args.steps, args.warmup)
         st = fastmm.get_stats()
         plain = {"ms_per_step": 1e3 * tot / args.steps, "value": flops / (tot / args.steps) / 1e9,
-                 "leaf_ms": st["leaf_ms"], "h2d_ms": st["h2d_ms"], "d2h_ms": st["d2h_ms"],
+                 "leaf_ms": st["leaf_ms"], "h2d_span_ms": st["h2d_ms"],
                  "leaf_tflops": st["leaf_flops"] / (st["leaf_ms"] * 1e-3) / 1e12}
         log(f"  plain: {plain}")
 
@@ -109,20 +124,18 @@ def main():
     else:
         best = depths[0]
     log(f"bench: Winograd depth {best}, {args.steps} timed steps")
-    leaf_ms, pre_ms, post_ms, h2d_ms, d2h_ms = [], [], [], [], []
+    leaf_ms, h2d_ms = [], []
 
     def step():
         fastmm.gemm(M, N, K, A, B, C, depth=best, leaf=args.leaf, tile=args.tile)
         s = fastmm.get_stats()
         leaf_ms.append(s["leaf_ms"])
-        pre_ms.append(s["preadd_ms"])
-        post_ms.append(s["postadd_ms"])
         h2d_ms.append(s["h2d_ms"])
-        d2h_ms.append(s["d2h_ms"])
 
     for _ in range(args.warmup):
         step()
-    leaf_ms.clear(); pre_ms.clear(); post_ms.clear(); h2d_ms.clear(); d2h_ms.clear()
+    leaf_ms.clear()
+    h2d_ms.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -145,22 +158,54 @@ def main():
               "rows": int(rows.size), "tolerance": 1e-4}
     log(f"bench: parity {parity}")
 
-    leaf_avg = float(np.mean(leaf_ms))
-    leaf_tflops = st["leaf_flops"] / (leaf_avg * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": "leaf_gemm_kernel (grouped, all 7^d leaves)",
+    # Dominant kernel: the grouped leaf GEMM.  Its launches are timed with
+    # HIP events recorded by the library on the stream it launches them on.
+    n_launch = max(1, st["leaf_launches"])
+    leaf_sum = float(np.mean(leaf_ms))          # ms per step, all leaf launches
+    avg_launch = leaf_sum / n_launch
+    flops_launch = st["leaf_flops"] / n_launch
+    leaf_tflops = flops_launch / (avg_launch * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": "leaf_gemm_kernel<128,128,16> (grouped leaves)",
                 "achieved": leaf_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": leaf_tflops / PEAK_FP32_TFLOPS, "traffic": None,
-                "flops_per_launch": st["leaf_flops"], "avg_launch_ms": leaf_avg}
-    adds = {"preadd_ms": float(np.mean(pre_ms)), "postadd_ms": float(np.mean(post_ms)),
-            "add_bytes": st["add_bytes"],
-            "add_GBps": st["add_bytes"] / ((np.mean(pre_ms) + np.mean(post_ms)) * 1e-3) / 1e9,
-            "h2d_ms": float(np.mean(h2d_ms)), "d2h_ms": float(np.mean(d2h_ms))}
+                "frac": leaf_tflops / PEAK_FP32_TFLOPS, "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+                "flops_per_launch": flops_launch, "avg_launch_ms": avg_launch,
+                "launches_per_step": n_launch}
+
+    # Context: the same product with device-resident operands (level-wise
+    # path, no transfers), with the addition kernels timed separately.
+    dev_ctx = None
+    if not args.no_device_context:
+        dA = A.to("cuda")
+        dB = B.to("cuda")
+        dC = torch.empty((M, N), dtype=torch.float32, device="cuda")
+        fastmm.gemm(M, N, K, dA, dB, dC, depth=best, leaf=args.leaf, tile=args.tile)
+        ts = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fastmm.gemm(M, N, K, dA, dB, dC, depth=best, leaf=args.leaf, tile=args.tile)
+            ts.append(time.perf_counter() - t)
+        sd = fastmm.get_stats()
+        add_ms = sd["preadd_ms"] + sd["postadd_ms"]
+        dev_ctx = {"ms": 1e3 * min(ts), "effective_GFLOPS": flops / min(ts) / 1e9,
+                   "leaf_ms": sd["leaf_ms"],
+                   "leaf_TFLOPs": sd["leaf_flops"] / (sd["leaf_ms"] * 1e-3) / 1e12,
+                   "preadd_ms": sd["preadd_ms"], "postadd_ms": sd["postadd_ms"],
+                   "add_bytes": sd["add_bytes"],
+                   "add_GBps": sd["add_bytes"] / (add_ms * 1e-3) / 1e9 if add_ms > 0 else None,
+                   "add_frac_of_hbm_peak": (sd["add_bytes"] / (add_ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
+                   if add_ms > 0 else None}
+        del dA, dB, dC
+        torch.cuda.empty_cache()
+        log(f"bench: device-resident context {dev_ctx}")
+    phases = {"h2d_span_ms": float(np.mean(h2d_ms)), "leaf_ms": leaf_sum,
+              "add_bytes": st["add_bytes"], "transfer_bytes": st["transfer_bytes"]}
 
     cpu = None
     if not args.no_cpu:
         from oracle import classic
         threads = classic.num_threads()
-        rows_c = synthgen.row_sample(7006, M, 4)
+        rows_c = synthgen.row_sample(7006, M, 32)
         t = time.perf_counter()
         classic.gemm_rows(An, Bn, rows_c)
         per_row = (time.perf_counter() - t) / rows_c.size
@@ -188,7 +233,7 @@ def main():
         "plain_sgemm": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms_per_step) if plain else None,
         "depth_probe_ms": {str(k): 1e3 * v for k, v in probe.items()},
-        "phases": adds, "parity": parity,
+        "phases": phases, "device_resident": dev_ctx, "parity": parity,
     }
     print(json.dumps(out), flush=True)
 

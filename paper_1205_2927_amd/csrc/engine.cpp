@@ -77,6 +77,7 @@ void ensure_init(Library& L) {
   FASTMM_HIP(hipStreamCreateWithFlags(&L.d2h_stream, hipStreamNonBlocking));
   for (auto& e : L.sync_ev) FASTMM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (auto& e : L.leaf_ev) FASTMM_HIP(hipEventCreate(&e));
+  for (auto& e : L.tune_ev) FASTMM_HIP(hipEventCreate(&e));
   L.initialised = true;
 }
 
@@ -491,9 +492,11 @@ double ev_ms(hipEvent_t a, hipEvent_t b) {
   return ms;
 }
 
-void do_gemm(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
-             const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
-             int tile) {
+}  // namespace
+
+void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+               const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
+               int tile) {
   validate_gemm_args(M, N, K, A, lda, B, ldb, C, ldc, depth);
   if (tile >= kNumTiles) throw Error(kInvalidValue, "unknown tile id");
   ensure_init(L);
@@ -617,6 +620,8 @@ void do_gemm(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_
   L.stats = st;
 }
 
+namespace {
+
 template <typename F>
 int guarded(F&& f) {
   try {
@@ -652,7 +657,7 @@ int fastmm_gemm_ex(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                    int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf, int tile) {
   Library& L = lib();
   std::lock_guard<std::mutex> g(L.mu);
-  return guarded([&] { do_gemm(L, M, N, K, A, lda, B, ldb, C, ldc, depth, leaf, tile); });
+  return guarded([&] { gemm_impl(L, M, N, K, A, lda, B, ldb, C, ldc, depth, leaf, tile); });
 }
 
 int fastmm_gemm(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
@@ -757,6 +762,8 @@ void fastmm_finalize(void) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : L.leaf_ev)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : L.tune_ev)
+    if (e) (void)hipEventDestroy(e);
   if (L.h2d_stream) (void)hipStreamSynchronize(L.h2d_stream);
   if (L.d2h_stream) (void)hipStreamSynchronize(L.d2h_stream);
   if (L.h2d_stream) (void)hipStreamDestroy(L.h2d_stream);
@@ -764,6 +771,7 @@ void fastmm_finalize(void) {
   L.h2d_stream = L.d2h_stream = nullptr;
   for (auto& e : L.sync_ev) e = nullptr;
   for (auto& e : L.leaf_ev) e = nullptr;
+  for (auto& e : L.tune_ev) e = nullptr;
   if (L.own_stream) (void)hipStreamDestroy(L.own_stream);
   L.arena = nullptr;
   L.arena_bytes = 0;

@@ -99,6 +99,7 @@ struct Library {
   hipEvent_t sync_ev[kSyncEvents] = {};  // ordering between the streams
   static constexpr int kLeafEvents = 16;
   hipEvent_t leaf_ev[kLeafEvents] = {};  // timing of leaf launches
+  hipEvent_t tune_ev[2] = {};            // planner's candidate timing
   fastmm_stats_t stats{};
   size_t limit = 0;              // workspace cap (0: none)
   int plan_mode = FASTMM_PLAN_DEFAULT;
@@ -122,6 +123,11 @@ size_t schedule_desc_bytes(const Schedule& s);
 void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const float* A,
                          int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
                          int depth, int tile, fastmm_stats_t& st);
+
+// The single-product path behind fastmm_gemm_ex (caller holds L.mu).
+void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+               const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
+               int tile);
 
 // Planner hooks (planner.cpp).
 int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out);

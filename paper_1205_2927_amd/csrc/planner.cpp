@@ -1,21 +1,448 @@
-// Planner stub (filled in below by the full planner).
+// Planner: chooses recursion depth and leaf tile per shape.
+//
+// The paper picks its leaf engine from the problem size with fixed
+// thresholds found by experiment (Table 2 and the K0 / K1 operating points of
+// Section 3.2) and stops the recursion at a fixed size (Section 3.1).  Three
+// modes here:
+//   DEFAULT     the fixed rule: split while the leaf stays >= 1024, tile
+//               128x128 (the analogue of the paper's size thresholds);
+//   EXHAUSTIVE  time every candidate (depth, tile) on the device with
+//               device-resident operands, keep the fastest; every timing is
+//               a record of the timing database;
+//   MODEL       a learned cost model (the 5 -> 64 -> 64 -> 1 network of
+//               mlp.hip, trained on the GPU on the timing database) predicts
+//               each candidate's log2 run time; the argmin is taken.  With no
+//               trained model it falls back to EXHAUSTIVE.
+// Candidates: depth 0..4 with leaves of at least 128 in every dimension,
+// times the four leaf tiles.  Ties go to the smaller depth, then tile id.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
 #include "engine.h"
 
 namespace fastmm {
 
-int64_t default_leaf() { return 1024; }
+// mlp.hip
+size_t mlp_scratch_floats(int batch);
+void mlp_forward(int batch, const float* p, const float* X, float* y, float* cache, hipStream_t s);
+void mlp_backward(int batch, const float* p, const float* X, const float* t, float* grad,
+                  float* loss, float* scratch, hipStream_t s);
+void mlp_adam(const float* g, float* p, float* m, float* v, int step, float lr, float b1,
+              float b2, float eps, hipStream_t s);
+// engine.cpp
+void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+               const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
+               int tile);
+
+namespace {
+
+constexpr int kNParams = FASTMM_MLP_PARAMS;
+constexpr int64_t kMinLeaf = 128;   // smallest leaf extent a candidate may reach
+constexpr int kMaxDepth = 4;
+constexpr int64_t kDefaultLeaf = 1024;
+
+struct Record {
+  int64_t M, N, K;
+  int depth, tile;
+  double ms;
+};
+
+struct Planner {
+  std::vector<Record> db;
+  std::map<std::tuple<int64_t, int64_t, int64_t, int>, fastmm_plan_t> cache;
+  bool trained = false;
+  std::vector<float> params;  // host copy of the model
+};
+
+Planner& planner() {
+  static Planner P;
+  return P;
+}
+
+// SplitMix64 (Steele, Lea and Flood 2014): the planner's own seeded draws
+// (weight initialisation, minibatch order).
+uint64_t splitmix64(uint64_t& state) {
+  uint64_t z = (state += 0x9E3779B97F4A7C15ULL);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+double uniform01(uint64_t& s) { return (double)(splitmix64(s) >> 11) * 0x1p-53; }
+
+// Features of a candidate, scaled to roughly [-1, 1].
+void features(int64_t M, int64_t N, int64_t K, int depth, int tile, float* f) {
+  const TileShape ts = tile_shape(tile);
+  f[0] = (float)((std::log2((double)M) - 10.0) / 2.0);
+  f[1] = (float)((std::log2((double)N) - 10.0) / 2.0);
+  f[2] = (float)((std::log2((double)K) - 10.0) / 2.0);
+  f[3] = (float)((depth - 2.0) / 2.0);
+  f[4] = (float)(std::log2((double)ts.bm * ts.bn) - 14.0);
+}
+
+std::vector<std::pair<int, int>> candidates(int64_t M, int64_t N, int64_t K) {
+  std::vector<std::pair<int, int>> c;
+  const int64_t mn = std::min(std::min(M, N), K);
+  for (int d = 0; d <= kMaxDepth; ++d) {
+    if (d > 0 && (mn >> d) < kMinLeaf) break;
+    for (int t = 0; t < kNumTiles; ++t) c.push_back({d, t});
+  }
+  return c;
+}
+
+fastmm_plan_t make_plan(int depth, int tile, double ms, int source) {
+  fastmm_plan_t p{};
+  p.depth = depth;
+  p.leaf = depth == 0 ? kDefaultLeaf : 1;  // depth is reachable: leaves >= kMinLeaf
+  p.tile = tile;
+  p.workspace_bytes = 0;
+  p.predicted_ms = ms;
+  p.source = source;
+  return p;
+}
+
+__global__ void fill_uniform_kernel(float* x, int64_t n, uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    x[i] = (float)((double)((int64_t)(z >> 40) - (1 << 23)) * 0x1p-23);
+  }
+}
+
+// Time every candidate of (M, N, K) with device-resident operands.
+fastmm_plan_t tune_exhaustive(Library& L, int64_t M, int64_t N, int64_t K) {
+  Planner& P = planner();
+  float *dA = nullptr, *dB = nullptr, *dC = nullptr;
+  FASTMM_HIP(hipMalloc(&dA, (size_t)M * K * 4));
+  FASTMM_HIP(hipMalloc(&dB, (size_t)K * N * 4));
+  FASTMM_HIP(hipMalloc(&dC, (size_t)M * N * 4));
+  auto release = [&] {
+    (void)hipFree(dA);
+    (void)hipFree(dB);
+    (void)hipFree(dC);
+  };
+  fastmm_plan_t best{};
+  double best_ms = 1e30;
+  try {
+    hipLaunchKernelGGL(fill_uniform_kernel, dim3(1024), dim3(256), 0, L.stream, dA, M * K, 0x5eedULL);
+    hipLaunchKernelGGL(fill_uniform_kernel, dim3(1024), dim3(256), 0, L.stream, dB, K * N, 0xbeefULL);
+    FASTMM_HIP(hipGetLastError());
+    hipEvent_t e0 = L.tune_ev[0], e1 = L.tune_ev[1];
+    for (auto [d, t] : candidates(M, N, K)) {
+      const int64_t leaf = d == 0 ? kDefaultLeaf : 1;
+      gemm_impl(L, M, N, K, dA, K, dB, N, dC, N, d, leaf, t);  // warm-up
+      double ms = 1e30;
+      for (int rep = 0; rep < 3; ++rep) {
+        FASTMM_HIP(hipEventRecord(e0, L.stream));
+        gemm_impl(L, M, N, K, dA, K, dB, N, dC, N, d, leaf, t);
+        FASTMM_HIP(hipEventRecord(e1, L.stream));
+        FASTMM_HIP(hipEventSynchronize(e1));
+        float x = 0.f;
+        FASTMM_HIP(hipEventElapsedTime(&x, e0, e1));
+        ms = std::min(ms, (double)x);
+      }
+      P.db.push_back({M, N, K, d, t, ms});
+      if (ms < best_ms) {  // strict: earlier (smaller depth, tile) wins ties
+        best_ms = ms;
+        best = make_plan(d, t, ms, FASTMM_PLAN_EXHAUSTIVE);
+      }
+    }
+  } catch (...) {
+    release();
+    throw;
+  }
+  release();
+  return best;
+}
+
+// Device copies of the model parameters and a small inference buffer.
+struct ModelDev {
+  float* params = nullptr;
+  float* buf = nullptr;  // features (64 x 5) and outputs (64)
+};
+
+ModelDev& model_dev() {
+  static ModelDev D;
+  return D;
+}
+
+void upload_model(Library& L) {
+  ModelDev& D = model_dev();
+  if (!D.params) FASTMM_HIP(hipMalloc(&D.params, kNParams * 4));
+  if (!D.buf) FASTMM_HIP(hipMalloc(&D.buf, 64 * 6 * 4));
+  FASTMM_HIP(hipMemcpyAsync(D.params, planner().params.data(), kNParams * 4,
+                            hipMemcpyHostToDevice, L.stream));
+  FASTMM_HIP(hipStreamSynchronize(L.stream));
+}
+
+fastmm_plan_t plan_model(Library& L, int64_t M, int64_t N, int64_t K) {
+  ModelDev& D = model_dev();
+  const auto cand = candidates(M, N, K);
+  const int n = (int)cand.size();
+  std::vector<float> X((size_t)n * 5), y(n);
+  for (int i = 0; i < n; ++i) features(M, N, K, cand[i].first, cand[i].second, &X[(size_t)i * 5]);
+  float* dX = D.buf;
+  float* dy = D.buf + 64 * 5;
+  FASTMM_HIP(hipMemcpyAsync(dX, X.data(), X.size() * 4, hipMemcpyHostToDevice, L.stream));
+  mlp_forward(n, D.params, dX, dy, nullptr, L.stream);
+  FASTMM_HIP(hipMemcpyAsync(y.data(), dy, n * 4, hipMemcpyDeviceToHost, L.stream));
+  FASTMM_HIP(hipStreamSynchronize(L.stream));
+  int bi = 0;
+  for (int i = 1; i < n; ++i)
+    if (y[i] < y[bi]) bi = i;
+  return make_plan(cand[bi].first, cand[bi].second, std::exp2((double)y[bi]), FASTMM_PLAN_MODEL);
+}
+
+}  // namespace
+
+int64_t default_leaf() { return kDefaultLeaf; }
 
 int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out) {
-  (void)L;
-  (void)mode;
-  out->depth = 16;
-  out->leaf = default_leaf();
-  out->tile = kTile128x128;
-  out->workspace_bytes = 0;
-  out->predicted_ms = -1.0;
-  out->source = FASTMM_PLAN_DEFAULT;
-  out->depth = effective_depth(M, N, K, 16, out->leaf);
+  if (mode < FASTMM_PLAN_DEFAULT || mode > FASTMM_PLAN_EXHAUSTIVE)
+    throw Error(kInvalidValue, "unknown planner mode");
+  if (M <= 0 || N <= 0 || K <= 0) {
+    *out = make_plan(0, kTile128x128, -1.0, FASTMM_PLAN_DEFAULT);
+    return kSuccess;
+  }
+  if (mode == FASTMM_PLAN_DEFAULT) {
+    *out = make_plan(effective_depth(M, N, K, 16, kDefaultLeaf), kTile128x128, -1.0,
+                     FASTMM_PLAN_DEFAULT);
+    out->leaf = kDefaultLeaf;
+    return kSuccess;
+  }
+  ensure_init(L);
+  Planner& P = planner();
+  if (mode == FASTMM_PLAN_MODEL && P.trained) {
+    *out = plan_model(L, M, N, K);
+    return kSuccess;
+  }
+  auto key = std::make_tuple(M, N, K, (int)FASTMM_PLAN_EXHAUSTIVE);
+  auto it = P.cache.find(key);
+  if (it == P.cache.end()) it = P.cache.emplace(key, tune_exhaustive(L, M, N, K)).first;
+  *out = it->second;
   return kSuccess;
 }
 
+namespace {
+
+void train(Library& L, int epochs, int batch, float lr, uint64_t seed, float* loss_out) {
+  Planner& P = planner();
+  if (P.db.empty()) throw Error(kInvalidValue, "timing database is empty");
+  if (epochs < 1 || batch < 1) throw Error(kInvalidValue, "epochs and batch must be positive");
+  ensure_init(L);
+  const int n = (int)P.db.size();
+  batch = std::min(batch, n);
+  std::vector<float> X((size_t)n * 5), t(n);
+  double tmean = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const Record& r = P.db[i];
+    features(r.M, r.N, r.K, r.depth, r.tile, &X[(size_t)i * 5]);
+    t[i] = (float)std::log2(std::max(r.ms, 1e-4));
+    tmean += t[i];
+  }
+  tmean /= n;
+  // He-uniform initialisation from the seeded stream; last bias = mean target.
+  std::vector<float> p(kNParams, 0.f);
+  uint64_t s = seed;
+  auto init = [&](int off, int fan_in, int count) {
+    const double a = std::sqrt(6.0 / fan_in);
+    for (int i = 0; i < count; ++i) p[off + i] = (float)((2.0 * uniform01(s) - 1.0) * a);
+  };
+  init(0, 5, 5 * 64);
+  init(5 * 64 + 64, 64, 64 * 64);
+  init(5 * 64 + 64 + 64 * 64 + 64, 64, 64);
+  p[kNParams - 1] = (float)tmean;
+
+  float *dp = nullptr, *dm = nullptr, *dv = nullptr, *dg = nullptr, *dX = nullptr, *dt = nullptr,
+        *dscr = nullptr, *dloss = nullptr, *hbuf = nullptr;
+  auto release = [&] {
+    for (float* q : {dp, dm, dv, dg, dX, dt, dscr, dloss}) (void)hipFree(q);
+    if (hbuf) (void)hipHostFree(hbuf);
+  };
+  try {
+    FASTMM_HIP(hipMalloc(&dp, kNParams * 4));
+    FASTMM_HIP(hipMalloc(&dm, kNParams * 4));
+    FASTMM_HIP(hipMalloc(&dv, kNParams * 4));
+    FASTMM_HIP(hipMalloc(&dg, kNParams * 4));
+    FASTMM_HIP(hipMalloc(&dX, (size_t)n * 5 * 4));
+    FASTMM_HIP(hipMalloc(&dt, (size_t)n * 4));
+    FASTMM_HIP(hipMalloc(&dscr, mlp_scratch_floats(n) * 4));
+    FASTMM_HIP(hipMalloc(&dloss, 4));
+    FASTMM_HIP(hipHostMalloc((void**)&hbuf, (size_t)2 * batch * 6 * 4, hipHostMallocDefault));
+    FASTMM_HIP(hipMemcpyAsync(dp, p.data(), kNParams * 4, hipMemcpyHostToDevice, L.stream));
+    FASTMM_HIP(hipMemsetAsync(dm, 0, kNParams * 4, L.stream));
+    FASTMM_HIP(hipMemsetAsync(dv, 0, kNParams * 4, L.stream));
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    int step = 0;
+    for (int e = 0; e < epochs; ++e) {
+      for (int i = n - 1; i > 0; --i) {  // Fisher-Yates with the seeded stream
+        const int j = (int)(splitmix64(s) % (uint64_t)(i + 1));
+        std::swap(order[i], order[j]);
+      }
+      for (int b0 = 0; b0 + batch <= n; b0 += batch) {
+        // Alternate two pinned halves so a copy in flight is never rewritten.
+        float* hx = hbuf + (size_t)(step & 1) * batch * 6;
+        float* ht = hx + (size_t)batch * 5;
+        FASTMM_HIP(hipStreamSynchronize(L.stream));
+        for (int k = 0; k < batch; ++k) {
+          std::memcpy(hx + (size_t)k * 5, &X[(size_t)order[b0 + k] * 5], 5 * 4);
+          ht[k] = t[order[b0 + k]];
+        }
+        FASTMM_HIP(hipMemcpyAsync(dX, hx, (size_t)batch * 5 * 4, hipMemcpyHostToDevice, L.stream));
+        FASTMM_HIP(hipMemcpyAsync(dt, ht, (size_t)batch * 4, hipMemcpyHostToDevice, L.stream));
+        mlp_backward(batch, dp, dX, dt, dg, nullptr, dscr, L.stream);
+        mlp_adam(dg, dp, dm, dv, ++step, lr, 0.9f, 0.999f, 1e-8f, L.stream);
+      }
+    }
+    // Full-data loss of the trained model.
+    FASTMM_HIP(hipMemcpyAsync(dX, X.data(), (size_t)n * 5 * 4, hipMemcpyHostToDevice, L.stream));
+    FASTMM_HIP(hipMemcpyAsync(dt, t.data(), (size_t)n * 4, hipMemcpyHostToDevice, L.stream));
+    mlp_backward(n, dp, dX, dt, dg, dloss, dscr, L.stream);
+    float loss = 0.f;
+    FASTMM_HIP(hipMemcpyAsync(&loss, dloss, 4, hipMemcpyDeviceToHost, L.stream));
+    FASTMM_HIP(hipMemcpyAsync(p.data(), dp, kNParams * 4, hipMemcpyDeviceToHost, L.stream));
+    FASTMM_HIP(hipStreamSynchronize(L.stream));
+    if (loss_out) *loss_out = loss;
+  } catch (...) {
+    release();
+    throw;
+  }
+  release();
+  P.params = p;
+  P.trained = true;
+  upload_model(L);
+}
+
+// Timing database: a flat JSON list of records.
+void save_db(const char* path) {
+  FILE* f = std::fopen(path, "w");
+  if (!f) throw Error(kInvalidValue, std::string("cannot write ") + path);
+  std::fprintf(f, "{\"device\": \"gfx950\", \"records\": [\n");
+  const auto& db = planner().db;
+  for (size_t i = 0; i < db.size(); ++i)
+    std::fprintf(f, "  {\"M\": %lld, \"N\": %lld, \"K\": %lld, \"depth\": %d, \"tile\": %d, \"ms\": %.6f}%s\n",
+                 (long long)db[i].M, (long long)db[i].N, (long long)db[i].K, db[i].depth,
+                 db[i].tile, db[i].ms, i + 1 < db.size() ? "," : "");
+  std::fprintf(f, "]}\n");
+  std::fclose(f);
+}
+
+void load_db(const char* path) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) throw Error(kInvalidValue, std::string("cannot read ") + path);
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  std::vector<Record> recs;
+  size_t pos = 0;
+  while ((pos = text.find("{\"M\":", pos)) != std::string::npos) {
+    long long M, N, K;
+    int d, t;
+    double ms;
+    if (std::sscanf(text.c_str() + pos,
+                    "{\"M\": %lld, \"N\": %lld, \"K\": %lld, \"depth\": %d, \"tile\": %d, \"ms\": %lf}",
+                    &M, &N, &K, &d, &t, &ms) != 6 ||
+        M <= 0 || N <= 0 || K <= 0 || d < 0 || d > 16 || t < 0 || t >= kNumTiles || !(ms > 0))
+      throw Error(kInvalidValue, std::string("malformed timing record in ") + path);
+    recs.push_back({M, N, K, d, t, ms});
+    pos += 5;
+  }
+  auto& db = planner().db;
+  db.insert(db.end(), recs.begin(), recs.end());
+}
+
+}  // namespace
+
 }  // namespace fastmm
+
+using namespace fastmm;
+
+extern "C" {
+
+int fastmm_plan(int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  return run_guarded([&] {
+    if (!out) throw Error(kInvalidValue, "out is NULL");
+    if (M < 0 || N < 0 || K < 0) throw Error(kInvalidValue, "negative dimension");
+    const int rc = plan_choose(L, M, N, K, mode, out);
+    if (rc != kSuccess) throw Error(rc, "planner failed");
+  });
+}
+
+int fastmm_set_plan_mode(int mode) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  return run_guarded([&] {
+    if (mode < FASTMM_PLAN_DEFAULT || mode > FASTMM_PLAN_EXHAUSTIVE)
+      throw Error(kInvalidValue, "unknown planner mode");
+    L.plan_mode = mode;
+  });
+}
+
+int fastmm_planner_load(const char* db_path, const char* model_path) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  return run_guarded([&] {
+    if (db_path) load_db(db_path);
+    if (model_path) {
+      FILE* f = std::fopen(model_path, "rb");
+      if (!f) throw Error(kInvalidValue, std::string("cannot read ") + model_path);
+      std::vector<float> p(kNParams);
+      const size_t got = std::fread(p.data(), 4, kNParams, f);
+      const bool extra = std::fgetc(f) != EOF;
+      std::fclose(f);
+      if (got != (size_t)kNParams || extra)
+        throw Error(kInvalidValue, std::string("model file has the wrong size: ") + model_path);
+      for (float x : p)
+        if (!std::isfinite(x)) throw Error(kInvalidValue, "model file holds non-finite values");
+      ensure_init(L);
+      planner().params = p;
+      planner().trained = true;
+      upload_model(L);
+    }
+  });
+}
+
+int fastmm_planner_save(const char* db_path, const char* model_path) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  return run_guarded([&] {
+    if (db_path) save_db(db_path);
+    if (model_path) {
+      if (!planner().trained) throw Error(kInvalidValue, "no trained model to save");
+      FILE* f = std::fopen(model_path, "wb");
+      if (!f) throw Error(kInvalidValue, std::string("cannot write ") + model_path);
+      std::fwrite(planner().params.data(), 4, kNParams, f);
+      std::fclose(f);
+    }
+  });
+}
+
+int fastmm_planner_train(int epochs, int batch, float lr, uint64_t seed, float* loss) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  return run_guarded([&] { train(L, epochs, batch, lr, seed, loss); });
+}
+
+int64_t fastmm_planner_records(void) {
+  Library& L = lib();
+  std::lock_guard<std::mutex> g(L.mu);
+  return (int64_t)planner().db.size();
+}
+
+}  // extern "C"

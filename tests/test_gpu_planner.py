@@ -1,0 +1,135 @@
+"""The learned planner: GPU network kernels against the FP64 oracle, the
+exhaustive autotuner, and the trained model judged by its regret against
+exhaustive timing and by what it gains over the fixed rule."""
+import numpy as np
+import pytest
+
+import synthgen
+from oracle import classic, checks, mlp
+from tests.gpu_util import dev, host, say, uniform
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(seed=901, batch=33):
+    flat = synthgen.uniform_pm1_np(seed, 1, mlp.N_PARAMS)[0] * np.float32(0.3)
+    X = synthgen.uniform_pm1_np(seed + 1, batch, mlp.D_IN)
+    t = synthgen.uniform_pm1_np(seed + 2, 1, batch)[0]
+    return flat.astype(np.float32), X, t
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@pytest.mark.parametrize("batch", [1, 33, 256])
+def test_mlp_forward_backward_match_oracle(fastmm, batch):
+    import torch
+    flat, X, t = _case(batch=batch)
+    y_ref, cache = mlp.forward(flat.astype(np.float64), X.astype(np.float64))
+    g_ref = mlp.backward(flat.astype(np.float64), cache, y_ref, t.astype(np.float64))
+    loss_ref = mlp.loss(y_ref, t)
+    dp, dX, dt = dev(flat), dev(X), dev(t)
+    y = torch.empty(batch, device="cuda")
+    fastmm.mlp_forward(batch, dp, dX, y)
+    assert rel(host(y), y_ref) < 1e-5
+    g = torch.empty(mlp.N_PARAMS, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    fastmm.mlp_backward(batch, dp, dX, dt, g, loss)
+    gh = host(g).astype(np.float64)
+    # per tensor (W1, b1, W2, b2, W3, b3)
+    o = 0
+    for name, shape in mlp.SHAPES:
+        size = int(np.prod(shape))
+        e = rel(gh[o:o + size], g_ref[o:o + size])
+        say(f"  batch={batch} grad {name}: rel={e:.2e}")
+        assert e < 1e-4, name
+        o += size
+    assert abs(float(host(loss)[0]) - loss_ref) <= 1e-5 * max(1.0, loss_ref)
+
+
+def test_mlp_adam_matches_oracle(fastmm):
+    import torch
+    flat, X, t = _case(seed=911)
+    g = synthgen.uniform_pm1_np(912, 1, mlp.N_PARAMS)[0]
+    m = synthgen.uniform_pm1_np(913, 1, mlp.N_PARAMS)[0] * np.float32(0.1)
+    v = np.abs(synthgen.uniform_pm1_np(914, 1, mlp.N_PARAMS)[0]) * np.float32(0.01)
+    p_ref, m_ref, v_ref = mlp.adam_step(flat.astype(np.float64), g.astype(np.float64),
+                                        m.astype(np.float64), v.astype(np.float64), 3, 1e-3)
+    dp, dm, dv = dev(flat), dev(m), dev(v)
+    fastmm.mlp_adam(dev(g), dp, dm, dv, 3, 1e-3)
+    assert rel(host(dm), m_ref) < 1e-6
+    assert rel(host(dv), v_ref) < 1e-6
+    assert np.max(np.abs(host(dp) - p_ref)) < 1e-6
+
+
+def test_default_rule(fastmm):
+    p = fastmm.plan(19456, 19456, 19456, fastmm.PLAN_DEFAULT)
+    assert (p.depth, p.tile, p.source) == (4, 0, fastmm.PLAN_DEFAULT)
+    p = fastmm.plan(512, 512, 512, fastmm.PLAN_DEFAULT)
+    assert p.depth == 0
+
+
+def test_exhaustive_model_regret_and_gain(fastmm, tmp_path):
+    train_shapes = synthgen.shapes_loguniform(4001, 40)
+    eval_shapes = synthgen.shapes_loguniform(3001, 12)
+    for (M, N, K) in train_shapes:
+        fastmm.plan(int(M), int(N), int(K), fastmm.PLAN_EXHAUSTIVE)
+    n_train = fastmm.planner_records()
+    say(f"training records: {n_train}")
+    assert n_train >= 40 * 4
+    loss = fastmm.planner_train(epochs=400, batch=64, lr=3e-3, seed=4001)
+    say(f"trained, loss={loss:.4f}")
+    assert np.isfinite(loss) and loss < 0.5
+    db = tmp_path / "db.json"
+    model = tmp_path / "model.bin"
+    fastmm.planner_save(str(db), str(model))
+    # Evaluate on held-out shapes: exhaustive timing gives the table.
+    regrets_model, regrets_default, gains = [], [], []
+    import json
+    for (M, N, K) in eval_shapes:
+        M, N, K = int(M), int(N), int(K)
+        best = fastmm.plan(M, N, K, fastmm.PLAN_EXHAUSTIVE)
+        fastmm.planner_save(str(db), None)
+        recs = [r for r in json.load(open(db))["records"] if (r["M"], r["N"], r["K"]) == (M, N, K)]
+        table = {(r["depth"], r["tile"]): r["ms"] for r in recs}
+        pm = fastmm.plan(M, N, K, fastmm.PLAN_MODEL)
+        pd = fastmm.plan(M, N, K, fastmm.PLAN_DEFAULT)
+        assert pm.source == fastmm.PLAN_MODEL
+        t_best = table[(best.depth, best.tile)]
+        t_model = table[(pm.depth, pm.tile)]
+        t_default = table[(pd.depth, pd.tile)]
+        regrets_model.append(t_model / t_best - 1)
+        regrets_default.append(t_default / t_best - 1)
+        gains.append(t_default / t_model)
+        say(f"  {M}x{N}x{K}: best d{best.depth}t{best.tile} {t_best:.3f} ms, model d{pm.depth}t{pm.tile} "
+            f"{t_model:.3f}, default d{pd.depth}t{pd.tile} {t_default:.3f}")
+    rm, rd = float(np.mean(regrets_model)), float(np.mean(regrets_default))
+    gain = float(np.exp(np.mean(np.log(gains))))
+    say(f"mean regret model={rm:.3f} default={rd:.3f}; geo-mean gain over default={gain:.3f}")
+    assert rm <= 0.15
+    assert gain >= 0.97
+
+
+def test_auto_depth_product_is_correct(fastmm):
+    n = 1536
+    A = uniform(921, n, n)
+    B = uniform(922, n, n)
+    import torch
+    C = torch.empty((n, n), device="cuda")
+    fastmm.set_plan_mode(fastmm.PLAN_DEFAULT)
+    fastmm.gemm(n, n, n, dev(A), dev(B), C, depth=fastmm.AUTO)
+    assert fastmm.get_stats()["depth"] == 0  # 1536 / 2 = 768 < 1024
+    assert checks.rel_frob(host(C), classic.gemm(A, B)) < 1e-4
+
+
+def test_model_file_errors(fastmm, tmp_path):
+    bad = tmp_path / "short.bin"
+    bad.write_bytes(b"\0" * 100)
+    with pytest.raises(fastmm.FastmmError) as e:
+        fastmm.planner_load(None, str(bad))
+    assert e.value.code == fastmm.ERROR_INVALID_VALUE
+    nan = tmp_path / "nan.bin"
+    nan.write_bytes(np.full(mlp.N_PARAMS, np.nan, np.float32).tobytes())
+    with pytest.raises(fastmm.FastmmError):
+        fastmm.planner_load(None, str(nan))
