@@ -91,6 +91,7 @@ typedef struct {
    * milliseconds; -1 when profiling is off (fastmm_set_profiling). */
   double h2d_ms, preadd_ms, leaf_ms, postadd_ms, d2h_ms, total_ms;
   int leaf_launches;       /* grouped leaf launches leaf_ms is summed over */
+  int graph_replayed;      /* batched: 1 if a cached HIP graph was replayed */
 } fastmm_stats_t;
 
 /* C = A*B.  M, N, K >= 0.  lda >= max(1,K), ldb >= max(1,N), ldc >= max(1,N).

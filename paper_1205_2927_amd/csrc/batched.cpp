@@ -1,9 +1,22 @@
-// Batched products: many independent C_i = A_i B_i in one level-wise
-// schedule (one grouped launch per level and per leaf tile shape).
+// Batched products: many independent C_i = A_i B_i of uneven extents, each
+// with its own plan, in one level-wise schedule -- one grouped launch per
+// recursion level and per leaf tile shape for the whole batch -- captured
+// once into a HIP graph and replayed.
+//
+// What a replay needs to change between calls is only data: the operand
+// pointers live in the descriptor arrays, which are copied to the device
+// (outside the graph) before every replay.  The kernels' own arguments (the
+// device addresses of those arrays, counts, grid sizes, vector-path flags)
+// are the graph's key: a call whose launches would have exactly these
+// arguments replays the graph, anything else captures a new one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "engine.h"
@@ -12,6 +25,73 @@ namespace fastmm {
 namespace {
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct GraphCache {
+  std::map<std::string, hipGraphExec_t> execs;
+  int64_t captures = 0, replays = 0;
+};
+
+GraphCache& graphs() {
+  static GraphCache G;
+  return G;
+}
+
+// Kernel arguments of every launch the schedule issues, in order.
+std::string signature(const Schedule& s) {
+  std::ostringstream o;
+  auto blocks_pre = [](const std::vector<PreAddNode>& v) {
+    return v.empty() ? 0 : v.back().block_begin + (int)add_blocks_for(v.back().h_r, v.back().h_c);
+  };
+  auto blocks_post = [](const std::vector<PostAddNode>& v) {
+    return v.empty() ? 0 : v.back().block_begin + (int)add_blocks_for(v.back().h_r, v.back().h_c);
+  };
+  for (int l = 0; l < s.max_depth; ++l)
+    o << "a" << (const void*)s.d_preA[l] << ',' << s.preA[l].size() << ',' << blocks_pre(s.preA[l])
+      << ',' << (int)s.vec_preA[l] << "b" << (const void*)s.d_preB[l] << ',' << s.preB[l].size()
+      << ',' << blocks_pre(s.preB[l]) << ',' << (int)s.vec_preB[l] << ';';
+  for (int t = 0; t < kNumTiles; ++t)
+    o << "g" << t << (const void*)s.d_leaf[t] << ',' << s.leaf[t].size() << ','
+      << s.leaf_tiles_total[t] << ',' << (int)s.vec_leaf[t] << ';';
+  for (int l = s.max_depth - 1; l >= 0; --l)
+    o << "p" << (const void*)s.d_post[l] << ',' << s.post[l].size() << ',' << blocks_post(s.post[l])
+      << ',' << (int)s.vec_post[l] << ';';
+  return o.str();
+}
+
+// Launch the schedule through a (possibly new) graph on L.stream.
+int launch_graphed(Library& L, Schedule& s, bool& replayed) {
+  GraphCache& G = graphs();
+  const std::string key = signature(s);
+  auto it = G.execs.find(key);
+  replayed = it != G.execs.end();
+  if (!replayed) {
+    hipGraph_t graph = nullptr;
+    FASTMM_HIP(hipStreamBeginCapture(L.stream, hipStreamCaptureModeRelaxed));
+    try {
+      launch_schedule(L, s, nullptr, nullptr, false);
+    } catch (...) {
+      hipGraph_t g2 = nullptr;
+      (void)hipStreamEndCapture(L.stream, &g2);
+      if (g2) (void)hipGraphDestroy(g2);
+      throw;
+    }
+    FASTMM_HIP(hipStreamEndCapture(L.stream, &graph));
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    FASTMM_HIP(e);
+    if (G.execs.size() >= 32) {  // bound the cache
+      (void)hipGraphExecDestroy(G.execs.begin()->second);
+      G.execs.erase(G.execs.begin());
+    }
+    it = G.execs.emplace(key, exec).first;
+    ++G.captures;
+  } else {
+    ++G.replays;
+  }
+  FASTMM_HIP(hipGraphLaunch(it->second, L.stream));
+  return s.launches;
+}
 
 void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const int64_t* K,
                 const float* const* A, const int64_t* lda, const float* const* B,
@@ -127,10 +207,18 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
   for (auto& p : probs)
     if (p.K > 0) work.push_back(p);
   int launches = 0;
+  bool replayed = false;
+  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[5], sm));
   if (!work.empty()) {
     build_schedule(work, ws + stage_bytes, s);
-    launches = enqueue_schedule(L, s, ws + stage_bytes + temp_bytes, desc_host);
+    upload_schedule(L, s, ws + stage_bytes + temp_bytes, desc_host);
+    const char* g = std::getenv("FASTMM_GRAPH");
+    if (g && g[0] == '0')
+      launches = launch_schedule(L, s, nullptr, nullptr, false);
+    else
+      launches = launch_graphed(L, s, replayed);
   }
+  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[6], sm));
   if (!on_dev) {
     for (size_t j = 0; j < probs.size(); ++j) {
       const Problem& p = probs[j];
@@ -148,10 +236,27 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
   st.add_bytes = s.add_bytes;
   st.launches = launches;
   st.workspace_bytes = L.arena_bytes;
+  st.leaf_launches = 0;
+  for (int t = 0; t < kNumTiles; ++t) st.leaf_launches += s.leaf_tiles_total[t] > 0 ? 1 : 0;
+  if (L.profiling && !work.empty()) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, L.ev[5], L.ev[6]) == hipSuccess) st.total_ms = ms;
+    else (void)hipGetLastError();
+  }
+  st.graph_replayed = replayed ? 1 : 0;
   L.stats = st;
 }
 
 }  // namespace
+
+void destroy_graphs() {
+  for (auto& kv : graphs().execs) (void)hipGraphExecDestroy(kv.second);
+  graphs().execs.clear();
+}
+
+int64_t graph_captures() { return graphs().captures; }
+int64_t graph_replays() { return graphs().replays; }
+
 }  // namespace fastmm
 
 using namespace fastmm;

@@ -117,6 +117,7 @@ char* ensure_arena(Library& L, size_t bytes) {
   }
   L.arena = static_cast<char*>(p);
   L.arena_bytes = want;
+  ++L.arena_generation;
   if (poison && poison[0] == '1') FASTMM_HIP(hipMemsetAsync(L.arena, 0xFF, L.arena_bytes, L.stream));
   return L.arena;
 }
@@ -364,8 +365,7 @@ int add_total_blocks(const std::vector<PostAddNode>& v) {
 }
 }  // namespace
 
-int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host,
-                     hipEvent_t leaf_begin, hipEvent_t leaf_end) {
+void upload_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host) {
   // Pack every descriptor array into one host block, upload it once.
   size_t off = 0;
   auto put = [&](const void* src, size_t bytes) {
@@ -374,43 +374,52 @@ int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host,
     off += align_up(bytes, 256);
     return dev;
   };
-  std::vector<const PreAddNode*> dA(s.max_depth), dB(s.max_depth);
-  std::vector<const PostAddNode*> dP(s.max_depth);
-  const GemmDesc* dL[kNumTiles] = {};
+  s.d_preA.assign(s.max_depth, nullptr);
+  s.d_preB.assign(s.max_depth, nullptr);
+  s.d_post.assign(s.max_depth, nullptr);
   for (int l = 0; l < s.max_depth; ++l) {
-    dA[l] = reinterpret_cast<const PreAddNode*>(put(s.preA[l].data(), s.preA[l].size() * sizeof(PreAddNode)));
-    dB[l] = reinterpret_cast<const PreAddNode*>(put(s.preB[l].data(), s.preB[l].size() * sizeof(PreAddNode)));
-    dP[l] = reinterpret_cast<const PostAddNode*>(put(s.post[l].data(), s.post[l].size() * sizeof(PostAddNode)));
+    s.d_preA[l] = reinterpret_cast<const PreAddNode*>(put(s.preA[l].data(), s.preA[l].size() * sizeof(PreAddNode)));
+    s.d_preB[l] = reinterpret_cast<const PreAddNode*>(put(s.preB[l].data(), s.preB[l].size() * sizeof(PreAddNode)));
+    s.d_post[l] = reinterpret_cast<const PostAddNode*>(put(s.post[l].data(), s.post[l].size() * sizeof(PostAddNode)));
   }
   for (int t = 0; t < kNumTiles; ++t)
-    dL[t] = reinterpret_cast<const GemmDesc*>(put(s.leaf[t].data(), s.leaf[t].size() * sizeof(GemmDesc)));
+    s.d_leaf[t] = reinterpret_cast<const GemmDesc*>(put(s.leaf[t].data(), s.leaf[t].size() * sizeof(GemmDesc)));
   if (off) FASTMM_HIP(hipMemcpyAsync(desc_dev, desc_host, off, hipMemcpyHostToDevice, L.stream));
+}
 
+int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t leaf_end,
+                    bool profile) {
   int launches = 0;
-  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[1], L.stream));
+  if (profile) FASTMM_HIP(hipEventRecord(L.ev[1], L.stream));
   for (int l = 0; l < s.max_depth; ++l) {
     const int ba = add_total_blocks(s.preA[l]);
     const int bb = add_total_blocks(s.preB[l]);
-    if (ba) { launch_preadd(0, dA[l], (int)s.preA[l].size(), ba, s.vec_preA[l], L.stream); ++launches; }
-    if (bb) { launch_preadd(1, dB[l], (int)s.preB[l].size(), bb, s.vec_preB[l], L.stream); ++launches; }
+    if (ba) { launch_preadd(0, s.d_preA[l], (int)s.preA[l].size(), ba, s.vec_preA[l], L.stream); ++launches; }
+    if (bb) { launch_preadd(1, s.d_preB[l], (int)s.preB[l].size(), bb, s.vec_preB[l], L.stream); ++launches; }
   }
-  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[2], L.stream));
+  if (profile) FASTMM_HIP(hipEventRecord(L.ev[2], L.stream));
   if (leaf_begin) FASTMM_HIP(hipEventRecord(leaf_begin, L.stream));
   for (int t = 0; t < kNumTiles; ++t) {
     if (s.leaf_tiles_total[t] > 0) {
-      launch_leaf_gemm(t, dL[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t], L.stream);
+      launch_leaf_gemm(t, s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t], L.stream);
       ++launches;
     }
   }
   if (leaf_end) FASTMM_HIP(hipEventRecord(leaf_end, L.stream));
-  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[3], L.stream));
+  if (profile) FASTMM_HIP(hipEventRecord(L.ev[3], L.stream));
   for (int l = s.max_depth - 1; l >= 0; --l) {
     const int bp = add_total_blocks(s.post[l]);
-    if (bp) { launch_postadd(dP[l], (int)s.post[l].size(), bp, s.vec_post[l], L.stream); ++launches; }
+    if (bp) { launch_postadd(s.d_post[l], (int)s.post[l].size(), bp, s.vec_post[l], L.stream); ++launches; }
   }
-  if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[4], L.stream));
+  if (profile) FASTMM_HIP(hipEventRecord(L.ev[4], L.stream));
   s.launches = launches;
   return launches;
+}
+
+int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host,
+                     hipEvent_t leaf_begin, hipEvent_t leaf_end) {
+  upload_schedule(L, s, desc_dev, desc_host);
+  return launch_schedule(L, s, leaf_begin, leaf_end, L.profiling);
 }
 
 // ---------------------------------------------------------------------------
@@ -754,6 +763,7 @@ void fastmm_finalize(void) {
   std::lock_guard<std::mutex> g(L.mu);
   if (!L.initialised) return;
   (void)hipStreamSynchronize(L.stream);
+  destroy_graphs();
   if (L.arena) (void)hipFree(L.arena);
   if (L.pinned) (void)hipHostFree(L.pinned);
   for (auto& e : L.ev)

@@ -62,6 +62,10 @@ struct Schedule {
   std::vector<GemmDesc> leaf[kNumTiles];
   std::vector<int> leaf_tiles_total;                // per tile id
   std::vector<char> vec_preA, vec_preB, vec_post;   // per level
+  // Device addresses of the uploaded descriptor arrays (upload_schedule).
+  std::vector<const PreAddNode*> d_preA, d_preB;
+  std::vector<const PostAddNode*> d_post;
+  const GemmDesc* d_leaf[kNumTiles] = {};
   bool vec_leaf[kNumTiles] = {true, true, true, true};
   int max_depth = 0;
   size_t temp_bytes = 0;  // bytes of S, T and P temporaries
@@ -103,6 +107,7 @@ struct Library {
   fastmm_stats_t stats{};
   size_t limit = 0;              // workspace cap (0: none)
   int plan_mode = FASTMM_PLAN_DEFAULT;
+  uint64_t arena_generation = 0;  // bumped whenever the workspace moves
 };
 
 Library& lib();
@@ -115,6 +120,12 @@ char* ensure_pinned(Library& L, size_t bytes);
 // pre-additions, leaves and post-additions when profiling is on.
 int enqueue_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host,
                      hipEvent_t leaf_begin = nullptr, hipEvent_t leaf_end = nullptr);
+// The two halves of enqueue_schedule: copy the descriptor arrays to the
+// device (stream-ordered), then issue the launches.  Only the launches are
+// captured into a graph by the batched path.
+void upload_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host);
+int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t leaf_end,
+                    bool profile);
 size_t schedule_desc_bytes(const Schedule& s);
 
 // Host-resident operands: stage quadrants in, run the top level of the
@@ -128,6 +139,11 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
 void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
                int tile);
+
+// Batched path's graph cache (batched.cpp).
+void destroy_graphs();
+int64_t graph_captures();
+int64_t graph_replays();
 
 // Planner hooks (planner.cpp).
 int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out);

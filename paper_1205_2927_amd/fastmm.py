@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t), ("h2d_ms", ctypes.c_double),
                 ("preadd_ms", ctypes.c_double), ("leaf_ms", ctypes.c_double),
                 ("postadd_ms", ctypes.c_double), ("d2h_ms", ctypes.c_double),
-                ("total_ms", ctypes.c_double), ("leaf_launches", ctypes.c_int)]
+                ("total_ms", ctypes.c_double), ("leaf_launches", ctypes.c_int),
+                ("graph_replayed", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
