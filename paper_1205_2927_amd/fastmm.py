@@ -205,6 +205,21 @@ def gemm_batched(As, Bs, Cs, depth=None, leaf=None, check=True):
     return rc
 
 
+def gemm_batched_raw(M, N, K, A, lda, B, ldb, C, ldc, depth=None, leaf=None) -> int:
+    """fastmm_gemm_batched on plain lists of extents, addresses and leading
+    dimensions; returns the status without raising (for error-path tests)."""
+    lib = load()
+    n = len(M)
+    I64 = ctypes.c_int64 * n
+    VP = ctypes.c_void_p * n
+    dep = (ctypes.c_int * n)(*depth) if depth is not None else None
+    lf = I64(*leaf) if leaf is not None else None
+    return lib.fastmm_gemm_batched(n, I64(*M), I64(*N), I64(*K), VP(*A), I64(*lda), VP(*B),
+                                   I64(*ldb), VP(*C), I64(*ldc),
+                                   ctypes.cast(dep, ctypes.c_void_p) if dep is not None else None,
+                                   ctypes.cast(lf, ctypes.c_void_p) if lf is not None else None)
+
+
 def plan(M, N, K, mode=PLAN_DEFAULT) -> Plan:
     p = Plan()
     _check(load().fastmm_plan(M, N, K, mode, ctypes.byref(p)))

@@ -92,10 +92,16 @@ def test_batched_validation_is_atomic(fastmm):
     shapes = SHAPES[:3]
     As, Bs = _make(shapes, 2100)
     Cs = [torch.full((m, n), 5.0, device="cuda") for (m, k, n, d) in shapes]
-    bad_B = list(Bs)
-    bad_B[2] = torch.zeros((3, 3), device="cuda")  # wrong inner extent -> bad ldb
-    rc = fastmm.gemm_batched(As, bad_B, Cs, depth=[1, 1, 1], leaf=[1, 1, 1], check=False)
-    assert rc != fastmm.SUCCESS
+    M = [m for (m, k, n, d) in shapes]
+    K = [k for (m, k, n, d) in shapes]
+    N = [n for (m, k, n, d) in shapes]
+    ldb = list(N)
+    ldb[2] = N[2] - 1  # invalid: ldb < N for the last problem only
+    rc = fastmm.gemm_batched_raw(M, N, K, [a.data_ptr() for a in As], K,
+                                 [b.data_ptr() for b in Bs], ldb, [c.data_ptr() for c in Cs], N,
+                                 depth=[1, 1, 1], leaf=[1, 1, 1])
+    assert rc == fastmm.ERROR_INVALID_VALUE
+    assert "problem 2" in fastmm.last_error()
     for C in Cs:
         assert torch.all(C == 5.0).item()
 
