@@ -1,0 +1,59 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times: operands in pinned host memory (transfers inside the call), square
+n = 19456 and the rectangular 19456 x 16384 x 12288 product.  The oracle
+cannot afford the full product on every run, so it checks seeded sampled rows
+exactly (FP64-accumulated) and Freivalds' probe C x = A (B x)."""
+import numpy as np
+import pytest
+
+import synthgen
+from oracle import checks
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _pinned(shape):
+    import torch
+    return torch.empty(shape, dtype=torch.float32, pin_memory=True)
+
+
+def _check(fastmm, M, N, K, depth, leaf, seed_a, seed_b, rows=24):
+    A = _pinned((M, K))
+    B = _pinned((K, N))
+    C = _pinned((M, N))
+    synthgen.fill_uniform_pm1(seed_a, M, K, A.data_ptr())
+    synthgen.fill_uniform_pm1(seed_b, K, N, B.data_ptr())
+    C.fill_(float("nan"))
+    say(f"full size {M}x{K}x{N} depth={depth} leaf={leaf}")
+    fastmm.gemm(M, N, K, A, B, C, depth=depth, leaf=leaf, tile=0)
+    st = fastmm.get_stats()
+    An, Bn, Cn = A.numpy(), B.numpy(), C.numpy()
+    assert np.isfinite(Cn).all()
+    r = synthgen.row_sample(seed_a + 7, M, rows)
+    e_rows = checks.sampled_rows_rel(Cn, An, Bn, r)
+    e_fv = checks.freivalds_rel(Cn, An, Bn, synthgen.signs_pm1(seed_b + 7, N))
+    say(f"  depth={st['depth']} sampled-rows rel={e_rows:.3e} freivalds rel={e_fv:.3e}")
+    assert e_rows <= TOL and e_fv <= TOL
+    return st
+
+
+def test_headline_square_19456_depth3_pinned(fastmm):
+    st = _check(fastmm, 19456, 19456, 19456, 3, 1024, 1001 + 3, 2001 + 3)
+    assert st["depth"] == 3 and st["leaves"] == 343
+    assert (st["leaf_m"], st["leaf_k"], st["leaf_n"]) == (2432, 2432, 2432)
+
+
+@pytest.mark.parametrize("depth", [0, 2, 4])
+def test_square_19456_other_depths_pinned(fastmm, depth):
+    st = _check(fastmm, 19456, 19456, 19456, depth, 1024 if depth < 4 else 1, 1001 + 3, 2001 + 3,
+                rows=12)
+    assert st["depth"] == depth
+
+
+@pytest.mark.parametrize("depth,leaf", [(2, 1024), (3, 1024), (4, 768)])
+def test_rectangular_19456x16384x12288_pinned(fastmm, depth, leaf):
+    st = _check(fastmm, 19456, 12288, 16384, depth, leaf, 1001 + 3, 2001 + 3, rows=12)
+    assert st["depth"] == depth
