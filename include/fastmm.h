@@ -65,7 +65,11 @@ enum {
   FASTMM_TILE_128x128 = 0,
   FASTMM_TILE_256x128 = 1,
   FASTMM_TILE_128x64 = 2,
-  FASTMM_TILE_64x64 = 3
+  FASTMM_TILE_64x64 = 3,
+  FASTMM_TILE_128x128_K32 = 4, /* 128x128, K-slabs of 32 */
+  FASTMM_TILE_256x128_W8 = 5,  /* 256x128 on 8 wavefronts */
+  FASTMM_TILE_256x256_W8 = 6,  /* 256x256 on 8 wavefronts */
+  FASTMM_TILE_128x256 = 7
 };
 
 typedef struct {

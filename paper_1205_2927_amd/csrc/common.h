@@ -99,7 +99,11 @@ enum TileId {
   kTile256x128 = 1,
   kTile128x64 = 2,
   kTile64x64 = 3,
-  kNumTiles = 4,
+  kTile128x128k32 = 4,  // K-slab of 32
+  kTile256x128w8 = 5,   // 8 wavefronts
+  kTile256x256w8 = 6,   // 8 wavefronts
+  kTile128x256 = 7,
+  kNumTiles = 8,
 };
 
 struct TileShape {
@@ -112,6 +116,10 @@ inline TileShape tile_shape(int id) {
     case kTile256x128: return {256, 128};
     case kTile128x64: return {128, 64};
     case kTile64x64: return {64, 64};
+    case kTile128x128k32: return {128, 128};
+    case kTile256x128w8: return {256, 128};
+    case kTile256x256w8: return {256, 256};
+    case kTile128x256: return {128, 256};
     default: throw Error(kInvalidValue, "unknown tile id " + std::to_string(id));
   }
 }

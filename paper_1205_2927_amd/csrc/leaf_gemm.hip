@@ -28,7 +28,6 @@ namespace fastmm {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kThreads = 256;  // 4 wavefronts of 64
 
 // Buffer resource over [p, p + bytes).  Both values are the same in every
 // lane; readfirstlane states that, so the resource lives in scalar registers
@@ -51,10 +50,11 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return xcd * q + (xcd < r ? xcd : r) + (bid >> 3);
 }
 
-template <int BM, int BN, int BK, bool VEC>
-__global__ void __launch_bounds__(kThreads)
+template <int BM, int BN, int BK, int WGM, int WGN, bool VEC>
+__global__ void __launch_bounds__(64 * WGM * WGN)
 leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles) {
-  constexpr int WM = BM / 2, WN = BN / 2;   // wave sub-tile
+  constexpr int kThreads = 64 * WGM * WGN;  // WGM x WGN wavefronts of 64
+  constexpr int WM = BM / WGM, WN = BN / WGN;  // wave sub-tile
   constexpr int FM = WM / 32, FN = WN / 32; // 32x32 blocks per wave
   constexpr int LDA = BK + 4;               // LDS row stride of A ([m][k])
   constexpr int LDB = BN + 8;               // LDS row stride of B ([k][n])
@@ -99,8 +99,8 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = (wave >> 1) * WM;
-  const int wn = (wave & 1) * WN;
+  const int wm = (wave / WGN) * WM;
+  const int wn = (wave % WGN) * WN;
   const int lr = lane & 31;
   const int lh = lane >> 5;
 
@@ -247,24 +247,28 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles)
     }
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, int WGM, int WGN>
 static void launch_t(const GemmDesc* d, int ndesc, int total, bool vec, hipStream_t s) {
   if (total <= 0) return;
-  dim3 grid(total), block(kThreads);
+  dim3 grid(total), block(64 * WGM * WGN);
   if (vec)
-    hipLaunchKernelGGL((leaf_gemm_kernel<BM, BN, BK, true>), grid, block, 0, s, d, ndesc, total);
+    hipLaunchKernelGGL((leaf_gemm_kernel<BM, BN, BK, WGM, WGN, true>), grid, block, 0, s, d, ndesc, total);
   else
-    hipLaunchKernelGGL((leaf_gemm_kernel<BM, BN, BK, false>), grid, block, 0, s, d, ndesc, total);
+    hipLaunchKernelGGL((leaf_gemm_kernel<BM, BN, BK, WGM, WGN, false>), grid, block, 0, s, d, ndesc, total);
   FASTMM_HIP(hipGetLastError());
 }
 
 void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
                       hipStream_t stream) {
   switch (tile) {
-    case kTile128x128: launch_t<128, 128, 16>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTile256x128: launch_t<256, 128, 16>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTile128x64: launch_t<128, 64, 16>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTile64x64: launch_t<64, 64, 16>(d_descs, ndesc, total_tiles, vec, stream); break;
+    case kTile128x128: launch_t<128, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
+    case kTile256x128: launch_t<256, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
+    case kTile128x64: launch_t<128, 64, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
+    case kTile64x64: launch_t<64, 64, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
+    case kTile128x128k32: launch_t<128, 128, 32, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
+    case kTile256x128w8: launch_t<256, 128, 16, 4, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
+    case kTile256x256w8: launch_t<256, 256, 16, 2, 4>(d_descs, ndesc, total_tiles, vec, stream); break;
+    case kTile128x256: launch_t<128, 256, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
     default: throw Error(kInvalidValue, "unknown tile id");
   }
 }

@@ -14,7 +14,7 @@
 //               each candidate's log2 run time; the argmin is taken.  With no
 //               trained model it falls back to EXHAUSTIVE.
 // Candidates: depth 0..4 with leaves of at least 128 in every dimension,
-// times the four leaf tiles.  Ties go to the smaller depth, then tile id.
+// times five leaf tiles (64x64 to 256x256).  Ties go to the smaller depth, then tile id.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,6 +48,10 @@ constexpr int kNParams = FASTMM_MLP_PARAMS;
 constexpr int64_t kMinLeaf = 128;   // smallest leaf extent a candidate may reach
 constexpr int kMaxDepth = 4;
 constexpr int64_t kDefaultLeaf = 1024;
+// Tiles the planner considers: one per macro-tile area (the area is the
+// model's tile feature), the best-measured variant of each.
+constexpr int kPlannerTiles[] = {kTile128x128, kTile128x64, kTile64x64, kTile256x128w8,
+                                 kTile256x256w8};
 
 struct Record {
   int64_t M, N, K;
@@ -93,7 +97,7 @@ std::vector<std::pair<int, int>> candidates(int64_t M, int64_t N, int64_t K) {
   const int64_t mn = std::min(std::min(M, N), K);
   for (int d = 0; d <= kMaxDepth; ++d) {
     if (d > 0 && (mn >> d) < kMinLeaf) break;
-    for (int t = 0; t < kNumTiles; ++t) c.push_back({d, t});
+    for (int t : kPlannerTiles) c.push_back({d, t});
   }
   return c;
 }

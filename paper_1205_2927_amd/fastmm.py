@@ -24,8 +24,10 @@ ERROR_NOT_SUPPORTED = -4
 AUTO = -1
 PLAN_DEFAULT, PLAN_MODEL, PLAN_EXHAUSTIVE = 0, 1, 2
 TILE_128x128, TILE_256x128, TILE_128x64, TILE_64x64 = 0, 1, 2, 3
+TILE_128x128_K32, TILE_256x128_W8, TILE_256x256_W8, TILE_128x256 = 4, 5, 6, 7
 TILES = {TILE_128x128: (128, 128), TILE_256x128: (256, 128), TILE_128x64: (128, 64),
-         TILE_64x64: (64, 64)}
+         TILE_64x64: (64, 64), TILE_128x128_K32: (128, 128), TILE_256x128_W8: (256, 128),
+         TILE_256x256_W8: (256, 256), TILE_128x256: (128, 256)}
 MLP_PARAMS = 4609
 
 # Every symbol include/fastmm.h declares.

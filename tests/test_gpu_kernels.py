@@ -62,7 +62,7 @@ def test_postadd_bit_exact(fastmm, h_r, h_c, rows, cols):
     assert np.array_equal(host(C), ref)
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7])
 def test_leaf_n512_uniform(fastmm, tile):
     say(f"leaf n=512 tile={tile}")
     n = 512
@@ -75,7 +75,7 @@ def test_leaf_n512_uniform(fastmm, tile):
     assert err <= 2e-6
 
 
-@pytest.mark.parametrize("tile", [0, 1, 2, 3])
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7])
 @pytest.mark.parametrize("m,k,n", [(257, 131, 383), (1, 1, 1), (33, 65, 17), (130, 7, 260),
                                    (300, 1000, 5), (64, 64, 64), (129, 257, 127)])
 def test_leaf_ragged_certified_exact(fastmm, tile, m, k, n):

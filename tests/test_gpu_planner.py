@@ -77,7 +77,7 @@ def test_exhaustive_model_regret_and_gain(fastmm, tmp_path):
         fastmm.plan(int(M), int(N), int(K), fastmm.PLAN_EXHAUSTIVE)
     n_train = fastmm.planner_records()
     say(f"training records: {n_train}")
-    assert n_train >= 40 * 4
+    assert n_train >= 40 * 5
     loss = fastmm.planner_train(epochs=400, batch=64, lr=3e-3, seed=4001)
     say(f"trained, loss={loss:.4f}")
     assert np.isfinite(loss) and loss < 0.5
