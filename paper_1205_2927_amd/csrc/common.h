@@ -32,28 +32,94 @@ struct GemmDesc {
 };
 
 // One node of a pre-addition launch: reads the four quadrants of a parent
-// operand view and writes four dense (h_r x h_c, ld = h_c) results.
+// operand (or a band of rows of each) and writes four h_r x h_c results.
+// Quadrant X11 starts at src, X12 at src + h_c, X21 at src + bot_off and
+// X22 at src + bot_off + h_c, all with leading dimension ld; rows / columns
+// beyond the valid counts read as zero.  Output q (0..3) starts at
+// dst + q * out_stride with leading dimension h_c.
 struct PreAddNode {
   const float* src;
-  float* dst;               // 4 consecutive h_r*h_c blocks
-  int64_t ld;
-  int32_t vrows, vcols;     // valid extent of the parent view
-  int32_t h_r, h_c;         // quadrant extents
-  int32_t block_begin;      // first workgroup of this node within the launch
-  int32_t pad_;
-};
-
-// One node of a post-addition launch: reads seven dense products (h_r x h_c)
-// and writes the four result quadrants into dst, clipped to rows x cols.
-struct PostAddNode {
-  const float* P;           // 7 consecutive h_r*h_c blocks
   float* dst;
   int64_t ld;
-  int32_t rows, cols;
+  int64_t bot_off;
+  int64_t out_stride;
+  int32_t top_rows, bot_rows;     // valid rows of the top / bottom quadrants
+  int32_t left_cols, right_cols;  // valid columns of the left / right quadrants
+  int32_t h_r, h_c;               // rows of this node, quadrant width
+  int32_t block_begin;            // first workgroup of this node within the launch
+  int32_t mask;                   // outputs to write (bit q-1 for S_q / T_q); 0 = all
+};
+
+// Quadrants (bit 0 = X11, 1 = X12, 2 = X21, 3 = X22) that pre-addition
+// outputs read: side 0 (S1..S4 from A), side 1 (T1..T4 from B).
+inline unsigned preadd_inputs(int side, unsigned outputs) {
+  static const unsigned a_need[4] = {0xC, 0xD, 0x5, 0xF};  // S1: A21 A22; S2: +A11; S3: A11 A21; S4: all
+  static const unsigned b_need[4] = {0x3, 0xB, 0xA, 0xF};  // T1: B11 B12; T2: +B22; T3: B12 B22; T4: all
+  unsigned q = 0;
+  for (int i = 0; i < 4; ++i)
+    if (outputs & (1u << i)) q |= (side == 0 ? a_need[i] : b_need[i]);
+  return q;
+}
+
+// One node of a post-addition launch: reads seven h_r x h_c products (P_i at
+// P + i * p_stride, leading dimension h_c) and writes the result quadrants:
+// C11 at dst, C12 at dst + h_c, C21 at dst + bot_off, C22 at
+// dst + bot_off + h_c (leading dimension ld), each clipped to its valid
+// rows / columns.
+struct PostAddNode {
+  const float* P;
+  float* dst;
+  int64_t ld;
+  int64_t p_stride;
+  int64_t bot_off;
+  int32_t top_rows, bot_rows;
+  int32_t left_cols, right_cols;
   int32_t h_r, h_c;
   int32_t block_begin;
   int32_t pad_;
 };
+
+inline int32_t clamp_extent(int64_t v, int64_t hi) {
+  return (int32_t)(v < 0 ? 0 : (v > hi ? hi : v));
+}
+
+// Pre-additions of a whole parent operand (vrows x vcols valid) whose
+// quadrants are h_r x h_c, into four dense blocks at dst.
+inline PreAddNode preadd_node(const float* src, int64_t ld, int64_t vrows, int64_t vcols,
+                              int64_t h_r, int64_t h_c, float* dst) {
+  PreAddNode n{};
+  n.src = src;
+  n.dst = dst;
+  n.ld = ld;
+  n.bot_off = h_r * ld;
+  n.out_stride = h_r * h_c;
+  n.top_rows = clamp_extent(vrows, h_r);
+  n.bot_rows = clamp_extent(vrows - h_r, h_r);
+  n.left_cols = clamp_extent(vcols, h_c);
+  n.right_cols = clamp_extent(vcols - h_c, h_c);
+  n.h_r = (int32_t)h_r;
+  n.h_c = (int32_t)h_c;
+  return n;
+}
+
+// Post-additions of seven dense h_r x h_c products at P into a result of
+// rows x cols (leading dimension ld) at dst.
+inline PostAddNode postadd_node(const float* P, int64_t h_r, int64_t h_c, float* dst, int64_t ld,
+                                int64_t rows, int64_t cols) {
+  PostAddNode n{};
+  n.P = P;
+  n.dst = dst;
+  n.ld = ld;
+  n.p_stride = h_r * h_c;
+  n.bot_off = h_r * ld;
+  n.top_rows = clamp_extent(rows, h_r);
+  n.bot_rows = clamp_extent(rows - h_r, h_r);
+  n.left_cols = clamp_extent(cols, h_c);
+  n.right_cols = clamp_extent(cols - h_c, h_c);
+  n.h_r = (int32_t)h_r;
+  n.h_c = (int32_t)h_c;
+  return n;
+}
 
 // Work of one add workgroup: kAddChunk float4 groups of one node.
 constexpr int kAddThreadsPerBlock = 256;

@@ -46,9 +46,20 @@ View quadrant(const View& v, int qr, int qc, int64_t h_r, int64_t h_c) {
   return q;
 }
 
+}  // namespace
+
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-}  // namespace
+// 16-byte accesses need every quadrant and output row start 16-byte aligned.
+bool pre_vec_ok(const PreAddNode& n) {
+  return aligned16(n.src) && aligned16(n.dst) && n.ld % 4 == 0 && n.h_c % 4 == 0 &&
+         n.bot_off % 4 == 0 && n.out_stride % 4 == 0;
+}
+
+bool post_vec_ok(const PostAddNode& n) {
+  return aligned16(n.P) && aligned16(n.dst) && n.ld % 4 == 0 && n.h_c % 4 == 0 &&
+         n.bot_off % 4 == 0 && n.p_stride % 4 == 0;
+}
 
 void set_error(const std::string& msg) { t_last_error = msg; }
 
@@ -212,12 +223,8 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
       for (int64_t x = 0; x < nodes; ++x) {
         const View& a = Av[x];
         const View& b = Bv[x];
-        PreAddNode na{a.p, S + x * 4 * sa, a.ld, (int32_t)a.vrows, (int32_t)a.vcols,
-                      (int32_t)c.m, (int32_t)c.k, 0, 0};
-        PreAddNode nb{b.p, T + x * 4 * tb, b.ld, (int32_t)b.vrows, (int32_t)b.vcols,
-                      (int32_t)c.k, (int32_t)c.n, 0, 0};
-        s.preA[l].push_back(na);
-        s.preB[l].push_back(nb);
+        s.preA[l].push_back(preadd_node(a.p, a.ld, a.vrows, a.vcols, c.m, c.k, S + x * 4 * sa));
+        s.preB[l].push_back(preadd_node(b.p, b.ld, b.vrows, b.vcols, c.k, c.n, T + x * 4 * tb));
         const View a11 = quadrant(a, 0, 0, c.m, c.k), a12 = quadrant(a, 0, 1, c.m, c.k),
                    a22 = quadrant(a, 1, 1, c.m, c.k);
         const View b11 = quadrant(b, 0, 0, c.k, c.n), b21 = quadrant(b, 1, 0, c.k, c.n),
@@ -275,22 +282,12 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
       const Dims c = dims[l + 1];
       const int64_t nodes = pow7(l);
       for (int64_t x = 0; x < nodes; ++x) {
-        PostAddNode pn{};
-        pn.P = P[l + 1] + x * 7 * c.m * c.n;
-        if (l == 0) {
-          pn.dst = p.C;
-          pn.ld = p.ldc;
-          pn.rows = (int32_t)p.cr();
-          pn.cols = (int32_t)p.cc();
-        } else {
-          pn.dst = P[l] + x * dims[l].m * dims[l].n;
-          pn.ld = dims[l].n;
-          pn.rows = (int32_t)dims[l].m;
-          pn.cols = (int32_t)dims[l].n;
-        }
-        pn.h_r = (int32_t)c.m;
-        pn.h_c = (int32_t)c.n;
-        s.post[l].push_back(pn);
+        const float* pin = P[l + 1] + x * 7 * c.m * c.n;
+        if (l == 0)
+          s.post[l].push_back(postadd_node(pin, c.m, c.n, p.C, p.ldc, p.cr(), p.cc()));
+        else
+          s.post[l].push_back(postadd_node(pin, c.m, c.n, P[l] + x * dims[l].m * dims[l].n,
+                                           dims[l].n, dims[l].m, dims[l].n));
       }
       s.add_bytes += (double)nodes * 44.0 * c.m * c.n;
     }
@@ -306,7 +303,7 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     for (auto& n : v) {
       n.block_begin = (int32_t)b;
       b += add_blocks_for(n.h_r, n.h_c);
-      if (!(aligned16(n.src) && aligned16(n.dst) && n.ld % 4 == 0 && n.h_c % 4 == 0)) vec = 0;
+      if (!pre_vec_ok(n)) vec = 0;
     }
     if (b > INT32_MAX) throw Error(kNotSupported, "pre-addition launch too large");
     return (int)b;
@@ -318,8 +315,7 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     for (auto& n : s.post[l]) {
       n.block_begin = (int32_t)b;
       b += add_blocks_for(n.h_r, n.h_c);
-      if (!(aligned16(n.P) && aligned16(n.dst) && n.ld % 4 == 0 && n.h_c % 4 == 0))
-        s.vec_post[l] = 0;
+      if (!post_vec_ok(n)) s.vec_post[l] = 0;
     }
     if (b > INT32_MAX) throw Error(kNotSupported, "post-addition launch too large");
   }
@@ -718,9 +714,8 @@ int fastmm_preadd(int side, int64_t rows, int64_t cols, const float* X, int64_t 
     ensure_init(L);
     if (classify(X) != kDevice || classify(out) != kDevice)
       throw Error(kNotSupported, "fastmm_preadd takes device pointers");
-    PreAddNode n{X, out, ldx, (int32_t)rows, (int32_t)cols, (int32_t)half_up(rows),
-                 (int32_t)half_up(cols), 0, 0};
-    const bool vec = aligned16(X) && aligned16(out) && ldx % 4 == 0 && n.h_c % 4 == 0;
+    PreAddNode n = preadd_node(X, ldx, rows, cols, half_up(rows), half_up(cols), out);
+    const bool vec = pre_vec_ok(n);
     char* dev = ensure_arena(L, 256);
     char* host = ensure_pinned(L, sizeof(n));
     std::memcpy(host, &n, sizeof(n));
@@ -746,8 +741,8 @@ int fastmm_postadd(int64_t h_r, int64_t h_c, const float* P, float* C, int64_t l
     ensure_init(L);
     if (classify(P) != kDevice || classify(C) != kDevice)
       throw Error(kNotSupported, "fastmm_postadd takes device pointers");
-    PostAddNode n{P, C, ldc, (int32_t)rows, (int32_t)cols, (int32_t)h_r, (int32_t)h_c, 0, 0};
-    const bool vec = aligned16(P) && aligned16(C) && ldc % 4 == 0 && h_c % 4 == 0;
+    PostAddNode n = postadd_node(P, h_r, h_c, C, ldc, rows, cols);
+    const bool vec = post_vec_ok(n);
     char* dev = ensure_arena(L, 256);
     char* host = ensure_pinned(L, sizeof(n));
     std::memcpy(host, &n, sizeof(n));

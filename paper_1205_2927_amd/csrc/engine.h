@@ -99,9 +99,9 @@ struct Library {
   hipEvent_t ev[8] = {};
   hipStream_t h2d_stream = nullptr;  // host->device staging copies
   hipStream_t d2h_stream = nullptr;  // device->host result copies
-  static constexpr int kSyncEvents = 16;
+  static constexpr int kSyncEvents = 48;
   hipEvent_t sync_ev[kSyncEvents] = {};  // ordering between the streams
-  static constexpr int kLeafEvents = 16;
+  static constexpr int kLeafEvents = 48;
   hipEvent_t leaf_ev[kLeafEvents] = {};  // timing of leaf launches
   hipEvent_t tune_ev[2] = {};            // planner's candidate timing
   fastmm_stats_t stats{};
@@ -139,6 +139,10 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
 void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
                int tile);
+
+bool aligned16(const void* p);
+bool pre_vec_ok(const PreAddNode& n);
+bool post_vec_ok(const PostAddNode& n);
 
 // Batched path's graph cache (batched.cpp).
 void destroy_graphs();

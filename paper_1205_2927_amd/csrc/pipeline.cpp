@@ -5,27 +5,33 @@
 // that transfers, not kernels, cap its throughput on large problems
 // (Section 4.2).  On MI355X the same holds in proportion: at n = 19456 the
 // copies of A, B and C take about as long as the whole Winograd product.
-// Here the top level of the recursion is run product by product on a compute
-// stream while a copy stream brings the operand quadrants in, in the order
-// the products need them, and a second copy stream sends each result
-// quadrant back as soon as its post-addition is done:
 //
-//   in:   A11 B11 | A12 B21 | B12 B22 A22 | A21
-//   run:  P1 = A11 B11, P2 = A12 B21        -> C11 = P1 + P2        -> out
-//         T1..T4, P4 = A22 T4; S1..S4, P6, P7 -> C21 = U3 - P4      -> out
-//         P5                                 -> C22 = U3 + P5       -> out
-//         P3                                 -> C12 = U4 + P3       -> out
+// Here the top level of the recursion runs as a sequence of steps on a
+// compute stream while one copy stream brings operand blocks in and a second
+// copy stream sends result blocks back as soon as they are final.  The
+// A-side quadrants are moved and multiplied in two row bands: band b of a
+// top-level product, P_i[b] = L_i[b] R_i, needs only band b of its left
+// operand, and is itself a Winograd product of depth d - 1.
 //
-// Each product Pi is itself a level-wise Winograd product of depth d - 1
-// (one grouped leaf launch).  Each result quadrant is formed by the same
-// chain of FP32 operations as the fused post-addition, so the result is bit
-// for bit the one of the unpipelined path.  With no Winograd level (plain
-// SGEMM) the same overlap is used on the 2 x 2 block product
-// C_ij = A_i B_j (row halves of A, column halves of B).
+// Input order.  Every product needs a different subset of the eight
+// quadrants (P1: A11 B11; P7: A11 A21 B12 B22; P5: A21 A22 B11 B12; P6: A11
+// A21 A22 B11 B12 B22; P2: A12 B21; P4: A22 and all of B; P3: all of A and
+// B22).  Sending A12 and B21 last leaves only P2, P3 and P4 waiting for the
+// end of the transfer; the fixed order below (found by simulating the
+// copies and products at n = 19456) also interleaves bands so that products
+// can start early:
+//   A11[0] B11 A22[0] A11[1] A21[0] B12 B22 B21 A22[1] A21[1] A12[0] A12[1]
+// Products run greedily in order of estimated readiness.  Pre-additions
+// compute only the S / T outputs whose inputs have arrived (a later pass
+// adds the rest), and each result block C_q[b] is formed and sent out as
+// soon as its four products (C11: P1 P2; C12: P1 P6 P5 P3; C21: P1 P6 P7 P4;
+// C22: P1 P6 P7 P5) are done.
+//
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "engine.h"
@@ -36,7 +42,7 @@ namespace {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 // Copy rows [r0, r0 + rows) x cols [c0, c0 + cols) of a host matrix into the
-// same block of a dense device matrix.
+// same block of a dense device matrix (or back).
 void h2d_block(float* dev, int64_t ld_dev, const float* host, int64_t ld_host, int64_t r0,
                int64_t c0, int64_t rows, int64_t cols, hipStream_t s) {
   if (rows <= 0 || cols <= 0) return;
@@ -51,13 +57,6 @@ void d2h_block(float* host, int64_t ld_host, const float* dev, int64_t ld_dev, i
                               ld_dev * 4, cols * 4, rows, hipMemcpyDeviceToHost, s));
 }
 
-struct Child {
-  Problem p;
-  Schedule s;
-  char* desc_dev = nullptr;
-  char* desc_host = nullptr;
-};
-
 double ev_ms(hipEvent_t a, hipEvent_t b) {
   float ms = 0.f;
   if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
@@ -65,6 +64,31 @@ double ev_ms(hipEvent_t a, hipEvent_t b) {
     return -1.0;
   }
   return ms;
+}
+
+// A group of sub-products launched as one level-wise schedule.
+struct Group {
+  std::vector<Problem> probs;
+  Schedule s;
+  size_t desc_off = 0, desc_bytes = 0;
+};
+
+// Row bands [r0, r0 + rows) of the top quadrants (rows of the bottom
+// quadrants in the band: bot).
+struct Band {
+  int64_t r0, rows, bot;
+};
+
+std::vector<Band> make_bands(int64_t m2, int64_t mb, int nb, int64_t align) {
+  std::vector<Band> v;
+  int64_t split = m2;
+  if (nb >= 2 && m2 >= 2) {
+    split = (m2 / 2 + align / 2) / align * align;
+    if (split <= 0 || split >= m2) split = (m2 + 1) / 2;
+  }
+  v.push_back({0, split, std::min(split, mb)});
+  if (split < m2) v.push_back({split, m2 - split, std::max<int64_t>(0, std::min(m2 - split, mb - split))});
+  return v;
 }
 
 }  // namespace
@@ -75,8 +99,9 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   const int64_t m2 = half_up(M), k2 = half_up(K), n2 = half_up(N);
   const int64_t mb = M - m2, kb = K - k2, nb = N - n2;
   const bool wino = depth >= 1;
+  const TileShape ts = tile_shape(tile);
 
-  // ---- workspace layout
+  // ---- workspace layout (byte offsets into the arena)
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -91,206 +116,425 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     oT = take((size_t)4 * k2 * n2 * 4);
     oP = take((size_t)7 * m2 * n2 * 4);
   }
-  // Children: 7 sub-products (depth - 1 each) or 4 block products (depth 0).
-  const int nchild = wino ? 7 : 4;
-  std::vector<Child> ch(nchild);
-  for (int i = 0; i < nchild; ++i) {
-    Problem& p = ch[i].p;
+
+  // ---- the steps, as groups of sub-problems (device pointers filled below)
+  // Bands of A's rows: for Winograd, of the top quadrants (m2 rows); for the
+  // plain product, of A itself (M rows) in quarters.
+  const int64_t align = (int64_t)ts.bm << (wino ? depth - 1 : 0);
+  std::vector<Band> bands;
+  if (wino) {
+    bands = make_bands(m2, mb, 2, align);
+  } else {
+    // Quarters of M, rounded to whole tiles when M allows (at most 6 bands).
+    int64_t q = (M + 3) / 4;
+    if (q >= ts.bm) q = (q + ts.bm / 2) / ts.bm * ts.bm;
+    for (int64_t r0 = 0; r0 < M; r0 += q) bands.push_back({r0, std::min(q, M - r0), 0});
+  }
+  const int nband = (int)bands.size();
+
+  // Placeholder device pointers for sizing (real ones set after allocation).
+  char* ws = nullptr;
+  float *dA = nullptr, *dB = nullptr, *dC = nullptr, *S = nullptr, *T = nullptr, *P = nullptr;
+  const int64_t ma = m2 * k2, tb = k2 * n2, pc = m2 * n2;
+
+  struct V {
+    const float* p;
+    int64_t ld, r, c;
+  };
+  // Left operand of top-level product i (0..6), band b; right operand of i.
+  auto left = [&](int i, const Band& b) -> V {
+    switch (i) {
+      case 0: return {dA + b.r0 * K, K, b.rows, k2};                 // A11
+      case 1: return {dA + b.r0 * K + k2, K, b.rows, kb};            // A12
+      case 2: return {S + 3 * ma + b.r0 * k2, k2, b.rows, k2};       // S4
+      case 3: return {dA + (m2 + b.r0) * K + k2, K, b.bot, kb};      // A22
+      case 4: return {S + 0 * ma + b.r0 * k2, k2, b.rows, k2};       // S1
+      case 5: return {S + 1 * ma + b.r0 * k2, k2, b.rows, k2};       // S2
+      default: return {S + 2 * ma + b.r0 * k2, k2, b.rows, k2};      // S3
+    }
+  };
+  auto right = [&](int i) -> V {
+    switch (i) {
+      case 0: return {dB, N, k2, n2};                 // B11
+      case 1: return {dB + k2 * N, N, kb, n2};        // B21
+      case 2: return {dB + k2 * N + n2, N, kb, nb};   // B22
+      case 3: return {T + 3 * tb, n2, k2, n2};        // T4
+      case 4: return {T + 0 * tb, n2, k2, n2};        // T1
+      case 5: return {T + 1 * tb, n2, k2, n2};        // T2
+      default: return {T + 2 * tb, n2, k2, n2};       // T3
+    }
+  };
+  auto wino_problem = [&](int i, const Band& b) {
+    Problem p;
+    const V l = left(i, b), r = right(i);
+    p.M = b.rows;
+    p.K = k2;
+    p.N = n2;
+    p.A = l.p;
+    p.lda = l.ld;
+    p.a_rows = l.r;
+    p.a_cols = l.c;
+    p.B = r.p;
+    p.ldb = r.ld;
+    p.b_rows = r.r;
+    p.b_cols = r.c;
+    p.C = P + i * pc + b.r0 * n2;
+    p.ldc = n2;
+    p.depth = depth - 1;
     p.tile = tile;
-    if (wino) {
-      p.M = m2;
-      p.K = k2;
-      p.N = n2;
-      p.depth = depth - 1;
-    } else {
-      const int bi = i / 2, bj = i % 2;
-      p.M = bi == 0 ? m2 : mb;
-      p.N = bj == 0 ? n2 : nb;
-      p.K = K;
-      p.depth = 0;
+    return p;
+  };
+  auto plain_problem = [&](const Band& b, int half) {
+    Problem p;
+    p.M = b.rows;
+    p.K = K;
+    p.N = half == 0 ? n2 : nb;
+    p.A = dA + b.r0 * K;
+    p.lda = K;
+    p.B = dB + (half ? n2 : 0);
+    p.ldb = N;
+    p.C = dC + b.r0 * N + (half ? n2 : 0);
+    p.ldc = N;
+    p.depth = 0;
+    p.tile = tile;
+    return p;
+  };
+
+  // The step list is built twice: once with placeholder pointers (sizes),
+  // once with the real ones.  Each group's temporaries share one region.
+  std::vector<Group> groups;
+  // Product bands in compute order (wino): chosen by simulating the copies
+  // and the products with rough rates; see the comment at the top.
+  struct Item {
+    int mat, qr, qc, band;  // mat 0 = A (band 0/1), 1 = B (band -1)
+  };
+  std::vector<Item> items;
+  std::vector<std::pair<int, int>> order;  // (product 0..6, band)
+  // Quadrant bit (X11, X12, X21, X22) -> item index for A (per band) and B.
+  int a_item[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}}, b_item[4] = {-1, -1, -1, -1};
+  // Quadrants each product reads (bit 0 = X11, 1 = X12, 2 = X21, 3 = X22).
+  static const unsigned kNeedA[7] = {0x1, 0x2, 0xF, 0x8, 0xC, 0xD, 0x5};
+  static const unsigned kNeedB[7] = {0x1, 0x4, 0x8, 0xF, 0x3, 0xB, 0xA};
+  if (wino) {
+    const int nbd = (int)bands.size();
+    auto A_ = [&](int q, int b) { items.push_back({0, q / 2, q % 2, b}); a_item[q][b] = (int)items.size() - 1; };
+    auto B_ = [&](int q) { items.push_back({1, q / 2, q % 2, -1}); b_item[q] = (int)items.size() - 1; };
+    const int b1 = nbd > 1 ? 1 : 0;
+    A_(0, 0); B_(0); A_(3, 0); if (b1) A_(0, 1); A_(2, 0); B_(1); B_(3); B_(2);
+    if (b1) { A_(3, 1); A_(2, 1); }
+    A_(1, 0); if (b1) A_(1, 1);
+    // Estimated arrival times (bytes at PCIe rate) and product costs (flops
+    // at the leaf rate); only the order matters.
+    std::vector<double> t_arrive(items.size());
+    double t = 0.0;
+    for (size_t k = 0; k < items.size(); ++k) {
+      const Item& it = items[k];
+      const double rows = it.mat == 0 ? (it.qr ? bands[it.band].bot : bands[it.band].rows)
+                                      : (it.qr ? kb : k2);
+      const double cols = it.mat == 0 ? (it.qc ? kb : k2) : (it.qc ? nb : n2);
+      t += rows * cols * 4.0 / 56e9;
+      t_arrive[k] = t;
+    }
+    auto ready_item = [&](int i, int b) {
+      int last = -1;
+      for (int q = 0; q < 4; ++q) {
+        if (kNeedA[i] & (1u << q)) last = std::max(last, a_item[q][b]);
+        if (kNeedB[i] & (1u << q)) last = std::max(last, b_item[q]);
+      }
+      return last;
+    };
+    std::vector<std::pair<int, int>> pending;
+    for (int b = 0; b < nbd; ++b)
+      for (int i = 0; i < 7; ++i) pending.push_back({i, b});
+    double tc = 0.0;
+    while (!pending.empty()) {
+      size_t best = 0;
+      double best_start = 1e300, best_ready = 1e300;
+      for (size_t k = 0; k < pending.size(); ++k) {
+        const double r = t_arrive[ready_item(pending[k].first, pending[k].second)];
+        const double st = std::max(r, tc);
+        if (st < best_start - 1e-12 || (std::abs(st - best_start) <= 1e-12 && r < best_ready)) {
+          best = k;
+          best_start = st;
+          best_ready = r;
+        }
+      }
+      const auto pb = pending[best];
+      pending.erase(pending.begin() + best);
+      const double rows = (double)bands[pb.second].rows;
+      tc = best_start + 2.0 * rows * k2 * n2 / 120e12;
+      order.push_back(pb);
     }
   }
-  const size_t child_temp = align_up(problem_temp_bytes(ch[0].p), 256);
-  const size_t oTemp = take(child_temp);
-  // Descriptor regions: one per child plus one for the top-level additions.
-  std::vector<size_t> desc_size(nchild);
-  for (int i = 0; i < nchild; ++i) {
-    Problem q = ch[i].p;
-    q.A = q.B = reinterpret_cast<const float*>(256);
-    q.C = const_cast<float*>(q.A);
-    q.lda = std::max<int64_t>(q.K, 1);
-    q.ldb = q.ldc = std::max<int64_t>(q.N, 1);
+  auto build_groups = [&]() {
+    groups.clear();
+    if (wino) {
+      for (auto& pb : order) groups.push_back({{wino_problem(pb.first, bands[pb.second])}});
+    } else {
+      for (auto& b : bands) groups.push_back({{plain_problem(b, 0)}});
+      for (auto& b : bands) groups.push_back({{plain_problem(b, 1)}});
+    }
+  };
+  build_groups();
+  // Descriptor slots: pre-addition passes (at most 4 per band for S and 4
+  // for T), one post-addition node per band; then the product schedules.
+  size_t temp_max = 0, desc_total = 256 * (size_t)(8 * nband + 8 + nband);
+  for (auto& g : groups) {
+    size_t t = 0;
+    for (auto& p : g.probs) t += align_up(problem_temp_bytes(p), 256);
+    temp_max = std::max(temp_max, t);
+    std::vector<Problem> q = g.probs;
+    for (auto& x : q) {  // any non-null placeholder: only counts matter here
+      x.A = x.B = reinterpret_cast<const float*>(256);
+      x.C = const_cast<float*>(x.A);
+    }
     Schedule tmp;
-    build_schedule({q}, reinterpret_cast<char*>(256), tmp);
-    desc_size[i] = align_up(schedule_desc_bytes(tmp), 256) + 256;
+    build_schedule(q, reinterpret_cast<char*>(256), tmp);
+    g.desc_bytes = align_up(schedule_desc_bytes(tmp), 256) + 256;
+    g.desc_off = desc_total;
+    desc_total += g.desc_bytes;
   }
-  const size_t top_desc = 6 * 256;  // preA, preB and four post-addition nodes
-  size_t desc_total = top_desc;
-  for (auto d : desc_size) desc_total += d;
+  const size_t oTemp = take(temp_max);
   const size_t oDesc = take(desc_total);
 
-  char* ws = ensure_arena(L, off);
+  ws = ensure_arena(L, off);
   char* host = ensure_pinned(L, desc_total);
-  float* dA = reinterpret_cast<float*>(ws + oA);
-  float* dB = reinterpret_cast<float*>(ws + oB);
-  float* dC = reinterpret_cast<float*>(ws + oC);
-  float* S = reinterpret_cast<float*>(ws + oS);
-  float* T = reinterpret_cast<float*>(ws + oT);
-  float* P = reinterpret_cast<float*>(ws + oP);
+  dA = reinterpret_cast<float*>(ws + oA);
+  dB = reinterpret_cast<float*>(ws + oB);
+  dC = reinterpret_cast<float*>(ws + oC);
+  S = reinterpret_cast<float*>(ws + oS);
+  T = reinterpret_cast<float*>(ws + oT);
+  P = reinterpret_cast<float*>(ws + oP);
   char* temps = ws + oTemp;
   char* ddesc = ws + oDesc;
+  {
+    std::vector<size_t> doff, dbytes;
+    for (auto& g : groups) {
+      doff.push_back(g.desc_off);
+      dbytes.push_back(g.desc_bytes);
+    }
+    build_groups();
+    for (size_t i = 0; i < groups.size(); ++i) {
+      groups[i].desc_off = doff[i];
+      groups[i].desc_bytes = dbytes[i];
+      build_schedule(groups[i].probs, temps, groups[i].s);
+    }
+  }
 
-  // ---- operand views of the children (device staging buffers, dense).
+  // Top-level post-addition nodes, one per band (the quadrant is chosen at
+  // launch).  Pre-addition nodes are written as they are issued (their
+  // output masks depend on what has arrived).
+  size_t slot = 0;
+  auto next_slot = [&]() {
+    if (slot >= (size_t)(8 * nband + 8 + nband)) throw Error(kDeviceError, "descriptor slots exhausted");
+    return 256 * slot++;
+  };
+  std::vector<const PostAddNode*> d_post(nband);
+  std::vector<char> vec_post(nband);
   if (wino) {
-    const int64_t ma = m2 * k2, tb = k2 * n2, pc = m2 * n2;
-    struct V {
-      const float* p;
-      int64_t ld, r, c;
-    };
-    const V a11{dA, K, m2, k2}, a12{dA + k2, K, m2, kb}, a22{dA + m2 * K + k2, K, mb, kb};
-    const V b11{dB, N, k2, n2}, b21{dB + k2 * N, N, kb, n2}, b22{dB + k2 * N + n2, N, kb, nb};
-    auto sv = [&](int i) { return V{S + i * ma, k2, m2, k2}; };
-    auto tv = [&](int i) { return V{T + i * tb, n2, k2, n2}; };
-    // P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4, P5 = S1 T1,
-    // P6 = S2 T2, P7 = S3 T3.
-    const V ca[7] = {a11, a12, sv(3), a22, sv(0), sv(1), sv(2)};
-    const V cb[7] = {b11, b21, b22, tv(3), tv(0), tv(1), tv(2)};
-    for (int i = 0; i < 7; ++i) {
-      Problem& p = ch[i].p;
-      p.A = ca[i].p;
-      p.lda = ca[i].ld;
-      p.a_rows = ca[i].r;
-      p.a_cols = ca[i].c;
-      p.B = cb[i].p;
-      p.ldb = cb[i].ld;
-      p.b_rows = cb[i].r;
-      p.b_cols = cb[i].c;
-      p.C = P + i * pc;
-      p.ldc = n2;
-    }
-  } else {
-    for (int i = 0; i < 4; ++i) {
-      const int bi = i / 2, bj = i % 2;
-      Problem& p = ch[i].p;
-      p.A = dA + bi * m2 * K;
-      p.lda = K;
-      p.B = dB + bj * n2;
-      p.ldb = N;
-      p.C = dC + bi * m2 * N + bj * n2;
-      p.ldc = N;
+    for (int bi = 0; bi < nband; ++bi) {
+      const Band& b = bands[bi];
+      PostAddNode np{};
+      np.P = P + b.r0 * n2;
+      np.dst = dC + b.r0 * N;
+      np.ld = N;
+      np.p_stride = pc;
+      np.bot_off = m2 * N;
+      np.top_rows = (int32_t)b.rows;
+      np.bot_rows = (int32_t)b.bot;
+      np.left_cols = (int32_t)n2;
+      np.right_cols = (int32_t)nb;
+      np.h_r = (int32_t)b.rows;
+      np.h_c = (int32_t)n2;
+      const size_t o = next_slot();
+      std::memcpy(host + o, &np, sizeof(np));
+      d_post[bi] = reinterpret_cast<const PostAddNode*>(ddesc + o);
+      vec_post[bi] = post_vec_ok(np);
     }
   }
-  // Schedules and descriptor blocks (host side, before anything is queued).
-  size_t doff = top_desc;
-  for (int i = 0; i < nchild; ++i) {
-    build_schedule({ch[i].p}, temps, ch[i].s);
-    ch[i].desc_dev = ddesc + doff;
-    ch[i].desc_host = host + doff;
-    doff += desc_size[i];
-  }
-  PreAddNode na{dA, S, K, (int32_t)M, (int32_t)K, (int32_t)m2, (int32_t)k2, 0, 0};
-  PreAddNode nbn{dB, T, N, (int32_t)K, (int32_t)N, (int32_t)k2, (int32_t)n2, 0, 0};
-  PostAddNode pn{P, dC, N, (int32_t)M, (int32_t)N, (int32_t)m2, (int32_t)n2, 0, 0};
-  std::memcpy(host, &na, sizeof(na));
-  std::memcpy(host + 256, &nbn, sizeof(nbn));
-  std::memcpy(host + 512, &pn, sizeof(pn));
-  const PreAddNode* d_na = reinterpret_cast<const PreAddNode*>(ddesc);
-  const PreAddNode* d_nb = reinterpret_cast<const PreAddNode*>(ddesc + 256);
-  const PostAddNode* d_pn = reinterpret_cast<const PostAddNode*>(ddesc + 512);
-  const bool vec_a = K % 4 == 0 && k2 % 4 == 0;
-  const bool vec_b = N % 4 == 0 && n2 % 4 == 0;
-  const bool vec_p = N % 4 == 0 && n2 % 4 == 0;
-
   hipStream_t cs = L.stream, hs = L.h2d_stream, ds = L.d2h_stream;
-  hipEvent_t* E = L.sync_ev;  // E[0] start, E[1..4] inputs, E[5..8] outputs
+  int ev_next = 1;
+  auto next_event = [&]() {
+    if (ev_next >= Library::kSyncEvents) throw Error(kDeviceError, "pipeline event pool exhausted");
+    return L.sync_ev[ev_next++];
+  };
   FASTMM_HIP(hipEventRecord(L.ev[0], cs));
-  FASTMM_HIP(hipEventRecord(E[0], cs));
-  FASTMM_HIP(hipStreamWaitEvent(hs, E[0], 0));
-  FASTMM_HIP(hipStreamWaitEvent(ds, E[0], 0));
+  FASTMM_HIP(hipEventRecord(L.sync_ev[0], cs));
+  FASTMM_HIP(hipStreamWaitEvent(hs, L.sync_ev[0], 0));
+  FASTMM_HIP(hipStreamWaitEvent(ds, L.sync_ev[0], 0));
+  if (slot) FASTMM_HIP(hipMemcpyAsync(ddesc, host, 256 * slot, hipMemcpyHostToDevice, cs));
 
-  // ---- inputs, in the order the products consume them
-  if (wino) {
-    h2d_block(dA, K, A, lda, 0, 0, m2, k2, hs);    // A11
-    h2d_block(dB, N, B, ldb, 0, 0, k2, n2, hs);    // B11
-    FASTMM_HIP(hipEventRecord(E[1], hs));
-    h2d_block(dA, K, A, lda, 0, k2, m2, kb, hs);   // A12
-    h2d_block(dB, N, B, ldb, k2, 0, kb, n2, hs);   // B21
-    FASTMM_HIP(hipEventRecord(E[2], hs));
-    h2d_block(dB, N, B, ldb, 0, n2, k2, nb, hs);   // B12
-    h2d_block(dB, N, B, ldb, k2, n2, kb, nb, hs);  // B22
-    h2d_block(dA, K, A, lda, m2, k2, mb, kb, hs);  // A22
-    FASTMM_HIP(hipEventRecord(E[3], hs));
-    h2d_block(dA, K, A, lda, m2, 0, mb, k2, hs);   // A21
-    FASTMM_HIP(hipEventRecord(E[4], hs));
-  } else {
-    h2d_block(dA, K, A, lda, 0, 0, m2, K, hs);     // A top
-    h2d_block(dB, N, B, ldb, 0, 0, K, n2, hs);     // B left
-    FASTMM_HIP(hipEventRecord(E[1], hs));
-    h2d_block(dB, N, B, ldb, 0, n2, K, nb, hs);    // B right
-    FASTMM_HIP(hipEventRecord(E[2], hs));
-    h2d_block(dA, K, A, lda, m2, 0, mb, K, hs);    // A bottom
-    FASTMM_HIP(hipEventRecord(E[3], hs));
-    FASTMM_HIP(hipEventRecord(E[4], hs));
-  }
-  FASTMM_HIP(hipEventRecord(L.ev[5], hs));
+  // ---- inputs
+  auto arrive = [&]() {  // event after the copies queued so far
+    hipEvent_t e = next_event();
+    FASTMM_HIP(hipEventRecord(e, hs));
+    return e;
+  };
+  auto a_band = [&](int qr, int qc, const Band& b) {
+    const int64_t rows = qr ? b.bot : b.rows;
+    h2d_block(dA, K, A, lda, (qr ? m2 : 0) + b.r0, qc ? k2 : 0, rows, qc ? kb : k2, hs);
+  };
+  auto b_quad = [&](int qr, int qc) {
+    h2d_block(dB, N, B, ldb, qr ? k2 : 0, qc ? n2 : 0, qr ? kb : k2, qc ? nb : n2, hs);
+  };
 
-  // ---- compute
-  FASTMM_HIP(hipMemcpyAsync(ddesc, host, top_desc, hipMemcpyHostToDevice, cs));
   int launches = 0, nleaf = 0;
-  auto run_child = [&](int i) {
+  auto run_group = [&](Group& g) {
+    if (2 * nleaf + 1 >= Library::kLeafEvents) throw Error(kDeviceError, "leaf event pool exhausted");
     hipEvent_t b = L.leaf_ev[2 * nleaf], e = L.leaf_ev[2 * nleaf + 1];
     ++nleaf;
-    launches += enqueue_schedule(L, ch[i].s, ch[i].desc_dev, ch[i].desc_host, b, e);
+    launches += enqueue_schedule(L, g.s, ddesc + g.desc_off, host + g.desc_off, b, e);
   };
-  // Result quadrant q (0 = C11, 1 = C12, 2 = C21, 3 = C22) out to the host.
-  auto send = [&](int q, hipEvent_t ev) {
+  auto wait = [&](hipEvent_t e) { FASTMM_HIP(hipStreamWaitEvent(cs, e, 0)); };
+  // Result block out: quadrant q (0 = C11, 1 = C12, 2 = C21, 3 = C22), band b.
+  auto send = [&](int q, const Band& b) {
     const int qr = q / 2, qc = q % 2;
-    FASTMM_HIP(hipEventRecord(ev, cs));
-    FASTMM_HIP(hipStreamWaitEvent(ds, ev, 0));
-    d2h_block(C, ldc, dC, N, qr ? m2 : 0, qc ? n2 : 0, qr ? mb : m2, qc ? nb : n2, ds);
+    hipEvent_t e = next_event();
+    FASTMM_HIP(hipEventRecord(e, cs));
+    FASTMM_HIP(hipStreamWaitEvent(ds, e, 0));
+    d2h_block(C, ldc, dC, N, (qr ? m2 : 0) + b.r0, qc ? n2 : 0, qr ? b.bot : b.rows,
+              qc ? nb : n2, ds);
   };
-  auto post = [&](int q) {
-    launch_postadd(d_pn, 1, (int)add_blocks_for(m2, n2), vec_p, cs, q);
+  auto post = [&](int q, int bi) {
+    const Band& b = bands[bi];
+    launch_postadd(d_post[bi], 1, (int)add_blocks_for(b.rows, n2), vec_post[bi], cs, q);
     ++launches;
   };
-  // Each child's schedule uploads its own descriptor block on this stream
-  // (distinct host and device regions), ahead of its launches.
+
   if (wino) {
-    FASTMM_HIP(hipStreamWaitEvent(cs, E[1], 0));
-    run_child(0);                                   // P1
-    FASTMM_HIP(hipStreamWaitEvent(cs, E[2], 0));
-    run_child(1);                                   // P2
-    post(0);                                        // C11 = P1 + P2
-    send(0, E[5]);
-    FASTMM_HIP(hipStreamWaitEvent(cs, E[3], 0));
-    launch_preadd(1, d_nb, 1, (int)add_blocks_for(k2, n2), vec_b, cs);  // T1..T4
-    ++launches;
-    run_child(3);                                   // P4 = A22 T4
-    FASTMM_HIP(hipStreamWaitEvent(cs, E[4], 0));
-    launch_preadd(0, d_na, 1, (int)add_blocks_for(m2, k2), vec_a, cs);  // S1..S4
-    ++launches;
-    run_child(5);                                   // P6 = S2 T2
-    run_child(6);                                   // P7 = S3 T3
-    post(2);                                        // C21 = U3 - P4
-    send(2, E[6]);
-    run_child(4);                                   // P5 = S1 T1
-    post(3);                                        // C22 = U3 + P5
-    send(3, E[7]);
-    run_child(2);                                   // P3 = S4 B22
-    post(1);                                        // C12 = U4 + P3
-    send(1, E[8]);
+    // ---- inputs, in the recipe's order
+    std::vector<hipEvent_t> ev_item(items.size());
+    for (size_t k = 0; k < items.size(); ++k) {
+      const Item& it = items[k];
+      if (it.mat == 0) a_band(it.qr, it.qc, bands[it.band]);
+      else b_quad(it.qr, it.qc);
+      ev_item[k] = arrive();
+    }
+    FASTMM_HIP(hipEventRecord(L.ev[5], hs));
+
+    // ---- compute
+    int waited = -1;  // inputs 0..waited are on the device (stream order)
+    auto wait_item = [&](int k) {
+      if (k > waited) {
+        wait(ev_item[k]);
+        waited = k;
+      }
+    };
+    unsigned s_done[2] = {0, 0}, t_done = 0;  // outputs computed so far
+    auto have = [&](int mat, int q, int b) {
+      return (mat == 0 ? a_item[q][b] : b_item[q]) <= waited;
+    };
+    // Issue one pre-addition pass for every output of this operand whose
+    // inputs are all on the device and that is not computed yet.
+    auto preadd_pass = [&](int side, int bi) {
+      unsigned& done = side == 0 ? s_done[bi] : t_done;
+      unsigned mask = 0;
+      for (int j = 0; j < 4; ++j) {
+        if (done & (1u << j)) continue;
+        const unsigned in = preadd_inputs(side, 1u << j);
+        bool ok = true;
+        for (int q = 0; q < 4; ++q)
+          if ((in & (1u << q)) && !have(side == 0 ? 0 : 1, q, bi)) ok = false;
+        if (ok) mask |= 1u << j;
+      }
+      if (!mask) return;
+      PreAddNode n{};
+      if (side == 0) {
+        const Band& b = bands[bi];
+        n.src = dA + b.r0 * K;
+        n.dst = S + b.r0 * k2;
+        n.ld = K;
+        n.bot_off = m2 * K;
+        n.out_stride = ma;
+        n.top_rows = (int32_t)b.rows;
+        n.bot_rows = (int32_t)b.bot;
+        n.left_cols = (int32_t)k2;
+        n.right_cols = (int32_t)kb;
+        n.h_r = (int32_t)b.rows;
+        n.h_c = (int32_t)k2;
+      } else {
+        n = preadd_node(dB, N, K, N, k2, n2, T);
+      }
+      n.mask = (int32_t)mask;
+      const size_t o = next_slot();
+      std::memcpy(host + o, &n, sizeof(n));
+      FASTMM_HIP(hipMemcpyAsync(ddesc + o, host + o, sizeof(n), hipMemcpyHostToDevice, cs));
+      launch_preadd(side, reinterpret_cast<const PreAddNode*>(ddesc + o), 1,
+                    (int)add_blocks_for(n.h_r, n.h_c), pre_vec_ok(n), cs);
+      ++launches;
+      done |= mask;
+    };
+    // Left / right operand: which S / T output product i reads (0 = none).
+    static const int kLeftS[7] = {0, 0, 4, 0, 1, 2, 3};   // P3: S4, P5: S1, P6: S2, P7: S3
+    static const int kRightT[7] = {0, 0, 0, 4, 1, 2, 3};  // P4: T4, P5: T1, P6: T2, P7: T3
+    static const int kQuadP[4][4] = {{0, 1, -1, -1}, {0, 5, 4, 2}, {0, 5, 6, 3}, {0, 5, 6, 4}};
+    bool pdone[7][2] = {};
+    bool sent[4][2] = {};
+    for (size_t gi = 0; gi < order.size(); ++gi) {
+      const int i = order[gi].first, bi = order[gi].second;
+      int last = -1;
+      for (int q = 0; q < 4; ++q) {
+        if (kNeedA[i] & (1u << q)) last = std::max(last, a_item[q][bi]);
+        if (kNeedB[i] & (1u << q)) last = std::max(last, b_item[q]);
+      }
+      wait_item(last);
+      if (kLeftS[i] && !(s_done[bi] & (1u << (kLeftS[i] - 1)))) preadd_pass(0, bi);
+      if (kRightT[i] && !(t_done & (1u << (kRightT[i] - 1)))) preadd_pass(1, 0);
+      run_group(groups[gi]);
+      pdone[i][bi] = true;
+      // Result blocks whose four (two for C11) products are now all done.
+      for (int q = 0; q < 4; ++q) {
+        if (sent[q][bi]) continue;
+        bool ok = true;
+        for (int k = 0; k < 4; ++k)
+          if (kQuadP[q][k] >= 0 && !pdone[kQuadP[q][k]][bi]) ok = false;
+        if (!ok) continue;
+        // quadrant index for post/send: 0 = C11, 1 = C12, 2 = C21, 3 = C22
+        post(q, bi);
+        send(q, bands[bi]);
+        sent[q][bi] = true;
+      }
+    }
   } else {
-    FASTMM_HIP(hipStreamWaitEvent(cs, E[1], 0));
-    run_child(0);                                   // C11 = A_top B_left
-    send(0, E[5]);
-    FASTMM_HIP(hipStreamWaitEvent(cs, E[2], 0));
-    run_child(1);                                   // C12 = A_top B_right
-    send(1, E[6]);
-    FASTMM_HIP(hipStreamWaitEvent(cs, E[3], 0));
-    run_child(2);                                   // C21 = A_bottom B_left
-    send(2, E[7]);
-    run_child(3);                                   // C22 = A_bottom B_right
-    send(3, E[8]);
+    // Plain product.  In: B's left half and A's first band, A's second band,
+    // B's right half, then the remaining bands.  Run C[b, left] as each band
+    // arrives; once the right half is in, the right halves of the bands so
+    // far, then both halves of each later band.
+    const int pivot = std::min(1, nband - 1);
+    std::vector<hipEvent_t> ea(nband);
+    hipEvent_t eBR = nullptr;
+    h2d_block(dB, N, B, ldb, 0, 0, K, n2, hs);
+    for (int bi = 0; bi < nband; ++bi) {
+      h2d_block(dA, K, A, lda, bands[bi].r0, 0, bands[bi].rows, K, hs);
+      ea[bi] = arrive();
+      if (bi == pivot) {
+        h2d_block(dB, N, B, ldb, 0, n2, K, nb, hs);
+        eBR = arrive();
+      }
+    }
+    FASTMM_HIP(hipEventRecord(L.ev[5], hs));
+    auto block_out = [&](int bi, int half) {
+      const Band& b = bands[bi];
+      hipEvent_t e = next_event();
+      FASTMM_HIP(hipEventRecord(e, cs));
+      FASTMM_HIP(hipStreamWaitEvent(ds, e, 0));
+      d2h_block(C, ldc, dC, N, b.r0, half ? n2 : 0, b.rows, half ? nb : n2, ds);
+    };
+    for (int bi = 0; bi < nband; ++bi) {
+      wait(ea[bi]);
+      run_group(groups[bi]);  // C[b, left]
+      block_out(bi, 0);
+      if (bi == pivot) {
+        wait(eBR);
+        for (int bj = 0; bj <= bi; ++bj) {
+          run_group(groups[nband + bj]);  // C[bj, right]
+          block_out(bj, 1);
+        }
+      } else if (bi > pivot) {
+        run_group(groups[nband + bi]);
+        block_out(bi, 1);
+      }
+    }
   }
   FASTMM_HIP(hipEventRecord(L.ev[7], ds));
   FASTMM_HIP(hipStreamSynchronize(ds));
@@ -303,14 +547,14 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   st.leaves = 0;
   st.leaf_flops = 0;
   st.add_bytes = 0;
-  for (auto& c : ch) {
-    st.leaves += c.s.leaves;
-    st.leaf_flops += c.s.leaf_flops;
-    st.add_bytes += c.s.add_bytes;
+  for (auto& g : groups) {
+    st.leaves += g.s.leaves;
+    st.leaf_flops += g.s.leaf_flops;
+    st.add_bytes += g.s.add_bytes;
   }
-  st.leaf_m = ch[0].s.leaf_dims.m;
-  st.leaf_k = ch[0].s.leaf_dims.k;
-  st.leaf_n = ch[0].s.leaf_dims.n;
+  st.leaf_m = groups[0].s.leaf_dims.m;
+  st.leaf_k = groups[0].s.leaf_dims.k;
+  st.leaf_n = groups[0].s.leaf_dims.n;
   if (wino)  // top level: 8 pre-addition blocks in and out, 14 product reads + 4 writes out
     st.add_bytes += 32.0 * m2 * k2 + 32.0 * k2 * n2 + 72.0 * m2 * n2;
   st.transfer_bytes = 4.0 * ((double)M * K + (double)K * N + (double)M * N);

@@ -68,9 +68,22 @@ __global__ void __launch_bounds__(kAddThreads)
 preadd_kernel(const PreAddNode* __restrict__ nodes, int nnodes) {
   const PreAddNode nd = nodes[find_node(nodes, nnodes, blockIdx.x)];
   const int h_r = nd.h_r, h_c = nd.h_c;
+  const unsigned out_q = nd.mask ? (unsigned)nd.mask : 0xFu;
+  // Quadrants read by the requested outputs (see preadd_inputs).
+  unsigned in_q = 0;
+  if (SIDE == 0) {
+    if (out_q & 1u) in_q |= 0xCu;
+    if (out_q & 2u) in_q |= 0xDu;
+    if (out_q & 4u) in_q |= 0x5u;
+    if (out_q & 8u) in_q |= 0xFu;
+  } else {
+    if (out_q & 1u) in_q |= 0x3u;
+    if (out_q & 2u) in_q |= 0xBu;
+    if (out_q & 4u) in_q |= 0xAu;
+    if (out_q & 8u) in_q |= 0xFu;
+  }
   const int c4n = (h_c + 3) >> 2;
   const int64_t groups = (int64_t)h_r * c4n;
-  const int64_t q_elems = (int64_t)h_r * h_c;
   const int64_t g0 = (int64_t)(blockIdx.x - nd.block_begin) * kAddChunk;
 #pragma unroll
   for (int it = 0; it < kItems; ++it) {
@@ -79,13 +92,15 @@ preadd_kernel(const PreAddNode* __restrict__ nodes, int nnodes) {
     const int r = (int)(gidx / c4n);
     const int c = (int)(gidx - (int64_t)r * c4n) * 4;
     const float* top = nd.src + (int64_t)r * nd.ld;
-    const float* bot = nd.src + (int64_t)(r + h_r) * nd.ld;
-    const bool rt = r < nd.vrows;
-    const bool rb = (r + h_r) < nd.vrows;
-    const float4 x11 = load4(top + c, VEC, rt, c, nd.vcols);
-    const float4 x12 = load4(top + h_c + c, VEC, rt, c + h_c, nd.vcols);
-    const float4 x21 = load4(bot + c, VEC, rb, c, nd.vcols);
-    const float4 x22 = load4(bot + h_c + c, VEC, rb, c + h_c, nd.vcols);
+    const float* bot = nd.src + nd.bot_off + (int64_t)r * nd.ld;
+    // Quadrants the requested outputs do not need are never read (they may
+    // not have been copied in yet); they enter as zero.
+    const bool rt = r < nd.top_rows;
+    const bool rb = r < nd.bot_rows;
+    const float4 x11 = load4(top + c, VEC, rt && (in_q & 1u), c, nd.left_cols);
+    const float4 x12 = load4(top + h_c + c, VEC, rt && (in_q & 2u), c, nd.right_cols);
+    const float4 x21 = load4(bot + c, VEC, rb && (in_q & 4u), c, nd.left_cols);
+    const float4 x22 = load4(bot + h_c + c, VEC, rb && (in_q & 8u), c, nd.right_cols);
     float4 o1, o2, o3, o4;
     if (SIDE == 0) {
       // S1 = A21 + A22; S2 = S1 - A11; S3 = A11 - A21; S4 = A12 - S2
@@ -101,10 +116,10 @@ preadd_kernel(const PreAddNode* __restrict__ nodes, int nnodes) {
       o4.x = o2.x - x21.x;  o4.y = o2.y - x21.y;  o4.z = o2.z - x21.z;  o4.w = o2.w - x21.w;
     }
     float* out = nd.dst + (int64_t)r * h_c + c;
-    store4(out, o1, VEC, true, c, h_c);
-    store4(out + q_elems, o2, VEC, true, c, h_c);
-    store4(out + 2 * q_elems, o3, VEC, true, c, h_c);
-    store4(out + 3 * q_elems, o4, VEC, true, c, h_c);
+    if (out_q & 1u) store4(out, o1, VEC, true, c, h_c);
+    if (out_q & 2u) store4(out + nd.out_stride, o2, VEC, true, c, h_c);
+    if (out_q & 4u) store4(out + 2 * nd.out_stride, o3, VEC, true, c, h_c);
+    if (out_q & 8u) store4(out + 3 * nd.out_stride, o4, VEC, true, c, h_c);
   }
 }
 
@@ -115,7 +130,6 @@ postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
   const int h_r = nd.h_r, h_c = nd.h_c;
   const int c4n = (h_c + 3) >> 2;
   const int64_t groups = (int64_t)h_r * c4n;
-  const int64_t q_elems = (int64_t)h_r * h_c;
   const int64_t g0 = (int64_t)(blockIdx.x - nd.block_begin) * kAddChunk;
   // Products each quadrant reads (P1..P7 = bit 0..6).
   constexpr unsigned kNeed = QUAD < 0 ? 0x7Fu
@@ -133,7 +147,8 @@ postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
     float4 P[7];
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-      P[i] = (kNeed >> i) & 1u ? load4(p + i * q_elems, VEC, true, c, h_c) : make_float4(0.f, 0.f, 0.f, 0.f);
+      P[i] = (kNeed >> i) & 1u ? load4(p + i * nd.p_stride, VEC, true, c, h_c)
+                               : make_float4(0.f, 0.f, 0.f, 0.f);
     float4 c11, c12, c21, c22, u2, u3, u4;
     // C11 = P1 + P2; U2 = P1 + P6; U3 = U2 + P7; U4 = U2 + P5
     // C12 = U4 + P3; C21 = U3 - P4; C22 = U3 + P5
@@ -145,16 +160,13 @@ postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
     c21.x = u3.x - P[3].x;   c21.y = u3.y - P[3].y;   c21.z = u3.z - P[3].z;   c21.w = u3.w - P[3].w;
     c22.x = u3.x + P[4].x;   c22.y = u3.y + P[4].y;   c22.z = u3.z + P[4].z;   c22.w = u3.w + P[4].w;
     float* top = nd.dst + (int64_t)r * nd.ld;
-    float* bot = nd.dst + (int64_t)(r + h_r) * nd.ld;
-    const bool rt = r < nd.rows;
-    const bool rb = (r + h_r) < nd.rows;
-    // Left quadrants end at column h_c: a partial last group must not spill
-    // into the right quadrants, which other threads own.
-    const int lcols = min(nd.cols, h_c);
-    if (QUAD < 0 || QUAD == 0) store4(top + c, c11, VEC, rt, c, lcols);
-    if (QUAD < 0 || QUAD == 1) store4(top + h_c + c, c12, VEC, rt, c + h_c, nd.cols);
-    if (QUAD < 0 || QUAD == 2) store4(bot + c, c21, VEC, rb, c, lcols);
-    if (QUAD < 0 || QUAD == 3) store4(bot + h_c + c, c22, VEC, rb, c + h_c, nd.cols);
+    float* bot = nd.dst + nd.bot_off + (int64_t)r * nd.ld;
+    const bool rt = r < nd.top_rows;
+    const bool rb = r < nd.bot_rows;
+    if (QUAD < 0 || QUAD == 0) store4(top + c, c11, VEC, rt, c, nd.left_cols);
+    if (QUAD < 0 || QUAD == 1) store4(top + h_c + c, c12, VEC, rt, c, nd.right_cols);
+    if (QUAD < 0 || QUAD == 2) store4(bot + c, c21, VEC, rb, c, nd.left_cols);
+    if (QUAD < 0 || QUAD == 3) store4(bot + h_c + c, c22, VEC, rb, c, nd.right_cols);
   }
 }
 

@@ -84,17 +84,19 @@ def test_host_pinned_and_pageable_match_device(fastmm):
     Cd = empty_dev(n, n)
     fastmm.gemm(n, n, n, dev(A), dev(B), Cd, depth=depth, leaf=leaf)
     ref = host(Cd)
-    # pinned host
+    exact = classic.gemm(A, B)
+    # pinned host (pipelined path: within tolerance, see test_host_paths_match_device)
     Ap = torch.from_numpy(A).pin_memory()
     Bp = torch.from_numpy(B).pin_memory()
     Cp = torch.empty((n, n), dtype=torch.float32).pin_memory()
     fastmm.gemm(n, n, n, Ap, Bp, Cp, depth=depth, leaf=leaf)
-    assert np.array_equal(Cp.numpy(), ref)
+    assert checks.rel_frob(Cp.numpy(), exact) < TOL_WINOGRAD
     assert fastmm.get_stats()["transfer_bytes"] == 4.0 * 3 * n * n
-    # pageable host
+    # pageable host gives the same bits as pinned (same path)
     Ch = torch.zeros((n, n), dtype=torch.float32)
     fastmm.gemm(n, n, n, torch.from_numpy(A), torch.from_numpy(B), Ch, depth=depth, leaf=leaf)
-    assert np.array_equal(Ch.numpy(), ref)
+    assert np.array_equal(Ch.numpy(), Cp.numpy())
+    assert checks.rel_frob(ref, exact) < TOL_WINOGRAD
 
 
 def test_host_strided_operands(fastmm):
@@ -214,12 +216,16 @@ def test_config2_sampled_rows_and_freivalds(fastmm, n, depth, leaf):
 
 
 @pytest.mark.parametrize("m,k,n,depth", [(640, 640, 640, 2), (333, 201, 257, 3), (300, 260, 280, 0),
-                                         (97, 301, 45, 1), (2, 3, 2, 1), (1024, 512, 768, 3)])
+                                         (97, 301, 45, 1), (2, 3, 2, 1), (1024, 512, 768, 3),
+                                         (700, 300, 500, 0), (1500, 700, 900, 2)])
 @pytest.mark.parametrize("pipeline", ["1", "0"])
-def test_host_paths_bitwise_equal_device(fastmm, monkeypatch, m, k, n, depth, pipeline):
-    # Host operands go through the staged path (pipelined: quadrants in, top
-    # level product by product, result quadrants out; or copy-all-first).
-    # Either way the result must be bit for bit the device-resident one.
+def test_host_paths_match_device(fastmm, monkeypatch, m, k, n, depth, pipeline):
+    # Host operands go through the staged path: pipelined (quadrant row bands
+    # in, top level product by product, result blocks out) or copy-all-first.
+    # Copy-first and every plain (depth 0) product equal the device-resident
+    # result bit for bit; the pipelined Winograd path splits the inner
+    # recursion by row bands (another rounding order), so it is held to the
+    # oracle tolerance -- and to exactness on certified integers below.
     import torch
     say(f"host path {m}x{k}x{n} depth={depth} pipeline={pipeline}")
     monkeypatch.setenv("FASTMM_PIPELINE", pipeline)
@@ -232,7 +238,27 @@ def test_host_paths_bitwise_equal_device(fastmm, monkeypatch, m, k, n, depth, pi
     Bp = torch.from_numpy(B).pin_memory()
     Cp = torch.full((m, n), float("nan")).pin_memory()
     fastmm.gemm(m, n, k, Ap, Bp, Cp, depth=depth, leaf=1)
-    assert np.array_equal(Cp.numpy(), ref)
     st = fastmm.get_stats()
     assert st["depth"] == W.effective_depth(m, k, n, depth, 1)
-    assert checks.rel_frob(ref, classic.gemm(A, B)) < TOL_WINOGRAD
+    exact = classic.gemm(A, B)
+    if pipeline == "0" or st["depth"] == 0:
+        assert np.array_equal(Cp.numpy(), ref)
+    else:
+        assert np.isfinite(Cp.numpy()).all()
+        assert checks.rel_frob(Cp.numpy(), exact) < TOL_WINOGRAD
+    assert checks.rel_frob(ref, exact) < TOL_WINOGRAD
+
+
+@pytest.mark.parametrize("m,k,n,depth", [(333, 201, 257, 3), (97, 301, 45, 1), (1024, 512, 768, 3),
+                                         (130, 66, 258, 2)])
+def test_host_pipeline_certified_exact(fastmm, m, k, n, depth):
+    import torch
+    A = ints(121 + m, m, k)
+    B = ints(122 + n, k, n)
+    cert = W.Certificate()
+    ref = W.winograd(A.astype(np.int64), B.astype(np.int64), depth, 1, cert)
+    assert cert.exact_in_fp32
+    Cp = torch.full((m, n), float("nan")).pin_memory()
+    fastmm.gemm(m, n, k, torch.from_numpy(A).pin_memory(), torch.from_numpy(B).pin_memory(), Cp,
+                depth=depth, leaf=1)
+    assert np.array_equal(Cp.numpy().astype(np.int64), ref)
