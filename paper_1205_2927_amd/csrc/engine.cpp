@@ -117,8 +117,11 @@ char* ensure_arena(Library& L, size_t bytes) {
     L.arena = nullptr;
     L.arena_bytes = 0;
   }
-  // Grow geometrically to avoid reallocating on every slightly larger call.
-  size_t want = std::max(bytes, std::min(bytes + bytes / 4, free_b));
+  // Grow geometrically to avoid reallocating on every slightly larger call,
+  // but leave a margin of free memory to the rest of the process.
+  const size_t margin = std::min<size_t>(free_b / 16, size_t(2) << 30);
+  const size_t room = free_b + L.arena_bytes > margin ? free_b + L.arena_bytes - margin : 0;
+  size_t want = std::max(bytes, std::min(bytes + bytes / 4, room));
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, want);
   if (e != hipSuccess) {
@@ -499,6 +502,146 @@ double ev_ms(hipEvent_t a, hipEvent_t b) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Workspace scheduler: level-wise when the whole tree's temporaries fit the
+// budget, otherwise depth-first at the top: one level's S, T and P blocks are
+// kept and the seven sub-products run one after another in the remaining
+// space (each again level-wise if it fits, else depth-first), as the paper's
+// recursion fits each call to the device capacity it finds (Section 3.3).
+
+namespace {
+
+size_t placeholder_desc_bytes(const Problem& p) {
+  Problem q = p;
+  q.A = q.B = reinterpret_cast<const float*>(256);
+  q.C = const_cast<float*>(q.A);
+  Schedule s;
+  build_schedule({q}, reinterpret_cast<char*>(256), s);
+  return align_up(schedule_desc_bytes(s), 256) + 256;
+}
+
+size_t bfs_need(const Problem& p) {
+  return align_up(problem_temp_bytes(p), 256) + placeholder_desc_bytes(p);
+}
+
+size_t top_need(const Problem& p) {
+  const int64_t m2 = half_up(p.M), k2 = half_up(p.K), n2 = half_up(p.N);
+  return align_up((size_t)4 * m2 * k2 * 4, 256) + align_up((size_t)4 * k2 * n2 * 4, 256) +
+         align_up((size_t)7 * m2 * n2 * 4, 256) + 3 * 256;
+}
+
+// Sub-product i (P1..P7 = 0..6) of p, with p's S, T and P blocks at S, T, P.
+Problem child_problem(const Problem& p, int i, float* S, float* T, float* P) {
+  const int64_t m2 = half_up(p.M), k2 = half_up(p.K), n2 = half_up(p.N);
+  const View a{p.A, p.lda, p.ar(), p.ac()}, b{p.B, p.ldb, p.br(), p.bc()};
+  auto sv = [&](int j) { return View{S + j * m2 * k2, k2, m2, k2}; };
+  auto tv = [&](int j) { return View{T + j * k2 * n2, n2, k2, n2}; };
+  const View ca[7] = {quadrant(a, 0, 0, m2, k2), quadrant(a, 0, 1, m2, k2), sv(3),
+                      quadrant(a, 1, 1, m2, k2), sv(0), sv(1), sv(2)};
+  const View cb[7] = {quadrant(b, 0, 0, k2, n2), quadrant(b, 1, 0, k2, n2),
+                      quadrant(b, 1, 1, k2, n2), tv(3), tv(0), tv(1), tv(2)};
+  Problem c;
+  c.M = m2;
+  c.K = k2;
+  c.N = n2;
+  c.A = ca[i].p;
+  c.lda = ca[i].ld;
+  c.a_rows = ca[i].vrows;
+  c.a_cols = ca[i].vcols;
+  c.B = cb[i].p;
+  c.ldb = cb[i].ld;
+  c.b_rows = cb[i].vrows;
+  c.b_cols = cb[i].vcols;
+  c.C = P + i * m2 * n2;
+  c.ldc = n2;
+  c.depth = p.depth - 1;
+  c.tile = p.tile;
+  return c;
+}
+
+// Smallest workspace the product can run in (level-wise or depth-first).
+size_t min_need(const Problem& p) {
+  const size_t b = bfs_need(p);
+  if (p.depth == 0) return b;
+  return std::min(b, top_need(p) + min_need(child_problem(p, 0, nullptr, nullptr, nullptr)));
+}
+
+struct RunTotals {
+  int64_t leaves = 0;
+  double leaf_flops = 0, add_bytes = 0;
+  int launches = 0, leaf_launches = 0, schedules = 0;
+  Dims leaf_dims{0, 0, 0};
+};
+
+// Enqueue p inside [ws, ws + bytes).  Each level-wise piece is followed by a
+// stream synchronisation, so the one pinned descriptor buffer can be reused.
+void run_within(Library& L, const Problem& p, char* ws, size_t bytes, RunTotals& rt) {
+  const size_t need = bfs_need(p);
+  if (need <= bytes) {
+    const size_t t = align_up(problem_temp_bytes(p), 256);
+    char* host = ensure_pinned(L, need - t);
+    Schedule s;
+    build_schedule({p}, ws, s);
+    rt.launches += enqueue_schedule(L, s, ws + t, host);
+    FASTMM_HIP(hipStreamSynchronize(L.stream));
+    rt.leaves += s.leaves;
+    rt.leaf_flops += s.leaf_flops;
+    rt.add_bytes += s.add_bytes;
+    rt.leaf_dims = s.leaf_dims;
+    for (int k = 0; k < kNumTiles; ++k) rt.leaf_launches += s.leaf_tiles_total[k] > 0 ? 1 : 0;
+    ++rt.schedules;
+    return;
+  }
+  if (p.depth == 0 || top_need(p) >= bytes)
+    throw Error(kOutOfMemory, "workspace budget too small even for depth-first execution");
+  const int64_t m2 = half_up(p.M), k2 = half_up(p.K), n2 = half_up(p.N);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* q = ws + off;
+    off += align_up(b, 256);
+    return q;
+  };
+  float* S = reinterpret_cast<float*>(take((size_t)4 * m2 * k2 * 4));
+  float* T = reinterpret_cast<float*>(take((size_t)4 * k2 * n2 * 4));
+  float* P = reinterpret_cast<float*>(take((size_t)7 * m2 * n2 * 4));
+  char* dnodes = take(3 * 256);
+  char* host = ensure_pinned(L, 3 * 256);
+  const PreAddNode na = preadd_node(p.A, p.lda, p.ar(), p.ac(), m2, k2, S);
+  const PreAddNode nb = preadd_node(p.B, p.ldb, p.br(), p.bc(), k2, n2, T);
+  const PostAddNode np = postadd_node(P, m2, n2, p.C, p.ldc, p.cr(), p.cc());
+  std::memcpy(host, &na, sizeof(na));
+  std::memcpy(host + 256, &nb, sizeof(nb));
+  std::memcpy(host + 512, &np, sizeof(np));
+  FASTMM_HIP(hipMemcpyAsync(dnodes, host, 3 * 256, hipMemcpyHostToDevice, L.stream));
+  launch_preadd(0, reinterpret_cast<const PreAddNode*>(dnodes), 1,
+                (int)add_blocks_for(m2, k2), pre_vec_ok(na), L.stream);
+  launch_preadd(1, reinterpret_cast<const PreAddNode*>(dnodes + 256), 1,
+                (int)add_blocks_for(k2, n2), pre_vec_ok(nb), L.stream);
+  FASTMM_HIP(hipStreamSynchronize(L.stream));  // the pinned block is reused below
+  rt.launches += 2;
+  for (int i = 0; i < 7; ++i) run_within(L, child_problem(p, i, S, T, P), ws + off, bytes - off, rt);
+  std::memcpy(host + 512, &np, sizeof(np));
+  FASTMM_HIP(hipMemcpyAsync(dnodes + 512, host + 512, sizeof(np), hipMemcpyHostToDevice, L.stream));
+  launch_postadd(reinterpret_cast<const PostAddNode*>(dnodes + 512), 1,
+                 (int)add_blocks_for(m2, n2), post_vec_ok(np), L.stream);
+  FASTMM_HIP(hipStreamSynchronize(L.stream));
+  rt.launches += 1;
+  rt.add_bytes += 32.0 * m2 * k2 + 32.0 * k2 * n2 + 44.0 * m2 * n2;
+}
+
+// Device memory the library may use: FASTMM_WORKSPACE_LIMIT if set, else the
+// free memory plus the current workspace, less a safety margin.
+size_t workspace_budget(Library& L) {
+  if (const char* s = std::getenv("FASTMM_WORKSPACE_LIMIT")) return std::strtoull(s, nullptr, 10);
+  size_t free_b = 0, total_b = 0;
+  FASTMM_HIP(hipMemGetInfo(&free_b, &total_b));
+  const size_t avail = free_b + L.arena_bytes;
+  const size_t margin = std::min<size_t>(avail / 16, size_t(2) << 30);
+  return avail - margin;
+}
+
+}  // namespace
+
 void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
                int tile) {
@@ -533,7 +676,8 @@ void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
 
   const char* pipe = std::getenv("FASTMM_PIPELINE");
   const bool pipelined = !(pipe && pipe[0] == '0');
-  if (!on_dev && pipelined && std::min(std::min(M, N), K) >= 2) {
+  if (!on_dev && pipelined && std::min(std::min(M, N), K) >= 2 &&
+      pipelined_need(M, N, K, p.depth, tile) <= workspace_budget(L)) {
     gemm_host_pipelined(L, M, N, K, A, lda, B, ldb, C, ldc, p.depth, tile, st);
     if (!L.profiling) {
       st.h2d_ms = st.preadd_ms = st.leaf_ms = st.postadd_ms = st.d2h_ms = st.total_ms = -1.0;
@@ -547,6 +691,52 @@ void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
   const size_t b_bytes = on_dev ? 0 : align_up((size_t)K * N * 4, 256);
   const size_t c_bytes = on_dev ? 0 : align_up((size_t)M * N * 4, 256);
   const size_t t_bytes = align_up(problem_temp_bytes(p), 256);
+
+  // Over budget: depth-first execution of the top levels.
+  if (K > 0 && p.depth > 0) {
+    const size_t stage = a_bytes + b_bytes + c_bytes;
+    const size_t budget = workspace_budget(L);
+    if (stage + bfs_need(p) > budget) {
+      const size_t need = stage + min_need(p);
+      if (need > budget)
+        throw Error(kOutOfMemory, "workspace of " + std::to_string(need) +
+                                      " bytes (depth-first) exceeds the budget of " +
+                                      std::to_string(budget) + " (FASTMM_WORKSPACE_LIMIT or free memory)");
+      char* ws = ensure_arena(L, budget);
+      float* dA = on_dev ? const_cast<float*>(A) : reinterpret_cast<float*>(ws);
+      float* dB = on_dev ? const_cast<float*>(B) : reinterpret_cast<float*>(ws + a_bytes);
+      float* dC = on_dev ? C : reinterpret_cast<float*>(ws + a_bytes + b_bytes);
+      if (!on_dev) {
+        FASTMM_HIP(hipMemcpy2DAsync(dA, K * 4, A, lda * 4, K * 4, M, hipMemcpyHostToDevice, L.stream));
+        FASTMM_HIP(hipMemcpy2DAsync(dB, N * 4, B, ldb * 4, N * 4, K, hipMemcpyHostToDevice, L.stream));
+      }
+      p.A = dA;
+      p.B = dB;
+      p.C = dC;
+      p.lda = on_dev ? lda : K;
+      p.ldb = on_dev ? ldb : N;
+      p.ldc = on_dev ? ldc : N;
+      RunTotals rt;
+      run_within(L, p, ws + stage, budget - stage, rt);
+      if (!on_dev)
+        FASTMM_HIP(hipMemcpy2DAsync(C, ldc * 4, dC, N * 4, N * 4, M, hipMemcpyDeviceToHost, L.stream));
+      FASTMM_HIP(hipStreamSynchronize(L.stream));
+      st.depth = p.depth;
+      st.tile = tile;
+      st.leaves = rt.leaves;
+      st.leaf_m = rt.leaf_dims.m;
+      st.leaf_k = rt.leaf_dims.k;
+      st.leaf_n = rt.leaf_dims.n;
+      st.leaf_flops = rt.leaf_flops;
+      st.add_bytes = rt.add_bytes;
+      st.transfer_bytes = on_dev ? 0.0 : 4.0 * ((double)M * K + (double)K * N + (double)M * N);
+      st.launches = rt.launches;
+      st.leaf_launches = rt.leaf_launches;
+      st.workspace_bytes = L.arena_bytes;
+      L.stats = st;
+      return;
+    }
+  }
 
   // Schedule with temporaries at a placeholder base to size the descriptors.
   Schedule s;

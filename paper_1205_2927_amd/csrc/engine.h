@@ -131,6 +131,8 @@ size_t schedule_desc_bytes(const Schedule& s);
 // Host-resident operands: stage quadrants in, run the top level of the
 // recursion product by product as the quadrants arrive, and stream result
 // quadrants out as they complete (pipeline.cpp).
+// Workspace bytes the pipelined path needs for this product.
+size_t pipelined_need(int64_t M, int64_t N, int64_t K, int depth, int tile);
 void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const float* A,
                          int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
                          int depth, int tile, fastmm_stats_t& st);

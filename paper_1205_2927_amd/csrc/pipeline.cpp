@@ -93,6 +93,19 @@ std::vector<Band> make_bands(int64_t m2, int64_t mb, int nb, int64_t align) {
 
 }  // namespace
 
+namespace {
+size_t g_dry_need = 0;
+}
+
+size_t pipelined_need(int64_t M, int64_t N, int64_t K, int depth, int tile) {
+  Library dummy;
+  fastmm_stats_t st{};
+  g_dry_need = 0;
+  gemm_host_pipelined(dummy, M, N, K, nullptr, 0, nullptr, 0, nullptr, 0, depth, tile, st);
+  return g_dry_need;
+}
+
+// With L.initialised false (pipelined_need), only sizes the workspace.
 void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const float* A,
                          int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
                          int depth, int tile, fastmm_stats_t& st) {
@@ -296,6 +309,10 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   }
   const size_t oTemp = take(temp_max);
   const size_t oDesc = take(desc_total);
+  if (!L.initialised) {  // sizing only
+    g_dry_need = off;
+    return;
+  }
 
   ws = ensure_arena(L, off);
   char* host = ensure_pinned(L, desc_total);

@@ -262,3 +262,36 @@ def test_host_pipeline_certified_exact(fastmm, m, k, n, depth):
     fastmm.gemm(m, n, k, torch.from_numpy(A).pin_memory(), torch.from_numpy(B).pin_memory(), Cp,
                 depth=depth, leaf=1)
     assert np.array_equal(Cp.numpy().astype(np.int64), ref)
+
+
+def test_depth_first_fallback_bitwise(fastmm, monkeypatch):
+    # A workspace cap below the level-wise need: the scheduler runs the top
+    # levels depth first (same tree, same arithmetic), so the result must be
+    # bit for bit the level-wise one; below the depth-first minimum it must
+    # report OUT_OF_MEMORY with C untouched.
+    import torch
+    n, depth, leaf = 1024, 3, 32
+    A = dev(uniform(131, n, n))
+    B = dev(uniform(132, n, n))
+    C0 = empty_dev(n, n)
+    monkeypatch.delenv("FASTMM_WORKSPACE_LIMIT", raising=False)
+    fastmm.gemm(n, n, n, A, B, C0, depth=depth, leaf=leaf)
+    ref = host(C0)
+    bfs_launches = fastmm.get_stats()["launches"]
+    ok = 0
+    for limit in [80_000_000, 50_000_000, 35_000_000, 28_000_000, 22_000_000, 18_000_000,
+                  14_000_000, 10_000_000]:
+        monkeypatch.setenv("FASTMM_WORKSPACE_LIMIT", str(limit))
+        C = torch.full((n, n), 7.0, device="cuda")
+        rc = fastmm.gemm_raw(n, n, n, A.data_ptr(), n, B.data_ptr(), n, C.data_ptr(), n, depth, leaf)
+        if rc == fastmm.ERROR_OUT_OF_MEMORY:
+            assert torch.all(C == 7.0).item()
+            break
+        assert rc == fastmm.SUCCESS, fastmm.last_error()
+        st = fastmm.get_stats()
+        say(f"  limit {limit}: launches {st['launches']} (level-wise {bfs_launches})")
+        assert st["depth"] == depth and st["leaves"] == 343
+        assert np.array_equal(host(C), ref)
+        if st["launches"] > bfs_launches:
+            ok += 1
+    assert ok >= 2
