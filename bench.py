@@ -24,12 +24,12 @@ sys.path.insert(0, ROOT)
 METRIC = "effective GFLOPS (2MNK/wall-clock) n=19456 FP32 Winograd vs plain MFMA SGEMM"
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per leaf launch (pipelined depth-3 launch of 49 leaves of
-# 2432^3) from the FETCH_SIZE and WRITE_SIZE counter runs, each scaled by the
-# reading of a 1 GiB calibration copy (fetch x2.000, write x1.000); see
-# profiles/leaf_gemm_n19456_d3_pinned_hbm_traffic.md.  Valid for
-# leaf_gemm_kernel<128,128,16> at that configuration only.
-TRAFFIC_BYTES_PER_LAUNCH = 5063520.5 * 1024 * 2.000 + 1132096.0 * 1024 * 1.000
+# HBM bytes per leaf launch (pipelined depth-3 call: 14 launches of 49 leaves
+# of 1280 or 1152 x 2432 x 2432) from the FETCH_SIZE and WRITE_SIZE counter
+# runs, each scaled by its reading for a 1 GiB calibration copy (fetch x2.000,
+# write x1.000); see profiles/leaf_gemm_n19456_d3_pinned_hbm_traffic.md.
+# Valid for leaf_gemm_kernel<128,128,16,2,2> in that configuration only.
+TRAFFIC_BYTES_PER_LAUNCH = 2776785.1875 * 1024 * 2.000 + 566048.0 * 1024 * 1.000
 
 
 def log(msg):
@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-device-context", action="store_true")
+    ap.add_argument("--resident", action="store_true",
+                    help="operands in device memory (no transfers): profiling the device path")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -96,6 +98,10 @@ def main():
     synthgen.fill_uniform_pm1(1001 + 3, M, K, A.data_ptr())
     synthgen.fill_uniform_pm1(2001 + 3, K, N, B.data_ptr())
     flops = 2.0 * M * N * K
+    if args.resident:
+        # Device-path profiling: the same inputs, resident in HBM.
+        A, B = A.to("cuda"), B.to("cuda")
+        C = torch.empty((M, N), dtype=torch.float32, device="cuda")
 
     fastmm.set_profiling(True)
 
@@ -149,9 +155,9 @@ def main():
     # Parity of the last result: sampled rows + Freivalds against the oracle
     # (the oracle is the checker; the timed path never touches it).
     from oracle import checks
-    An = A.numpy()
-    Bn = B.numpy()
-    Cn = C.numpy()
+    An = A.cpu().numpy()
+    Bn = B.cpu().numpy()
+    Cn = C.cpu().numpy()
     rows = synthgen.row_sample(7004, M, 8)
     parity = {"sampled_rows_rel": checks.sampled_rows_rel(Cn, An, Bn, rows),
               "freivalds_rel": checks.freivalds_rel(Cn, An, Bn, synthgen.signs_pm1(7005, N)),
@@ -165,16 +171,18 @@ def main():
     avg_launch = leaf_sum / n_launch
     flops_launch = st["leaf_flops"] / n_launch
     leaf_tflops = flops_launch / (avg_launch * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": "leaf_gemm_kernel<128,128,16> (grouped leaves)",
+    roofline = {"bound": "mfma", "kernel": "leaf_gemm_kernel<128,128,16,2,2> (grouped leaves)",
                 "achieved": leaf_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": leaf_tflops / PEAK_FP32_TFLOPS, "traffic": TRAFFIC_BYTES_PER_LAUNCH,
+                "frac": leaf_tflops / PEAK_FP32_TFLOPS,
+                "traffic": TRAFFIC_BYTES_PER_LAUNCH if (best == 3 and n == 19456 and args.tile == 0
+                                                        and args.leaf == 1024) else None,
                 "flops_per_launch": flops_launch, "avg_launch_ms": avg_launch,
                 "launches_per_step": n_launch}
 
     # Context: the same product with device-resident operands (level-wise
     # path, no transfers), with the addition kernels timed separately.
     dev_ctx = None
-    if not args.no_device_context:
+    if not args.no_device_context and not args.resident:
         dA = A.to("cuda")
         dB = B.to("cuda")
         dC = torch.empty((M, N), dtype=torch.float32, device="cuda")
@@ -225,8 +233,10 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"FP32 Winograd-Strassen C=A*B, square n={n}, pinned host in/out "
-                               f"(transfers timed), depth {st['depth']}, leaf {args.leaf}",
+        "config": {"workload": f"FP32 Winograd-Strassen C=A*B, square n={n}, "
+                               + ("device-resident operands" if args.resident else
+                                  "pinned host in/out (transfers timed)")
+                               + f", depth {st['depth']}, leaf {args.leaf}",
                    "M": M, "N": N, "K": K, "depth": st["depth"], "leaf": args.leaf,
                    "tile": args.tile, "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu,
