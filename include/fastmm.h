@@ -69,7 +69,13 @@ enum {
   FASTMM_TILE_128x128_K32 = 4, /* 128x128, K-slabs of 32 */
   FASTMM_TILE_256x128_W8 = 5,  /* 256x128 on 8 wavefronts */
   FASTMM_TILE_256x256_W8 = 6,  /* 256x256 on 8 wavefronts */
-  FASTMM_TILE_128x256 = 7
+  FASTMM_TILE_128x256 = 7,
+  /* Precision form of the leaf, never chosen by the planner: 128x128 tiles in
+   * split-BF16 arithmetic (each FP32 operand as hi + lo BF16, products
+   * hi*hi + hi*lo + lo*hi accumulated in FP32 on the BF16 matrix cores):
+   * about 2^-16 relative accuracy per product instead of FP32's 2^-24.  The
+   * quadrant additions stay FP32. */
+  FASTMM_TILE_BF16X3_128x128 = 8
 };
 
 typedef struct {

@@ -169,7 +169,8 @@ enum TileId {
   kTile256x128w8 = 5,   // 8 wavefronts
   kTile256x256w8 = 6,   // 8 wavefronts
   kTile128x256 = 7,
-  kNumTiles = 8,
+  kTileBf16x3 = 8,      // 128x128, split-BF16 arithmetic (precision form)
+  kNumTiles = 9,
 };
 
 struct TileShape {
@@ -186,6 +187,7 @@ inline TileShape tile_shape(int id) {
     case kTile256x128w8: return {256, 128};
     case kTile256x256w8: return {256, 256};
     case kTile128x256: return {128, 256};
+    case kTileBf16x3: return {128, 128};
     default: throw Error(kInvalidValue, "unknown tile id " + std::to_string(id));
   }
 }
@@ -193,6 +195,8 @@ inline TileShape tile_shape(int id) {
 // Kernel launchers (stream-ordered, no synchronisation).
 void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
                       hipStream_t stream);
+void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
+                        hipStream_t stream);
 void launch_preadd(int side, const PreAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
                    hipStream_t stream);
 // quad < 0: all four result quadrants; 0..3: only C11, C12, C21 or C22

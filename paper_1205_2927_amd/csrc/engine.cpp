@@ -324,6 +324,7 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
   }
   s.leaf_tiles_total.assign(kNumTiles, 0);
   for (int t = 0; t < kNumTiles; ++t) {
+    s.vec_leaf[t] = true;
     const TileShape ts = tile_shape(t);
     int64_t total = 0;
     for (auto& g : s.leaf[t]) {

@@ -66,7 +66,7 @@ struct Schedule {
   std::vector<const PreAddNode*> d_preA, d_preB;
   std::vector<const PostAddNode*> d_post;
   const GemmDesc* d_leaf[kNumTiles] = {};
-  bool vec_leaf[kNumTiles] = {true, true, true, true, true, true, true, true};
+  bool vec_leaf[kNumTiles] = {};  // set in build_schedule
   int max_depth = 0;
   size_t temp_bytes = 0;  // bytes of S, T and P temporaries
   // statistics

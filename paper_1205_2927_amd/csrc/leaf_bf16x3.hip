@@ -1,0 +1,266 @@
+// Leaf product in split BF16 arithmetic ("bf16x3") on the BF16 matrix cores.
+//
+// Each FP32 operand element x is split into two BF16 numbers, hi = bf16(x)
+// and lo = bf16(x - hi) (round to nearest even), so that x = hi + lo up to a
+// relative 2^-17.  The product a*b is taken as hi_a*hi_b + hi_a*lo_b +
+// lo_a*hi_b (the lo*lo term, relative 2^-16, is dropped) with every term
+// accumulated in FP32 by v_mfma_f32_32x32x16_bf16 (Henry, Tang and Heinecke,
+// "Leveraging the bfloat16 Artificial Intelligence Datatype For
+// Higher-Precision Computations", ARITH 2019).  The result is accurate to
+// about 2^-16 relative per product, not FP32's 2^-24; it is a precision form
+// of the leaf, selected explicitly, never substituted for the FP32 leaf.
+//
+// Tiling mirrors the FP32 leaf kernel (128x128 macro tile, 4 wavefronts of
+// 64x64, grouped launch with the same descriptors and XCD-aware walk) with
+// K-slabs of 32: global FP32 loads (branch-free buffer loads, zero outside
+// the valid extent) are split in registers and stored to LDS as hi and lo
+// arrays with k contiguous ([m][k] for A, [n][k] for B), so one 16-byte LDS
+// read gives the 8 consecutive k a lane supplies to a 32x32x16 step.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace fastmm {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc16(const float* p, int bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  float* q = reinterpret_cast<float*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, __builtin_amdgcn_readfirstlane(bytes),
+                                           0x00020000);
+}
+
+// BF16 bits of x rounded to nearest even (finite inputs).
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+
+// hi and lo halves of four values.
+__device__ __forceinline__ void split4(float4 v, u16x4& hi, u16x4& lo) {
+  const float x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const unsigned short h = bf16_rne(x[i]);
+    hi[i] = h;
+    lo[i] = bf16_rne(x[i] - bf16_to_f32(h));
+  }
+}
+
+}  // namespace
+
+template <bool VEC>
+__global__ void __launch_bounds__(256)
+leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles) {
+  constexpr int BM = 128, BN = 128, BK = 32;
+  constexpr int WM = 64, WN = 64, FM = 2, FN = 2;
+  constexpr int LDK = BK + 8;  // bf16 elements per LDS row (80 bytes: conflict-free 16-byte reads)
+  constexpr int kThreads = 256;
+
+  __shared__ __attribute__((aligned(16))) unsigned short Ah[2][BM * LDK], Al[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) unsigned short Bh[2][BN * LDK], Bl[2][BN * LDK];
+
+  // Tile of this workgroup: the same XCD remap and grouped walk as the FP32 leaf.
+  const int nb = gridDim.x, bid = blockIdx.x;
+  const int xcd = bid & 7, q8 = nb >> 3, r8 = nb & 7;
+  const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + (bid >> 3);
+  if (logical >= total_tiles) return;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= logical) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc& d = descs[lo];
+  const float* __restrict__ A = d.A;
+  const float* __restrict__ B = d.B;
+  float* __restrict__ C = d.C;
+  const int64_t lda = d.lda, ldb = d.ldb, ldc = d.ldc;
+  const int a_rows = d.a_rows, b_cols = d.b_cols, kmax = d.kmax;
+  const int c_rows = d.c_rows, c_cols = d.c_cols;
+  const int tiles_n = d.tiles_n;
+  const int tiles_m = (c_rows + BM - 1) / BM;
+  const int lt = logical - d.tile_begin;
+  constexpr int GROUP = 8;
+  const int group_tiles = GROUP * tiles_n;
+  const int g = lt / group_tiles;
+  const int first_m = g * GROUP;
+  const int gm = min(tiles_m - first_m, GROUP);
+  const int in_g = lt - g * group_tiles;
+  const int tm = (first_m + in_g % gm) * BM;
+  const int tn = (in_g / gm) * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int lr = lane & 31, lh = lane >> 5;
+
+  // A: thread loads rows a_r + 32 i (i = 0..3), columns a_c..a_c+3.
+  const int a_r = tid / 8, a_c = (tid % 8) * 4;
+  // B: thread loads rows b_k..b_k+3, columns b_n..b_n+3.
+  const int b_k = (tid / 32) * 4, b_n = (tid % 32) * 4;
+
+  const int rv = min(BM, a_rows - tm);
+  const int cv = min(BN, b_cols - tn);
+  const float* a_tile = A + (int64_t)tm * lda;
+  const float* b_tile = B + tn;
+  constexpr int kOOB = 0x7FFFFFF0;
+
+  float4 ra[4], rb[4];
+  auto load_slab = [&](int k0) {
+    const int kv = min(BK, kmax - k0);
+    const uint32_t a_bytes =
+        (rv > 0 && kv > 0) ? (uint32_t)(((int64_t)(rv - 1) * lda + kv) * 4) : 0u;
+    const uint32_t b_bytes =
+        (cv > 0 && kv > 0) ? (uint32_t)(((int64_t)(kv - 1) * ldb + cv) * 4) : 0u;
+    const __amdgpu_buffer_rsrc_t ar = make_rsrc16(a_tile + k0, (int)a_bytes);
+    const __amdgpu_buffer_rsrc_t br = make_rsrc16(b_tile + (int64_t)k0 * ldb, (int)b_bytes);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = a_r + 32 * i;
+      const int base = (r * (int)lda + a_c) * 4;
+      if (VEC) {
+        const int off = (r < rv && a_c < kv) ? base : kOOB;
+        ra[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(ar, off, 0, 0));
+      } else {
+        float e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int off = (r < rv && a_c + q < kv) ? base + 4 * q : kOOB;
+          e[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ar, off, 0, 0));
+        }
+        ra[i] = make_float4(e[0], e[1], e[2], e[3]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = b_k + i;
+      const int base = (k * (int)ldb + b_n) * 4;
+      if (VEC) {
+        const int off = (k < kv && b_n < cv) ? base : kOOB;
+        rb[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(br, off, 0, 0));
+      } else {
+        float e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int off = (k < kv && b_n + q < cv) ? base + 4 * q : kOOB;
+          e[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(br, off, 0, 0));
+        }
+        rb[i] = make_float4(e[0], e[1], e[2], e[3]);
+      }
+    }
+  };
+
+  auto store_slab = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      u16x4 h, l;
+      split4(ra[i], h, l);
+      const int o = (a_r + 32 * i) * LDK + a_c;
+      *reinterpret_cast<u16x4*>(&Ah[buf][o]) = h;
+      *reinterpret_cast<u16x4*>(&Al[buf][o]) = l;
+    }
+    // B: the four k of column b_n + c go to row b_n + c of the [n][k] arrays.
+    u16x4 h[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) split4(rb[i], h[i], l[i]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      u16x4 hc, lc;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        hc[i] = h[i][c];
+        lc[i] = l[i][c];
+      }
+      const int o = (b_n + c) * LDK + b_k;
+      *reinterpret_cast<u16x4*>(&Bh[buf][o]) = hc;
+      *reinterpret_cast<u16x4*>(&Bl[buf][o]) = lc;
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int nk = (kmax + BK - 1) / BK;
+  if (nk > 0) {
+    load_slab(0);
+    store_slab(0);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) load_slab((kt + 1) * BK);
+#pragma unroll
+    for (int g16 = 0; g16 < BK / 16; ++g16) {
+      // Lane half h supplies k = 16 g16 + 8 h + e (e = 0..7) for both operands.
+      const int kb = g16 * 16 + lh * 8;
+      bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int o = (wm + 32 * i + lr) * LDK + kb;
+        ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[cur][o]);
+        al[i] = *reinterpret_cast<const bf16x8*>(&Al[cur][o]);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int o = (wn + 32 * j + lr) * LDK + kb;
+        bh[j] = *reinterpret_cast<const bf16x8*>(&Bh[cur][o]);
+        bl[j] = *reinterpret_cast<const bf16x8*>(&Bl[cur][o]);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    if (more) store_slab(cur ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: register r of block (i, j) holds row 8*(r/4) + 4*(lane/32) + r%4
+  // and column lane%32 of that 32x32 block.
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = tn + wn + 32 * j + lr;
+      if (col >= c_cols) continue;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = tm + wm + 32 * i + 8 * (r >> 2) + 4 * lh + (r & 3);
+        if (row < c_rows) C[(int64_t)row * ldc + col] = acc[i][j][r];
+      }
+    }
+}
+
+void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
+                        hipStream_t stream) {
+  if (total_tiles <= 0) return;
+  dim3 grid(total_tiles), block(256);
+  if (vec)
+    hipLaunchKernelGGL((leaf_bf16x3_kernel<true>), grid, block, 0, stream, d_descs, ndesc, total_tiles);
+  else
+    hipLaunchKernelGGL((leaf_bf16x3_kernel<false>), grid, block, 0, stream, d_descs, ndesc, total_tiles);
+  FASTMM_HIP(hipGetLastError());
+}
+
+}  // namespace fastmm

@@ -269,6 +269,7 @@ void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_ti
     case kTile256x128w8: launch_t<256, 128, 16, 4, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
     case kTile256x256w8: launch_t<256, 256, 16, 2, 4>(d_descs, ndesc, total_tiles, vec, stream); break;
     case kTile128x256: launch_t<128, 256, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
+    case kTileBf16x3: launch_leaf_bf16x3(d_descs, ndesc, total_tiles, vec, stream); break;
     default: throw Error(kInvalidValue, "unknown tile id");
   }
 }
