@@ -124,6 +124,17 @@ int fastmm_gemm_ex(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                    const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
                    int tile);
 
+/* C = A*B by the paper's classic recursion (Table 1): eight sub-products per
+ * level over the quadrant split of equation (1), the second product of each
+ * result quadrant accumulated (C += AB), down to the same stop rule as
+ * fastmm_gemm (depth >= 0 levels, leaf cutoff; leaf = 3008 is the paper's
+ * recursion point 6016, Section 3.1).  A comparator: it performs all 2MNK
+ * flops.  Leaves run on the MFMA kernel `tile`, one grouped launch per
+ * reduction chunk (2^depth launches).  Arguments, residency and errors as
+ * fastmm_gemm. */
+int fastmm_rmul(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf, int tile);
+
 /* count independent products C[i] = A[i]*B[i], each with its own extents and
  * leading dimensions (same rules as fastmm_gemm, per problem).  depth == NULL:
  * each problem's depth/tile from the planner (mode set by

@@ -28,7 +28,7 @@ struct GemmDesc {
   int32_t c_rows, c_cols;   // extent of C that is written
   int32_t tiles_n;          // ceil(c_cols / BN) for the launch's tile shape
   int32_t tile_begin;       // first tile of this problem within the launch
-  int32_t pad_;
+  int32_t beta;             // 0: C = A B; 1: C += A B
 };
 
 // One node of a pre-addition launch: reads the four quadrants of a parent

@@ -89,6 +89,7 @@ leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tile
   const int a_rows = d.a_rows, b_cols = d.b_cols, kmax = d.kmax;
   const int c_rows = d.c_rows, c_cols = d.c_cols;
   const int tiles_n = d.tiles_n;
+  const int beta = d.beta;
   const int tiles_m = (c_rows + BM - 1) / BM;
   const int lt = logical - d.tile_begin;
   constexpr int GROUP = 8;
@@ -247,7 +248,10 @@ leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tile
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = tm + wm + 32 * i + 8 * (r >> 2) + 4 * lh + (r & 3);
-        if (row < c_rows) C[(int64_t)row * ldc + col] = acc[i][j][r];
+        if (row < c_rows) {
+          float* cp = C + (int64_t)row * ldc + col;
+          *cp = beta ? *cp + acc[i][j][r] : acc[i][j][r];
+        }
       }
     }
 }

@@ -33,7 +33,7 @@ MLP_PARAMS = 4609
 
 # Every symbol include/fastmm.h declares.
 EXPORTS = [
-    "fastmm_gemm", "fastmm_gemm_ex", "fastmm_gemm_batched", "fastmm_plan",
+    "fastmm_gemm", "fastmm_gemm_ex", "fastmm_rmul", "fastmm_gemm_batched", "fastmm_plan",
     "fastmm_set_plan_mode", "fastmm_planner_load", "fastmm_planner_save",
     "fastmm_planner_train", "fastmm_planner_records", "fastmm_set_stream",
     "fastmm_set_profiling", "fastmm_get_stats", "fastmm_get_last_error", "fastmm_finalize",
@@ -93,6 +93,7 @@ def load(path: str | None = None):
     sig = {
         "fastmm_gemm": [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, i64],
         "fastmm_gemm_ex": [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, i64, i32],
+        "fastmm_rmul": [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, i64, i32],
         "fastmm_gemm_batched": [i32, P64, P64, P64, vp, P64, vp, P64, vp, P64, vp, vp],
         "fastmm_plan": [i64, i64, i64, i32, ctypes.POINTER(Plan)],
         "fastmm_set_plan_mode": [i32],
@@ -160,6 +161,12 @@ def gemm(M, N, K, A, B, C, depth=0, leaf=1024, tile=None, lda=None, ldb=None, ld
                                 _ld(C, ldc), int(depth), int(leaf), int(tile))
     _check(rc)
     return rc
+
+
+def rmul(M, N, K, A, B, C, depth=0, leaf=3008, tile=TILE_128x128, lda=None, ldb=None, ldc=None):
+    """fastmm_rmul: C = A B by the classic 8-product recursion (comparator)."""
+    _check(load().fastmm_rmul(M, N, K, _ptr(A), _ld(A, lda), _ptr(B), _ld(B, ldb), _ptr(C),
+                              _ld(C, ldc), int(depth), int(leaf), int(tile)))
 
 
 def gemm_raw(M, N, K, A, lda, B, ldb, C, ldc, depth, leaf, tile=None) -> int:
