@@ -50,8 +50,18 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return xcd * q + (xcd < r ? xcd : r) + (bid >> 3);
 }
 
+// Occupancy: waves whose accumulators fit in 64 registers are asked to fit
+// four per SIMD (all operands in 128 registers), which hides the per-slab
+// barrier better than the three the register allocator would otherwise give.
+// (The element-wise load variant needs a few more registers and is left to
+// the allocator.)
+template <int BM, int BN, int WGM, int WGN, bool VEC>
+constexpr int leaf_waves_per_simd() {
+  return VEC && (BM / WGM / 32) * (BN / WGN / 32) <= 4 ? 4 : 1;
+}
+
 template <int BM, int BN, int BK, int WGM, int WGN, bool VEC>
-__global__ void __launch_bounds__(64 * WGM * WGN)
+__global__ void __launch_bounds__(64 * WGM * WGN, (leaf_waves_per_simd<BM, BN, WGM, WGN, VEC>()))
 leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles) {
   constexpr int kThreads = 64 * WGM * WGN;  // WGM x WGN wavefronts of 64
   constexpr int WM = BM / WGM, WN = BN / WGN;  // wave sub-tile
