@@ -51,6 +51,50 @@ def time_calls(fn, steps, warmup):
     return time.perf_counter() - t0, times
 
 
+def batched_context(fastmm, torch):
+    """256 independent products with M, N, K log-uniform in [256, 6144]
+    (multiples of 64), device-resident, uniform[-1, 1) inputs: one
+    fastmm_gemm_batched call (each problem's plan from the default rule;
+    replayed from its HIP graph after the first call) against the same
+    products issued one fastmm_gemm call at a time, and against the batched
+    plain product (depth 0)."""
+    import synthgen
+    shapes = synthgen.shapes_loguniform(3001, 256, lo=256, hi=6144)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5001)
+    As, Bs, Cs = [], [], []
+    for m, n, k in shapes.tolist():
+        As.append(torch.rand((m, k), device="cuda", generator=g) * 2 - 1)
+        Bs.append(torch.rand((k, n), device="cuda", generator=g) * 2 - 1)
+        Cs.append(torch.empty((m, n), device="cuda"))
+    flops = float(sum(2.0 * m * n * k for m, n, k in shapes.tolist()))
+    fastmm.set_plan_mode(fastmm.PLAN_DEFAULT)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return best
+
+    t_b = timed(lambda: fastmm.gemm_batched(As, Bs, Cs), 3)
+    st = fastmm.get_stats()
+    t_plain = timed(lambda: fastmm.gemm_batched(As, Bs, Cs, depth=[0] * len(As)), 3)
+
+    def singles():
+        for (m, n, k), A, B, C in zip(shapes.tolist(), As, Bs, Cs):
+            fastmm.gemm(m, n, k, A, B, C, depth=-1)
+    t_s = timed(singles, 1)
+    return {"problems": len(As), "flops": flops, "ms": 1e3 * t_b, "TFLOPS": flops / t_b / 1e12,
+            "graph_replayed": st["graph_replayed"], "launches": st["launches"],
+            "plain_batched_ms": 1e3 * t_plain, "plain_batched_TFLOPS": flops / t_plain / 1e12,
+            "single_calls_ms": 1e3 * t_s, "single_calls_TFLOPS": flops / t_s / 1e12}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +108,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-device-context", action="store_true")
+    ap.add_argument("--no-shards", action="store_true",
+                    help="skip one GPU's share of the sharded product")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 256-problem batched context (uneven shapes)")
     ap.add_argument("--resident", action="store_true",
                     help="operands in device memory (no transfers): profiling the device path")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -164,6 +212,22 @@ def main():
               "rows": int(rows.size), "tolerance": 1e-4}
     log(f"bench: parity {parity}")
 
+    # One GPU's share of the column-panel sharding (the paper's two-device
+    # split, eqs. (3)-(4), generalised): 1 x 8 panels (19456 x 19456 x 2432)
+    # and a 2 x 4 grid (9728 x 19456 x 4864), staged from the same pinned
+    # host operands (strided views), planner's default plan.
+    shards = None
+    if n == 19456 and not args.resident and not args.no_shards:
+        shards = {}
+        for name, (sm, sn) in {"panel_1x8": (M, N // 8), "grid_2x4": (M // 2, N // 4)}.items():
+            fn = lambda: fastmm.gemm(sm, sn, K, A[:sm], B[:, :sn], C[:sm, :sn], depth=-1,
+                                     leaf=args.leaf)
+            tot, ts = time_calls(fn, 3, 1)
+            sst = fastmm.get_stats()
+            shards[name] = {"M": sm, "N": sn, "K": K, "depth": sst["depth"], "ms": 1e3 * min(ts),
+                            "effective_GFLOPS": 2.0 * sm * sn * K / min(ts) / 1e9}
+        log(f"bench: shard shapes {shards}")
+
     # Dominant kernel: the grouped leaf GEMM.  Its launches are timed with
     # HIP events recorded by the library on the stream it launches them on.
     n_launch = max(1, st["leaf_launches"])
@@ -203,9 +267,24 @@ def main():
                    "add_GBps": sd["add_bytes"] / (add_ms * 1e-3) / 1e9 if add_ms > 0 else None,
                    "add_frac_of_hbm_peak": (sd["add_bytes"] / (add_ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
                    if add_ms > 0 else None}
+        # The paper's own algorithm: the classic eight-product recursion of
+        # Table 1 with its recursion point (leaves below 6016, i.e. leaf
+        # cutoff 3008), MFMA leaves, same operands.
+        fastmm.rmul(M, N, K, dA, dB, dC, depth=8, leaf=3008)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fastmm.rmul(M, N, K, dA, dB, dC, depth=8, leaf=3008)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t
+        dev_ctx["classic_recursion"] = {"ms": 1e3 * t, "effective_GFLOPS": flops / t / 1e9,
+                                        "depth": fastmm.get_stats()["depth"], "leaf": 3008}
         del dA, dB, dC
         torch.cuda.empty_cache()
         log(f"bench: device-resident context {dev_ctx}")
+    batched = None
+    if not args.no_batched and not args.resident:
+        batched = batched_context(fastmm, torch)
+        log(f"bench: batched context {batched}")
     phases = {"h2d_span_ms": float(np.mean(h2d_ms)), "leaf_ms": leaf_sum,
               "add_bytes": st["add_bytes"], "transfer_bytes": st["transfer_bytes"]}
 
@@ -243,7 +322,7 @@ def main():
         "plain_sgemm": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms_per_step) if plain else None,
         "depth_probe_ms": {str(k): 1e3 * v for k, v in probe.items()},
-        "phases": phases, "device_resident": dev_ctx, "parity": parity,
+        "phases": phases, "device_resident": dev_ctx, "batched": batched, "shards": shards, "parity": parity,
     }
     print(json.dumps(out), flush=True)
 

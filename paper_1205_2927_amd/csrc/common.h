@@ -192,11 +192,33 @@ inline TileShape tile_shape(int id) {
   }
 }
 
-// Kernel launchers (stream-ordered, no synchronisation).
+// Workgroup id -> logical tile of a grouped leaf launch.  The dispatcher
+// deals workgroups round-robin over the 8 XCDs (XCD = id % 8), each with its
+// own L2.  chunk == 0: each XCD gets one contiguous run of logical tiles (the
+// most L2 reuse, right when every tile costs the same).  chunk > 0: runs of
+// `chunk` consecutive tiles are dealt round-robin over the XCDs, so that
+// when tile costs differ (uneven products, ordered longest first) every XCD
+// gets the same mix, in the same order; ids past the last whole round keep
+// their own index.
+__device__ __forceinline__ int leaf_tile_of_block(int bid, int nblocks, int chunk) {
+  if (chunk <= 0) {
+    const int xcd = bid & 7;
+    const int q = nblocks >> 3;
+    const int r = nblocks & 7;
+    return xcd * q + (xcd < r ? xcd : r) + (bid >> 3);
+  }
+  const int span = 8 * chunk;
+  if (bid >= nblocks / span * span) return bid;
+  const int j = bid >> 3;
+  return ((j / chunk) * 8 + (bid & 7)) * chunk + j % chunk;
+}
+
+// Kernel launchers (stream-ordered, no synchronisation).  xcd_chunk: see
+// leaf_tile_of_block.
 void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
-                      hipStream_t stream);
+                      hipStream_t stream, int xcd_chunk = 0);
 void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
-                        hipStream_t stream);
+                        hipStream_t stream, int xcd_chunk = 0);
 void launch_preadd(int side, const PreAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
                    hipStream_t stream);
 // quad < 0: all four result quadrants; 0..3: only C11, C12, C21 or C22

@@ -326,6 +326,16 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
   for (int t = 0; t < kNumTiles; ++t) {
     s.vec_leaf[t] = true;
     const TileShape ts = tile_shape(t);
+    // Leaves of different reduction lengths (a batch of uneven products):
+    // dispatch the longest tiles first and deal tiles to the XCDs in small
+    // round-robin runs, so that no XCD is left with the long tail.
+    auto& lv = s.leaf[t];
+    s.xcd_chunk[t] = 0;
+    for (auto& g : lv)
+      if (g.kmax != lv[0].kmax) s.xcd_chunk[t] = 8;
+    if (s.xcd_chunk[t])
+      std::stable_sort(lv.begin(), lv.end(),
+                       [](const GemmDesc& a, const GemmDesc& b) { return a.kmax > b.kmax; });
     int64_t total = 0;
     for (auto& g : s.leaf[t]) {
       g.tile_begin = (int32_t)total;
@@ -401,7 +411,8 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
   if (leaf_begin) FASTMM_HIP(hipEventRecord(leaf_begin, L.stream));
   for (int t = 0; t < kNumTiles; ++t) {
     if (s.leaf_tiles_total[t] > 0) {
-      launch_leaf_gemm(t, s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t], L.stream);
+      launch_leaf_gemm(t, s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t],
+                       L.stream, s.xcd_chunk[t]);
       ++launches;
     }
   }

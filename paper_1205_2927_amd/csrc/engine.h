@@ -67,6 +67,7 @@ struct Schedule {
   std::vector<const PostAddNode*> d_post;
   const GemmDesc* d_leaf[kNumTiles] = {};
   bool vec_leaf[kNumTiles] = {};  // set in build_schedule
+  int xcd_chunk[kNumTiles] = {};  // leaf launch tile -> XCD mapping (leaf_tile_of_block)
   int max_depth = 0;
   size_t temp_bytes = 0;  // bytes of S, T and P temporaries
   // statistics

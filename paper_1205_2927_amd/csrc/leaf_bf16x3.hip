@@ -62,7 +62,7 @@ __device__ __forceinline__ void split4(float4 v, u16x4& hi, u16x4& lo) {
 
 template <bool VEC>
 __global__ void __launch_bounds__(256)
-leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles) {
+leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles, int xcd_chunk) {
   constexpr int BM = 128, BN = 128, BK = 32;
   constexpr int WM = 64, WN = 64, FM = 2, FN = 2;
   constexpr int LDK = BK + 8;  // bf16 elements per LDS row (80 bytes: conflict-free 16-byte reads)
@@ -71,10 +71,8 @@ leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tile
   __shared__ __attribute__((aligned(16))) unsigned short Ah[2][BM * LDK], Al[2][BM * LDK];
   __shared__ __attribute__((aligned(16))) unsigned short Bh[2][BN * LDK], Bl[2][BN * LDK];
 
-  // Tile of this workgroup: the same XCD remap and grouped walk as the FP32 leaf.
-  const int nb = gridDim.x, bid = blockIdx.x;
-  const int xcd = bid & 7, q8 = nb >> 3, r8 = nb & 7;
-  const int logical = xcd * q8 + (xcd < r8 ? xcd : r8) + (bid >> 3);
+  // Tile of this workgroup: the same XCD mapping and grouped walk as the FP32 leaf.
+  const int logical = leaf_tile_of_block(blockIdx.x, gridDim.x, xcd_chunk);
   if (logical >= total_tiles) return;
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
@@ -257,13 +255,13 @@ leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tile
 }
 
 void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
-                        hipStream_t stream) {
+                        hipStream_t stream, int xcd_chunk) {
   if (total_tiles <= 0) return;
   dim3 grid(total_tiles), block(256);
   if (vec)
-    hipLaunchKernelGGL((leaf_bf16x3_kernel<true>), grid, block, 0, stream, d_descs, ndesc, total_tiles);
+    hipLaunchKernelGGL((leaf_bf16x3_kernel<true>), grid, block, 0, stream, d_descs, ndesc, total_tiles, xcd_chunk);
   else
-    hipLaunchKernelGGL((leaf_bf16x3_kernel<false>), grid, block, 0, stream, d_descs, ndesc, total_tiles);
+    hipLaunchKernelGGL((leaf_bf16x3_kernel<false>), grid, block, 0, stream, d_descs, ndesc, total_tiles, xcd_chunk);
   FASTMM_HIP(hipGetLastError());
 }
 

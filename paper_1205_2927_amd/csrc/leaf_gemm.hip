@@ -41,15 +41,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const float* p, int 
                                            0x00020000);
 }
 
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
-  // Blocks bid, bid+8, ... run on XCD bid%8; give each XCD a contiguous run
-  // of logical tiles.
-  const int xcd = bid & 7;
-  const int q = nblocks >> 3;
-  const int r = nblocks & 7;
-  return xcd * q + (xcd < r ? xcd : r) + (bid >> 3);
-}
-
 // Occupancy: waves whose accumulators fit in 64 registers are asked to fit
 // four per SIMD (all operands in 128 registers), which hides the per-slab
 // barrier better than the three the register allocator would otherwise give.
@@ -62,7 +53,7 @@ constexpr int leaf_waves_per_simd() {
 
 template <int BM, int BN, int BK, int WGM, int WGN, bool VEC>
 __global__ void __launch_bounds__(64 * WGM * WGN, (leaf_waves_per_simd<BM, BN, WGM, WGN, VEC>()))
-leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles) {
+leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles, int xcd_chunk) {
   constexpr int kThreads = 64 * WGM * WGN;  // WGM x WGN wavefronts of 64
   constexpr int WM = BM / WGM, WN = BN / WGN;  // wave sub-tile
   constexpr int FM = WM / 32, FN = WN / 32; // 32x32 blocks per wave
@@ -76,7 +67,7 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles)
   __shared__ __attribute__((aligned(16))) float As[2][BM * LDA];
   __shared__ __attribute__((aligned(16))) float Bs[2][BK * LDB];
 
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int logical = leaf_tile_of_block(blockIdx.x, gridDim.x, xcd_chunk);
   if (logical >= total_tiles) return;
 
   // Which problem owns this tile (tile_begin is ascending).
@@ -262,28 +253,28 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles)
 }
 
 template <int BM, int BN, int BK, int WGM, int WGN>
-static void launch_t(const GemmDesc* d, int ndesc, int total, bool vec, hipStream_t s) {
+static void launch_t(const GemmDesc* d, int ndesc, int total, bool vec, hipStream_t s, int xc) {
   if (total <= 0) return;
   dim3 grid(total), block(64 * WGM * WGN);
   if (vec)
-    hipLaunchKernelGGL((leaf_gemm_kernel<BM, BN, BK, WGM, WGN, true>), grid, block, 0, s, d, ndesc, total);
+    hipLaunchKernelGGL((leaf_gemm_kernel<BM, BN, BK, WGM, WGN, true>), grid, block, 0, s, d, ndesc, total, xc);
   else
-    hipLaunchKernelGGL((leaf_gemm_kernel<BM, BN, BK, WGM, WGN, false>), grid, block, 0, s, d, ndesc, total);
+    hipLaunchKernelGGL((leaf_gemm_kernel<BM, BN, BK, WGM, WGN, false>), grid, block, 0, s, d, ndesc, total, xc);
   FASTMM_HIP(hipGetLastError());
 }
 
 void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
-                      hipStream_t stream) {
+                      hipStream_t stream, int xcd_chunk) {
   switch (tile) {
-    case kTile128x128: launch_t<128, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTile256x128: launch_t<256, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTile128x64: launch_t<128, 64, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTile64x64: launch_t<64, 64, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTile128x128k32: launch_t<128, 128, 32, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTile256x128w8: launch_t<256, 128, 16, 4, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTile256x256w8: launch_t<256, 256, 16, 2, 4>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTile128x256: launch_t<128, 256, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream); break;
-    case kTileBf16x3: launch_leaf_bf16x3(d_descs, ndesc, total_tiles, vec, stream); break;
+    case kTile128x128: launch_t<128, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
+    case kTile256x128: launch_t<256, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
+    case kTile128x64: launch_t<128, 64, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
+    case kTile64x64: launch_t<64, 64, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
+    case kTile128x128k32: launch_t<128, 128, 32, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
+    case kTile256x128w8: launch_t<256, 128, 16, 4, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
+    case kTile256x256w8: launch_t<256, 256, 16, 2, 4>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
+    case kTile128x256: launch_t<128, 256, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
+    case kTileBf16x3: launch_leaf_bf16x3(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
     default: throw Error(kInvalidValue, "unknown tile id");
   }
 }
