@@ -4,8 +4,11 @@
 // thresholds found by experiment (Table 2 and the K0 / K1 operating points of
 // Section 3.2) and stops the recursion at a fixed size (Section 3.1).  Three
 // modes here:
-//   DEFAULT     the fixed rule: split while the leaf stays >= 1024, tile
-//               128x128 (the analogue of the paper's size thresholds);
+//   DEFAULT     the fixed rule: split while the leaf stays >= 1536, tile
+//               128x128 (the analogue of the paper's size thresholds and
+//               recursion point, set from measured Winograd-vs-classic
+//               crossovers on MI355X: the fastest depth leaves 1536..2432
+//               in every dimension for square n from 3072 to 19456);
 //   EXHAUSTIVE  time every candidate (depth, tile) on the device with
 //               device-resident operands, keep the fastest; every timing is
 //               a record of the timing database;
@@ -47,7 +50,7 @@ namespace {
 constexpr int kNParams = FASTMM_MLP_PARAMS;
 constexpr int64_t kMinLeaf = 128;   // smallest leaf extent a candidate may reach
 constexpr int kMaxDepth = 4;
-constexpr int64_t kDefaultLeaf = 1024;
+constexpr int64_t kDefaultLeaf = 1536;
 // Tiles the planner considers: one per macro-tile area (the area is the
 // model's tile feature), the best-measured variant of each.
 constexpr int kPlannerTiles[] = {kTile128x128, kTile128x64, kTile64x64, kTile256x128w8,

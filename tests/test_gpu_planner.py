@@ -64,10 +64,12 @@ def test_mlp_adam_matches_oracle(fastmm):
 
 
 def test_default_rule(fastmm):
-    p = fastmm.plan(19456, 19456, 19456, fastmm.PLAN_DEFAULT)
-    assert (p.depth, p.tile, p.source) == (4, 0, fastmm.PLAN_DEFAULT)
-    p = fastmm.plan(512, 512, 512, fastmm.PLAN_DEFAULT)
-    assert p.depth == 0
+    # deepest split whose leaf stays >= 1536 in every dimension
+    for n, d in [(19456, 3), (16384, 3), (8192, 2), (4096, 1), (3072, 1), (2048, 0), (512, 0)]:
+        p = fastmm.plan(n, n, n, fastmm.PLAN_DEFAULT)
+        assert (p.depth, p.leaf, p.tile, p.source) == (d, 1536, 0, fastmm.PLAN_DEFAULT), n
+    p = fastmm.plan(19456, 12288, 16384, fastmm.PLAN_DEFAULT)  # leaves 2432 x 1536 x 2048
+    assert p.depth == 3
 
 
 def test_exhaustive_model_regret_and_gain(fastmm, tmp_path):
