@@ -181,13 +181,26 @@ int64_t pow7(int l) {
 
 }  // namespace
 
+size_t b_tree_bytes(int64_t M, int64_t K, int64_t N, int depth) {
+  Problem p;
+  p.M = M;
+  p.K = K;
+  p.N = N;
+  p.depth = depth;
+  const auto dims = level_dims(p);
+  size_t floats = 0;
+  for (int l = 0; l < depth; ++l)
+    floats += align_up((size_t)pow7(l) * 4 * dims[l + 1].k * dims[l + 1].n, kAlignFloats);
+  return floats * sizeof(float);
+}
+
 size_t problem_temp_bytes(const Problem& p) {
   const auto dims = level_dims(p);
   size_t floats = 0;
   for (int l = 0; l < p.depth; ++l) {
     const Dims& c = dims[l + 1];
     floats += align_up((size_t)pow7(l) * 4 * c.m * c.k, kAlignFloats);
-    floats += align_up((size_t)pow7(l) * 4 * c.k * c.n, kAlignFloats);
+    if (!p.b_tree) floats += align_up((size_t)pow7(l) * 4 * c.k * c.n, kAlignFloats);
   }
   for (int l = 1; l <= p.depth; ++l)
     floats += align_up((size_t)pow7(l) * dims[l].m * dims[l].n, kAlignFloats);
@@ -214,20 +227,28 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     const auto dims = level_dims(p);
     const int d = p.depth;
     std::vector<View> Av{{p.A, p.lda, p.ar(), p.ac()}}, Bv{{p.B, p.ldb, p.br(), p.bc()}};
+    size_t t_off = 0;  // floats into p.b_tree
     // Pre-additions, level by level; the next level's operands are views
     // of this level's operands or of the new S / T blocks.
     for (int l = 0; l < d; ++l) {
       const Dims c = dims[l + 1];
       const int64_t nodes = pow7(l);
       float* S = carve((size_t)nodes * 4 * c.m * c.k);
-      float* T = carve((size_t)nodes * 4 * c.k * c.n);
+      float* T;
+      if (p.b_tree) {
+        T = p.b_tree + t_off;
+        t_off += align_up((size_t)nodes * 4 * c.k * c.n, kAlignFloats);
+      } else {
+        T = carve((size_t)nodes * 4 * c.k * c.n);
+      }
       std::vector<View> nA(7 * nodes), nB(7 * nodes);
       const int64_t sa = c.m * c.k, tb = c.k * c.n;
       for (int64_t x = 0; x < nodes; ++x) {
         const View& a = Av[x];
         const View& b = Bv[x];
         s.preA[l].push_back(preadd_node(a.p, a.ld, a.vrows, a.vcols, c.m, c.k, S + x * 4 * sa));
-        s.preB[l].push_back(preadd_node(b.p, b.ld, b.vrows, b.vcols, c.k, c.n, T + x * 4 * tb));
+        if (!p.b_tree_ready)
+          s.preB[l].push_back(preadd_node(b.p, b.ld, b.vrows, b.vcols, c.k, c.n, T + x * 4 * tb));
         const View a11 = quadrant(a, 0, 0, c.m, c.k), a12 = quadrant(a, 0, 1, c.m, c.k),
                    a22 = quadrant(a, 1, 1, c.m, c.k);
         const View b11 = quadrant(b, 0, 0, c.k, c.n), b21 = quadrant(b, 1, 0, c.k, c.n),
@@ -245,7 +266,7 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
       }
       Av.swap(nA);
       Bv.swap(nB);
-      s.add_bytes += (double)nodes * (32.0 * c.m * c.k + 32.0 * c.k * c.n);
+      s.add_bytes += (double)nodes * (32.0 * c.m * c.k + (p.b_tree_ready ? 0.0 : 32.0 * c.k * c.n));
     }
     // Product buffers P[l] (l = 1..d), 7^l blocks of m_l x n_l.
     std::vector<float*> P(d + 1, nullptr);

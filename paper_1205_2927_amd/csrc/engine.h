@@ -47,6 +47,13 @@ struct Problem {
   int64_t c_rows = -1, c_cols = -1;  // -1: M, N
   int depth = 0;  // effective depth
   int tile = 0;
+  // Optional home of the B-side temporaries (the T blocks of every level,
+  // b_tree_bytes of them) outside the schedule's workspace, so that several
+  // products with the same right operand can share them; with
+  // b_tree_ready they are taken as already computed and no B-side
+  // pre-additions are issued.
+  float* b_tree = nullptr;
+  bool b_tree_ready = false;
   int64_t ar() const { return a_rows < 0 ? M : a_rows; }
   int64_t ac() const { return a_cols < 0 ? K : a_cols; }
   int64_t br() const { return b_rows < 0 ? K : b_rows; }
@@ -78,8 +85,11 @@ struct Schedule {
   Dims leaf_dims{0, 0, 0};
 };
 
-// Bytes of temporaries a problem needs (no allocation).
+// Bytes of temporaries a problem needs in the schedule's workspace (no
+// allocation; without the B-side blocks when p.b_tree is set).
 size_t problem_temp_bytes(const Problem& p);
+// Bytes of the B-side temporaries of a product with these extents and depth.
+size_t b_tree_bytes(int64_t M, int64_t K, int64_t N, int depth);
 
 // Builds the schedule; temporaries are carved from `ws` (device), which must
 // hold at least the sum of problem_temp_bytes.

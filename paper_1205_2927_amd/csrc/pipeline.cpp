@@ -144,6 +144,14 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     for (int64_t r0 = 0; r0 < M; r0 += q) bands.push_back({r0, std::min(q, M - r0), 0});
   }
   const int nband = (int)bands.size();
+  // Both row bands of a top-level product share its right operand, so the
+  // B-side temporaries of the inner recursion are computed by the first band
+  // and reused by the second: one region per product, outside the
+  // temporaries the bands take in turn.
+  const size_t bt_each =
+      (wino && nband > 1) ? align_up(b_tree_bytes(1, k2, n2, depth - 1), 256) : 0;
+  const size_t oBT = bt_each ? take(7 * bt_each) : 0;
+  char* bt_base = reinterpret_cast<char*>(256);  // placeholder until allocation
 
   // Placeholder device pointers for sizing (real ones set after allocation).
   char* ws = nullptr;
@@ -195,6 +203,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     p.ldc = n2;
     p.depth = depth - 1;
     p.tile = tile;
+    if (bt_each) p.b_tree = reinterpret_cast<float*>(bt_base + i * bt_each);
     return p;
   };
   auto plain_problem = [&](const Band& b, int half) {
@@ -282,7 +291,13 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   auto build_groups = [&]() {
     groups.clear();
     if (wino) {
-      for (auto& pb : order) groups.push_back({{wino_problem(pb.first, bands[pb.second])}});
+      bool seen[7] = {};
+      for (auto& pb : order) {
+        Problem p = wino_problem(pb.first, bands[pb.second]);
+        p.b_tree_ready = bt_each && seen[pb.first];
+        seen[pb.first] = true;
+        groups.push_back({{p}});
+      }
     } else {
       for (auto& b : bands) groups.push_back({{plain_problem(b, 0)}});
       for (auto& b : bands) groups.push_back({{plain_problem(b, 1)}});
@@ -322,6 +337,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   S = reinterpret_cast<float*>(ws + oS);
   T = reinterpret_cast<float*>(ws + oT);
   P = reinterpret_cast<float*>(ws + oP);
+  bt_base = ws + oBT;
   char* temps = ws + oTemp;
   char* ddesc = ws + oDesc;
   {
