@@ -215,12 +215,12 @@ def main():
     # One GPU's share of the column-panel sharding (the paper's two-device
     # split, eqs. (3)-(4), generalised): 1 x 8 panels (19456 x 19456 x 2432)
     # and a 2 x 4 grid (9728 x 19456 x 4864), staged from the same pinned
-    # host operands (strided views), planner's default plan.
+    # host operands (strided views), as many levels as the leaf cutoff allows.
     shards = None
     if n == 19456 and not args.resident and not args.no_shards:
         shards = {}
         for name, (sm, sn) in {"panel_1x8": (M, N // 8), "grid_2x4": (M // 2, N // 4)}.items():
-            fn = lambda: fastmm.gemm(sm, sn, K, A[:sm], B[:, :sn], C[:sm, :sn], depth=-1,
+            fn = lambda: fastmm.gemm(sm, sn, K, A[:sm], B[:, :sn], C[:sm, :sn], depth=16,
                                      leaf=args.leaf)
             tot, ts = time_calls(fn, 3, 1)
             sst = fastmm.get_stats()
