@@ -153,11 +153,12 @@ inline void hip_check(hipError_t e, const char* what) {
 
 #define FASTMM_HIP(call) ::fastmm::hip_check((call), #call)
 
-// The leaf kernel addresses a tile's slab with 32-bit byte offsets relative
-// to the slab (at most 256 rows of A, 16 rows of B): these bounds keep every
-// offset below 2^31.
+// The leaf kernels address a tile's slab with 32-bit byte offsets relative
+// to the slab: at most 256 rows of A (255 * 2^21 * 4 < 2^31) and 32 rows of
+// B (31 * 2^24 * 4 < 2^31).  These bounds keep every offset and every slab
+// extent below 2^31.
 constexpr int64_t kMaxLeadingDimA = int64_t(1) << 21;
-constexpr int64_t kMaxLeadingDimB = int64_t(1) << 26;
+constexpr int64_t kMaxLeadingDimB = int64_t(1) << 24;
 
 // Leaf tile shapes (ids are part of the ABI: fastmm_plan_t.tile).
 enum TileId {

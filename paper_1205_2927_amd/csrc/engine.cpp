@@ -497,7 +497,7 @@ void validate_gemm_args(int64_t M, int64_t N, int64_t K, const float* A, int64_t
   if (ldc < std::max<int64_t>(1, N)) throw Error(kInvalidValue, "ldc < max(1, N)");
   if (depth > 16) throw Error(kInvalidValue, "depth > 16");
   if (lda > kMaxLeadingDimA || ldb > kMaxLeadingDimB)
-    throw Error(kNotSupported, "lda above 2^21 or ldb above 2^26 is not supported");
+    throw Error(kNotSupported, "lda above 2^21 or ldb above 2^24 is not supported");
   if (M > 0 && N > 0 && C == nullptr) throw Error(kInvalidValue, "C is NULL");
   if (M > 0 && K > 0 && A == nullptr) throw Error(kInvalidValue, "A is NULL");
   if (K > 0 && N > 0 && B == nullptr) throw Error(kInvalidValue, "B is NULL");
