@@ -57,7 +57,13 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
   constexpr int kThreads = 64 * WGM * WGN;  // WGM x WGN wavefronts of 64
   constexpr int WM = BM / WGM, WN = BN / WGN;  // wave sub-tile
   constexpr int FM = WM / 32, FN = WN / 32; // 32x32 blocks per wave
-  constexpr int LDA = BK + 4;               // LDS row stride of A ([m][k])
+  // A in LDS as [m][k].  With BK = 16 rows are unpadded and the 16-byte
+  // group g of row r is stored at group g ^ ((r >> 2) & 3): both the stores
+  // (16 lanes write 4 rows x 4 groups) and the fragment reads (16 lanes read
+  // 16 rows, one group) then touch 64 distinct banks.  Other BK: rows padded
+  // by 4 floats.
+  constexpr bool SWZ = BK == 16;
+  constexpr int LDA = SWZ ? BK : BK + 4;    // LDS row stride of A
   constexpr int LDB = BN + 8;               // LDS row stride of B ([k][n])
   constexpr int A_F4 = BM * BK / 4 / kThreads;  // float4 loads per thread
   constexpr int B_F4 = BK * BN / 4 / kThreads;
@@ -178,10 +184,13 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
     }
   };
 
+  auto a_slot = [&](int r, int c) {  // float offset of A[r][c..c+3] in a buffer
+    return r * LDA + (SWZ ? (((c >> 2) ^ ((r >> 2) & 3)) << 2) : c);
+  };
   auto store_slab = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < A_F4; ++i)
-      *reinterpret_cast<float4*>(&As[buf][a_r[i] * LDA + a_c[i]]) = ra[i];
+      *reinterpret_cast<float4*>(&As[buf][a_slot(a_r[i], a_c[i])]) = ra[i];
 #pragma unroll
     for (int i = 0; i < B_F4; ++i)
       *reinterpret_cast<float4*>(&Bs[buf][b_r[i] * LDB + b_c[i]]) = rb[i];
@@ -213,7 +222,7 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
       float4 af[FM];
 #pragma unroll
       for (int i = 0; i < FM; ++i)
-        af[i] = *reinterpret_cast<const float4*>(&as[(wm + 32 * i + lr) * LDA + kb]);
+        af[i] = *reinterpret_cast<const float4*>(&as[a_slot(wm + 32 * i + lr, kb)]);
       float bf[FN][4];
 #pragma unroll
       for (int j = 0; j < FN; ++j)
