@@ -64,14 +64,28 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
   // by 4 floats.
   constexpr bool SWZ = BK == 16;
   constexpr int LDA = SWZ ? BK : BK + 4;    // LDS row stride of A
-  constexpr int LDB = BN + 8;               // LDS row stride of B ([k][n])
+  // DTL: the vector path with BK = 16 loads both slabs straight into LDS
+  // (buffer loads with the LDS bit: each wave instruction fills 1 KB of LDS,
+  // lane i at byte 16 i), with no register staging and no LDS stores.  B is
+  // then kept unpadded as [k][n] with column bit 5 flipped on rows whose
+  // (k >> 2) is odd, so the two lane halves of a fragment read (rows k and
+  // k + 4) fall on different banks.
+  constexpr int kWaves = kThreads / 64;
+  constexpr bool DTL = VEC && SWZ && (BM / 16) % kWaves == 0 && (BN / 16) % kWaves == 0 &&
+                       BN >= 64 && 256 % BN == 0;
+  constexpr int LDB = DTL ? BN : BN + 8;    // LDS row stride of B ([k][n])
   constexpr int A_F4 = BM * BK / 4 / kThreads;  // float4 loads per thread
   constexpr int B_F4 = BK * BN / 4 / kThreads;
   static_assert(A_F4 >= 1 && B_F4 >= 1, "tile too small for 256 threads");
   static_assert(BK % 8 == 0, "BK must be a multiple of 8");
 
-  __shared__ __attribute__((aligned(16))) float As[2][BM * LDA];
-  __shared__ __attribute__((aligned(16))) float Bs[2][BK * LDB];
+  // Double-buffered slabs as four separate arrays.  With DTL the K loop is
+  // unrolled by two so that every access names its buffer statically: the
+  // compiler then knows that slab k + 1 landing in one buffer cannot alias
+  // the reads of slab k from the other, and does not wait for the in-flight
+  // loads before those reads.
+  __shared__ __attribute__((aligned(16))) float As0[BM * LDA], As1[BM * LDA];
+  __shared__ __attribute__((aligned(16))) float Bs0[BK * LDB], Bs1[BK * LDB];
 
   const int logical = leaf_tile_of_block(blockIdx.x, gridDim.x, xcd_chunk);
   if (logical >= total_tiles) return;
@@ -138,7 +152,36 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
   const float* b_tile = B + tn;
   constexpr int kOOB = 0x7FFFFFF0;
 
-  float4 ra[A_F4], rb[B_F4];
+  float4 ra[DTL ? 1 : A_F4], rb[DTL ? 1 : B_F4];
+
+  // Direct-to-LDS slab load into one buffer pair (DTL only).
+  auto load_slab_lds = [&](int k0, float* __restrict__ as_dst, float* __restrict__ bs_dst) {
+    const int kv = min(BK, kmax - k0);
+    const uint32_t a_bytes =
+        (rv > 0 && kv > 0) ? (uint32_t)(((int64_t)(rv - 1) * lda + kv) * 4) : 0u;
+    const uint32_t b_bytes =
+        (cv > 0 && kv > 0) ? (uint32_t)(((int64_t)(kv - 1) * ldb + cv) * 4) : 0u;
+    const __amdgpu_buffer_rsrc_t ar = make_rsrc(a_tile + k0, (int)a_bytes);
+    const __amdgpu_buffer_rsrc_t br = make_rsrc(b_tile + (int64_t)k0 * ldb, (int)b_bytes);
+#pragma unroll
+    for (int j = 0; j < BM / 16 / kWaves; ++j) {
+      const int q = j * kWaves + wave;            // 1 KB chunk: rows 16 q .. 16 q + 15
+      const int row = q * 16 + (lane >> 2);
+      const int g = (lane & 3) ^ ((row >> 2) & 3);  // global 16-byte group of this slot
+      const int off = (row < rv && 4 * g < kv) ? (row * (int)lda + 4 * g) * 4 : kOOB;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          ar, (__attribute__((address_space(3))) void*)&as_dst[q * 256], 16, off, 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < BN / 16 / kWaves; ++j) {
+      const int q = j * kWaves + wave;            // 1 KB chunk: 256 / BN rows of B
+      const int k = q * (256 / BN) + lane / (BN / 4);
+      const int g = (lane % (BN / 4)) ^ (((k >> 2) & 1) << 3);
+      const int off = (k < kv && 4 * g < cv) ? (k * (int)ldb + 4 * g) * 4 : kOOB;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          br, (__attribute__((address_space(3))) void*)&bs_dst[q * 256], 16, off, 0, 0, 0);
+    }
+  };
 
   auto load_slab = [&](int k0) {
     const int kv = min(BK, kmax - k0);  // valid k in this slab
@@ -187,13 +230,13 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
   auto a_slot = [&](int r, int c) {  // float offset of A[r][c..c+3] in a buffer
     return r * LDA + (SWZ ? (((c >> 2) ^ ((r >> 2) & 3)) << 2) : c);
   };
-  auto store_slab = [&](int buf) {
+  auto store_slab = [&](float* __restrict__ as_dst, float* __restrict__ bs_dst) {
 #pragma unroll
     for (int i = 0; i < A_F4; ++i)
-      *reinterpret_cast<float4*>(&As[buf][a_slot(a_r[i], a_c[i])]) = ra[i];
+      *reinterpret_cast<float4*>(&as_dst[a_slot(a_r[i], a_c[i])]) = ra[i];
 #pragma unroll
     for (int i = 0; i < B_F4; ++i)
-      *reinterpret_cast<float4*>(&Bs[buf][b_r[i] * LDB + b_c[i]]) = rb[i];
+      *reinterpret_cast<float4*>(&bs_dst[b_r[i] * LDB + b_c[i]]) = rb[i];
   };
 
   f32x16 acc[FM][FN];
@@ -206,16 +249,23 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
 
   const int nk = (kmax + BK - 1) / BK;
   if (nk > 0) {
-    load_slab(0);
-    store_slab(0);
+    if (DTL) {
+      load_slab_lds(0, As0, Bs0);
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the slab is in LDS
+    } else {
+      load_slab(0);
+      store_slab(As0, Bs0);
+    }
     __syncthreads();
   }
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
+  // One K-slab: prefetch slab kt + 1 into the other buffers, multiply slab kt.
+  auto step = [&](const float* __restrict__ as, const float* __restrict__ bs,
+                  float* __restrict__ as_next, float* __restrict__ bs_next, int kt) {
     const bool more = (kt + 1 < nk);
-    if (more) load_slab((kt + 1) * BK);
-    const float* as = As[cur];
-    const float* bs = Bs[cur];
+    if (more) {
+      if (DTL) load_slab_lds((kt + 1) * BK, as_next, bs_next);
+      else load_slab((kt + 1) * BK);
+    }
 #pragma unroll
     for (int g8 = 0; g8 < BK / 8; ++g8) {
       const int kb = g8 * 8 + lh * 4;
@@ -227,7 +277,10 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
 #pragma unroll
       for (int j = 0; j < FN; ++j)
 #pragma unroll
-        for (int s = 0; s < 4; ++s) bf[j][s] = bs[(kb + s) * LDB + wn + 32 * j + lr];
+        for (int s = 0; s < 4; ++s) {
+          const int k = kb + s, n = wn + 32 * j + lr;
+          bf[j][s] = bs[k * LDB + (DTL ? (n ^ (((k >> 2) & 1) << 5)) : n)];
+        }
 #pragma unroll
       for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -238,8 +291,22 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
             acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, bf[j][s], acc[i][j], 0, 0, 0);
         }
     }
-    if (more) store_slab(cur ^ 1);
+    if (more) {
+      if (DTL) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+      else store_slab(as_next, bs_next);
+    }
     __syncthreads();
+  };
+  if constexpr (DTL) {
+    for (int kt = 0; kt < nk; kt += 2) {
+      step(As0, Bs0, As1, Bs1, kt);
+      if (kt + 1 < nk) step(As1, Bs1, As0, Bs0, kt + 1);
+    }
+  } else {  // register staging: the stores wait for the loads anyway
+    for (int kt = 0; kt < nk; ++kt) {
+      const bool odd = kt & 1;
+      step(odd ? As1 : As0, odd ? Bs1 : Bs0, odd ? As0 : As1, odd ? Bs0 : Bs1, kt);
+    }
   }
 
   // Epilogue: register r of block (i, j) holds row 8*(r/4) + 4*(lane/32) + r%4
