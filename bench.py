@@ -29,7 +29,7 @@ PEAK_HBM_GBS = 8000.0
 # runs, each scaled by its reading for a 1 GiB calibration copy (fetch x2.000,
 # write x1.000); see profiles/leaf_gemm_n19456_d3_pinned_hbm_traffic.md.
 # Valid for leaf_gemm_kernel<128,128,16,2,2> in that configuration only.
-TRAFFIC_BYTES_PER_LAUNCH = 2655555.1 * 1024 * 2.000 + 566048.0 * 1024 * 1.000
+TRAFFIC_BYTES_PER_LAUNCH = 2669524.3 * 1024 * 2.000 + 576963.6 * 1024 * 1.000
 
 
 def log(msg):
