@@ -89,6 +89,22 @@ def test_leaf_ragged_certified_exact(fastmm, tile, m, k, n):
     assert np.array_equal(host(C).astype(np.int64), ref)
 
 
+@pytest.mark.parametrize("tile", [0, 1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("m,k,n", [(300, 1000, 260), (129, 36, 132), (1000, 4, 4),
+                                   (5, 20, 1028), (257, 132, 388)])
+def test_leaf_vector_path_ragged_exact(fastmm, tile, m, k, n):
+    # K and N multiples of 4 with aligned rows: the 16-byte load path (slabs
+    # loaded straight into LDS for 16-deep tiles), with partial tiles in M
+    # and N and a partial last K-slab, all zero-filled by the buffer loads.
+    say(f"leaf vector-path ragged {m}x{k}x{n} tile={tile}")
+    A = ints(43 + m, m, k, -2, 2)
+    B = ints(44 + n, k, n, -2, 2)
+    C = empty_dev(m, n)
+    fastmm.gemm(m, n, k, dev(A), dev(B), C, depth=0, tile=tile)
+    ref = classic.gemm(A.astype(np.int64), B.astype(np.int64))
+    assert np.array_equal(host(C).astype(np.int64), ref)
+
+
 def test_leaf_identity_bit_exact(fastmm):
     n = 384
     A = uniform(51, n, n)
