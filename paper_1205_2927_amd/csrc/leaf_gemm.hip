@@ -8,14 +8,16 @@
 // v_mfma_f32_32x32x2_f32 (FP32 inputs, FP32 accumulation).
 //
 // Grouped launch: all leaves of a level (and of every problem of a batch) are
-// one grid.  Workgroup ids are first remapped so that consecutive logical
-// tiles stay on one XCD (the dispatcher deals workgroups round-robin over the
-// 8 XCDs, each with its own L2), then tiles of a problem are walked in groups
-// of 8 tile-rows so that neighbours share A row-panels and B column-panels.
+// one grid.  Workgroup ids are first mapped to logical tiles with the XCDs in
+// mind (the dispatcher deals workgroups round-robin over the 8 XCDs, each with
+// its own L2; see leaf_tile_of_block), then tiles of a problem are walked in
+// groups of 8 tile-rows so that neighbours share A row-panels and B
+// column-panels.
 //
-// Data path per K-slab of BK:
-//   global -> registers (float4, prefetched one slab ahead)
-//   registers -> LDS (double buffered; A as [m][k], B as [k][n])
+// Data path per K-slab of BK (double-buffered in LDS, one slab ahead):
+//   16-byte vector tiles with BK = 16: global -> LDS directly (buffer loads
+//   with the LDS bit), A as [m][k] and B as [k][n], unpadded and swizzled;
+//   otherwise global -> registers -> LDS (A padded or swizzled, B padded).
 //   LDS -> MFMA operands: lane l of a 32x32x2 step supplies A[row l%32][k]
 //   and B[k][col l%32] with k chosen by the lane half l/32.  Over a slab the
 //   two halves take the k-indices 8g+4h+s (s = 0..3); the sum over k does not
