@@ -16,7 +16,7 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(fastmm_[a-z_]+)\s*\(", text)))
 
 
-def test_header_declares_the_three_north_star_calls():
+def test_header_declares_the_three_entry_points():
     names = declared_functions()
     for n in ("fastmm_gemm", "fastmm_gemm_batched", "fastmm_plan"):
         assert n in names

@@ -1,5 +1,5 @@
 """The learned planner: GPU network kernels against the FP64 oracle, the
-exhaustive autotuner, and the trained model judged by its regret against
+exhaustive autotuner, and the trained model evaluated by its regret against
 exhaustive timing and by what it gains over the fixed rule."""
 import numpy as np
 import pytest
