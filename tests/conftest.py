@@ -23,7 +23,7 @@ def gpu_available() -> bool:
 
 @pytest.fixture(scope="session")
 def fastmm():
-    """The GPU library binding.  On a GPU machine a missing build is an error,
+    """The GPU library binding.  On a machine with a GPU a missing build is an error,
     never a skip: the tests must exercise the native library."""
     from paper_1205_2927_amd import fastmm as fm
     fm.load()

@@ -67,5 +67,5 @@ def test_config4_depth2_sampled(fastmm, n):
         rows = synthgen.row_sample(7008, n, 12)
         e_rows = checks.sampled_rows_rel(got, A, B, rows)
         e_fv = checks.freivalds_rel(got, A, B, synthgen.signs_pm1(7009, n))
-        say(f"  config 4 {dist} n={n}: sampled-rows rel={e_rows:.3e} freivalds rel={e_fv:.3e}")
+        say(f"  split-BF16 {dist} n={n}: sampled-rows rel={e_rows:.3e} freivalds rel={e_fv:.3e}")
         assert e_rows <= 2e-4 and e_fv <= 2e-4
