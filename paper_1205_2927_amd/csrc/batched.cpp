@@ -51,7 +51,8 @@ std::string signature(const Schedule& s) {
       << ',' << blocks_pre(s.preB[l]) << ',' << (int)s.vec_preB[l] << ';';
   for (int t = 0; t < kNumTiles; ++t)
     o << "g" << t << (const void*)s.d_leaf[t] << ',' << s.leaf[t].size() << ','
-      << s.leaf_tiles_total[t] << ',' << (int)s.vec_leaf[t] << ';';
+      << s.leaf_tiles_total[t] << ',' << (int)s.vec_leaf[t] << ',' << s.xcd_chunk[t] << ','
+      << (int)s.persistent << ';';
   for (int l = s.max_depth - 1; l >= 0; --l)
     o << "p" << (const void*)s.d_post[l] << ',' << s.post[l].size() << ',' << blocks_post(s.post[l])
       << ',' << (int)s.vec_post[l] << ';';
@@ -211,6 +212,11 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
   if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[5], sm));
   if (!work.empty()) {
     build_schedule(work, ws + stage_bytes, s);
+    // Leaves of every problem in one persistent launch per tile shape, its
+    // workgroups taking tiles (longest reduction first) from a device
+    // counter; FASTMM_PERSISTENT=0 launches one workgroup per tile instead.
+    const char* pe = std::getenv("FASTMM_PERSISTENT");
+    s.persistent = !(pe && pe[0] == '0');
     upload_schedule(L, s, ws + stage_bytes + temp_bytes, desc_host);
     const char* g = std::getenv("FASTMM_GRAPH");
     if (g && g[0] == '0')

@@ -217,9 +217,11 @@ __device__ __forceinline__ int leaf_tile_of_block(int bid, int nblocks, int chun
 }
 
 // Kernel launchers (stream-ordered, no synchronisation).  xcd_chunk: see
-// leaf_tile_of_block.
+// leaf_tile_of_block.  queue: two zeroed ints in device memory for a
+// persistent launch (workgroups take tiles from a counter; the kernel leaves
+// the counters zeroed), or nullptr for one workgroup per tile.
 void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
-                      hipStream_t stream, int xcd_chunk = 0);
+                      hipStream_t stream, int xcd_chunk = 0, int* queue = nullptr);
 void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
                         hipStream_t stream, int xcd_chunk = 0);
 void launch_preadd(int side, const PreAddNode* d_nodes, int nnodes, int total_blocks, bool vec,

@@ -89,6 +89,8 @@ void ensure_init(Library& L) {
   for (auto& e : L.sync_ev) FASTMM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (auto& e : L.leaf_ev) FASTMM_HIP(hipEventCreate(&e));
   for (auto& e : L.tune_ev) FASTMM_HIP(hipEventCreate(&e));
+  FASTMM_HIP(hipMalloc(&L.leaf_queue, 256));
+  FASTMM_HIP(hipMemset(L.leaf_queue, 0, 256));
   L.initialised = true;
 }
 
@@ -433,7 +435,7 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
   for (int t = 0; t < kNumTiles; ++t) {
     if (s.leaf_tiles_total[t] > 0) {
       launch_leaf_gemm(t, s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t],
-                       L.stream, s.xcd_chunk[t]);
+                       L.stream, s.xcd_chunk[t], s.persistent ? L.leaf_queue : nullptr);
       ++launches;
     }
   }
@@ -1001,6 +1003,8 @@ void fastmm_finalize(void) {
   for (auto& e : L.leaf_ev) e = nullptr;
   for (auto& e : L.tune_ev) e = nullptr;
   if (L.own_stream) (void)hipStreamDestroy(L.own_stream);
+  if (L.leaf_queue) (void)hipFree(L.leaf_queue);
+  L.leaf_queue = nullptr;
   L.arena = nullptr;
   L.arena_bytes = 0;
   L.pinned = nullptr;

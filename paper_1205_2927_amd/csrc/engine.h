@@ -75,6 +75,7 @@ struct Schedule {
   const GemmDesc* d_leaf[kNumTiles] = {};
   bool vec_leaf[kNumTiles] = {};  // set in build_schedule
   int xcd_chunk[kNumTiles] = {};  // leaf launch tile -> XCD mapping (leaf_tile_of_block)
+  bool persistent = false;        // leaf launches take tiles from L.leaf_queue
   int max_depth = 0;
   size_t temp_bytes = 0;  // bytes of S, T and P temporaries
   // statistics
@@ -115,6 +116,7 @@ struct Library {
   static constexpr int kLeafEvents = 48;
   hipEvent_t leaf_ev[kLeafEvents] = {};  // timing of leaf launches
   hipEvent_t tune_ev[2] = {};            // planner's candidate timing
+  int* leaf_queue = nullptr;             // two counters for persistent leaf launches
   fastmm_stats_t stats{};
   size_t limit = 0;              // workspace cap (0: none)
   int plan_mode = FASTMM_PLAN_DEFAULT;

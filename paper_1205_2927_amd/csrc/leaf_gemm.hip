@@ -24,6 +24,8 @@
 //   depend on the order the indices are visited in.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace fastmm {
@@ -53,9 +55,10 @@ constexpr int leaf_waves_per_simd() {
   return VEC && (BM / WGM / 32) * (BN / WGN / 32) <= 4 ? 4 : 1;
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, bool VEC>
+template <int BM, int BN, int BK, int WGM, int WGN, bool VEC, bool PERSIST>
 __global__ void __launch_bounds__(64 * WGM * WGN, (leaf_waves_per_simd<BM, BN, WGM, WGN, VEC>()))
-leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles, int xcd_chunk) {
+leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles, int xcd_chunk,
+                 int* __restrict__ queue) {
   constexpr int kThreads = 64 * WGM * WGN;  // WGM x WGN wavefronts of 64
   constexpr int WM = BM / WGM, WN = BN / WGN;  // wave sub-tile
   constexpr int FM = WM / 32, FN = WN / 32; // 32x32 blocks per wave
@@ -89,8 +92,22 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
   __shared__ __attribute__((aligned(16))) float As0[BM * LDA], As1[BM * LDA];
   __shared__ __attribute__((aligned(16))) float Bs0[BK * LDB], Bs1[BK * LDB];
 
-  const int logical = leaf_tile_of_block(blockIdx.x, gridDim.x, xcd_chunk);
-  if (logical >= total_tiles) return;
+  // Without a queue each workgroup owns one tile.  With one (a persistent
+  // launch of about one workgroup per slot), workgroups take tiles in
+  // logical order from queue[0] until it passes total_tiles; every workgroup
+  // then counts itself out in queue[1], and the last one clears both, so the
+  // queue is ready for the next launch (also on a graph replay) without a
+  // memset.  No workgroup ever waits for another.
+  __shared__ int next_tile;
+  int logical = PERSIST ? 0 : leaf_tile_of_block(blockIdx.x, gridDim.x, xcd_chunk);
+  for (;;) {
+  if (PERSIST) {
+    if (threadIdx.x == 0) next_tile = atomicAdd(&queue[0], 1);
+    __syncthreads();
+    logical = next_tile;
+    __syncthreads();
+  }
+  if (logical >= total_tiles) break;
 
   // Which problem owns this tile (tile_begin is ascending).
   int lo = 0, hi = ndesc - 1;
@@ -328,30 +345,62 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
         }
       }
     }
+  if (!PERSIST) break;
+  }
+  if (PERSIST && threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&queue[1], 1) == (int)gridDim.x - 1) {
+      atomicExch(&queue[0], 0);
+      atomicExch(&queue[1], 0);
+    }
+  }
 }
 
 template <int BM, int BN, int BK, int WGM, int WGN>
-static void launch_t(const GemmDesc* d, int ndesc, int total, bool vec, hipStream_t s, int xc) {
+static void launch_t(const GemmDesc* d, int ndesc, int total, bool vec, hipStream_t s, int xc,
+                     int* queue) {
   if (total <= 0) return;
-  dim3 grid(total), block(64 * WGM * WGN);
+  constexpr int kThreads = 64 * WGM * WGN;
+  // Persistent launches are built for the 128-wide and smaller tiles only.
+  constexpr bool kCanPersist = BM <= 128 && BN <= 128 && BK == 16;
+  if (!kCanPersist) queue = nullptr;
+  auto kv = queue ? leaf_gemm_kernel<BM, BN, BK, WGM, WGN, true, kCanPersist>
+                  : leaf_gemm_kernel<BM, BN, BK, WGM, WGN, true, false>;
+  auto ks = queue ? leaf_gemm_kernel<BM, BN, BK, WGM, WGN, false, kCanPersist>
+                  : leaf_gemm_kernel<BM, BN, BK, WGM, WGN, false, false>;
+  int blocks = total;
+  if (queue) {  // persistent: one workgroup per slot the device can hold at once
+    static int slots[2] = {0, 0};
+    int& sl = slots[vec ? 1 : 0];
+    if (!sl) {
+      int dev = 0, cus = 0, per_cu = 0;
+      FASTMM_HIP(hipGetDevice(&dev));
+      FASTMM_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      FASTMM_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per_cu, reinterpret_cast<const void*>(vec ? kv : ks), kThreads, 0));
+      sl = std::max(1, cus * per_cu);
+    }
+    blocks = std::min(total, sl);
+  }
+  dim3 grid(blocks), block(kThreads);
   if (vec)
-    hipLaunchKernelGGL((leaf_gemm_kernel<BM, BN, BK, WGM, WGN, true>), grid, block, 0, s, d, ndesc, total, xc);
+    hipLaunchKernelGGL(kv, grid, block, 0, s, d, ndesc, total, xc, queue);
   else
-    hipLaunchKernelGGL((leaf_gemm_kernel<BM, BN, BK, WGM, WGN, false>), grid, block, 0, s, d, ndesc, total, xc);
+    hipLaunchKernelGGL(ks, grid, block, 0, s, d, ndesc, total, xc, queue);
   FASTMM_HIP(hipGetLastError());
 }
 
 void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
-                      hipStream_t stream, int xcd_chunk) {
+                      hipStream_t stream, int xcd_chunk, int* queue) {
   switch (tile) {
-    case kTile128x128: launch_t<128, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
-    case kTile256x128: launch_t<256, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
-    case kTile128x64: launch_t<128, 64, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
-    case kTile64x64: launch_t<64, 64, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
-    case kTile128x128k32: launch_t<128, 128, 32, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
-    case kTile256x128w8: launch_t<256, 128, 16, 4, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
-    case kTile256x256w8: launch_t<256, 256, 16, 2, 4>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
-    case kTile128x256: launch_t<128, 256, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
+    case kTile128x128: launch_t<128, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
+    case kTile256x128: launch_t<256, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
+    case kTile128x64: launch_t<128, 64, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
+    case kTile64x64: launch_t<64, 64, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
+    case kTile128x128k32: launch_t<128, 128, 32, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
+    case kTile256x128w8: launch_t<256, 128, 16, 4, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
+    case kTile256x256w8: launch_t<256, 256, 16, 2, 4>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
+    case kTile128x256: launch_t<128, 256, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
     case kTileBf16x3: launch_leaf_bf16x3(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
     default: throw Error(kInvalidValue, "unknown tile id");
   }

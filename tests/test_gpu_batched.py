@@ -73,6 +73,26 @@ def test_batched_graph_off_matches(fastmm, monkeypatch):
         assert np.array_equal(host(a), host(b))
 
 
+@pytest.mark.parametrize("graph", ["1", "0"])
+def test_batched_persistent_matches_one_workgroup_per_tile(fastmm, monkeypatch, graph):
+    # The persistent leaf launch (tiles taken from a device counter that the
+    # kernel clears when it ends) gives the same bits as one workgroup per
+    # tile, call after call (graph replays included).
+    depths = [d for (_, _, _, d) in SHAPES]
+    As, Bs = _make(SHAPES, 2100)
+    monkeypatch.setenv("FASTMM_GRAPH", graph)
+    monkeypatch.setenv("FASTMM_PERSISTENT", "0")
+    ref = [empty_dev(m, n) for (m, k, n, d) in SHAPES]
+    fastmm.gemm_batched(As, Bs, ref, depth=depths, leaf=[1] * len(SHAPES))
+    monkeypatch.setenv("FASTMM_PERSISTENT", "1")
+    for call in range(3):
+        say(f"persistent batched call {call} graph={graph}")
+        Cs = [empty_dev(m, n) for (m, k, n, d) in SHAPES]
+        fastmm.gemm_batched(As, Bs, Cs, depth=depths, leaf=[1] * len(SHAPES))
+        for a, b in zip(Cs, ref):
+            assert np.array_equal(host(a), host(b))
+
+
 def test_batched_host_operands(fastmm):
     import torch
     shapes = SHAPES[:5]
