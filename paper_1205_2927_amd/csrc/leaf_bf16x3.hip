@@ -25,6 +25,7 @@ namespace fastmm {
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 namespace {
 
@@ -106,8 +107,11 @@ leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tile
 
   // A: thread loads rows a_r + 32 i (i = 0..3), columns a_c..a_c+3.
   const int a_r = tid / 8, a_c = (tid % 8) * 4;
-  // B: thread loads rows b_k..b_k+3, columns b_n..b_n+3.
-  const int b_k = (tid / 32) * 4, b_n = (tid % 32) * 4;
+  // B: thread loads column b_n, k-rows b_k..b_k+15 (4-byte loads, coalesced
+  // across the wave), and writes them as one row of the [n][k] arrays: the
+  // lanes of a store then write consecutive rows, which fall on distinct
+  // LDS banks (four columns per thread gave 8-way bank conflicts).
+  const int b_n = tid & (BN - 1), b_k = (tid / BN) * 16;
 
   const int rv = min(BM, a_rows - tm);
   const int cv = min(BN, b_cols - tn);
@@ -115,7 +119,8 @@ leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tile
   const float* b_tile = B + tn;
   constexpr int kOOB = 0x7FFFFFF0;
 
-  float4 ra[4], rb[4];
+  float4 ra[4];
+  float rb[16];
   auto load_slab = [&](int k0) {
     const int kv = min(BK, kmax - k0);
     const uint32_t a_bytes =
@@ -142,21 +147,10 @@ leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tile
       }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 16; ++i) {
       const int k = b_k + i;
-      const int base = (k * (int)ldb + b_n) * 4;
-      if (VEC) {
-        const int off = (k < kv && b_n < cv) ? base : kOOB;
-        rb[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(br, off, 0, 0));
-      } else {
-        float e[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int off = (k < kv && b_n + q < cv) ? base + 4 * q : kOOB;
-          e[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(br, off, 0, 0));
-        }
-        rb[i] = make_float4(e[0], e[1], e[2], e[3]);
-      }
+      const int off = (k < kv && b_n < cv) ? (k * (int)ldb + b_n) * 4 : kOOB;
+      rb[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(br, off, 0, 0));
     }
   };
 
@@ -169,21 +163,18 @@ leaf_bf16x3_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tile
       *reinterpret_cast<u16x4*>(&Ah[buf][o]) = h;
       *reinterpret_cast<u16x4*>(&Al[buf][o]) = l;
     }
-    // B: the four k of column b_n + c go to row b_n + c of the [n][k] arrays.
-    u16x4 h[4], l[4];
+    // B: the 16 k of column b_n go to row b_n of the [n][k] arrays, 8 at a
+    // time (16-byte stores).
 #pragma unroll
-    for (int i = 0; i < 4; ++i) split4(rb[i], h[i], l[i]);
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      u16x4 hc, lc;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        hc[i] = h[i][c];
-        lc[i] = l[i][c];
-      }
-      const int o = (b_n + c) * LDK + b_k;
-      *reinterpret_cast<u16x4*>(&Bh[buf][o]) = hc;
-      *reinterpret_cast<u16x4*>(&Bl[buf][o]) = lc;
+    for (int q = 0; q < 2; ++q) {
+      u16x4 h0, l0, h1, l1;
+      split4(make_float4(rb[8 * q], rb[8 * q + 1], rb[8 * q + 2], rb[8 * q + 3]), h0, l0);
+      split4(make_float4(rb[8 * q + 4], rb[8 * q + 5], rb[8 * q + 6], rb[8 * q + 7]), h1, l1);
+      const u16x8 h = {h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+      const u16x8 l = {l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+      const int o = b_n * LDK + b_k + 8 * q;
+      *reinterpret_cast<u16x8*>(&Bh[buf][o]) = h;
+      *reinterpret_cast<u16x8*>(&Bl[buf][o]) = l;
     }
   };
 
