@@ -1,11 +1,12 @@
 """Headline benchmark: effective GFLOPS (2MNK / wall-clock) of FP32 Winograd
-on MFMA leaves vs the plain MFMA SGEMM, square n = 19456, operands in pinned
-host memory so that the wall-clock includes the host<->device transfers (the
-paper measures GFLOPS as 2N^3 over wall-clock with transfers included,
-Section 4).
+on MFMA leaves vs the plain MFMA SGEMM, square n = 19456.
 
-One step = one synchronous fastmm_gemm call: stage A, B in, pre-additions,
-grouped leaf products, post-additions, C out.  Inputs are seeded synthetic
+One step = one synchronous fastmm_gemm call over operands already resident in
+HBM when the timed region starts: pre-additions, grouped leaf products,
+post-additions.  The same product with operands in pinned host memory, where
+the wall-clock includes the host<->device transfers (the paper measures
+GFLOPS as 2N^3 over wall-clock with transfers included, Section 4), is
+reported beside it as context (`pinned_host`).  Inputs are seeded synthetic
 (uniform on the 2^-23 grid of [-1, 1)).  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--depth D]
@@ -24,12 +25,12 @@ sys.path.insert(0, ROOT)
 METRIC = "effective GFLOPS (2MNK/wall-clock) n=19456 FP32 Winograd vs plain MFMA SGEMM"
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per leaf launch (pipelined depth-3 call: 14 launches of 49 leaves
-# of 1280 or 1152 x 2432 x 2432) from the FETCH_SIZE and WRITE_SIZE counter
+# HBM bytes per leaf launch (HBM-resident depth-3 call: one grouped launch of
+# 343 leaves of 2432 x 2432 x 2432) from the FETCH_SIZE and WRITE_SIZE counter
 # runs, each scaled by its reading for a 1 GiB calibration copy (fetch x2.000,
-# write x1.000); see profiles/leaf_gemm_n19456_d3_pinned_hbm_traffic.md.
+# write x1.000); see profiles/leaf_gemm_n19456_d3_device_hbm_traffic.md.
 # Valid for leaf_gemm_kernel<128,128,16,2,2> in that configuration only.
-TRAFFIC_BYTES_PER_LAUNCH = 2669524.3 * 1024 * 2.000 + 576963.6 * 1024 * 1.000
+TRAFFIC_BYTES_PER_LAUNCH = 37010240.4 * 1024 * 2.000 + 7924672.0 * 1024 * 1.000
 
 
 def log(msg):
@@ -107,13 +108,16 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-device-context", action="store_true")
+    ap.add_argument("--no-pinned", action="store_true",
+                    help="skip the pinned-host (transfer-inclusive) context")
+    ap.add_argument("--no-device-context", action="store_true",
+                    help="skip the addition-kernel and classic-recursion context")
     ap.add_argument("--no-shards", action="store_true",
                     help="skip one GPU's share of the sharded product")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-problem batched context (uneven shapes)")
-    ap.add_argument("--resident", action="store_true",
-                    help="operands in device memory (no transfers): profiling the device path")
+    ap.add_argument("--pinned-headline", action="store_true",
+                    help="time the pinned-host path in the main loop (profiling that path)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (calibrates HBM counters)")
     args = ap.parse_args()
@@ -138,32 +142,34 @@ def main():
         torch.cuda.empty_cache()
     n = args.n
     M = N = K = n
-    log(f"bench: n={n} allocating pinned host operands")
-    A = torch.empty((M, K), dtype=torch.float32, pin_memory=True)
-    B = torch.empty((K, N), dtype=torch.float32, pin_memory=True)
-    C = torch.empty((M, N), dtype=torch.float32, pin_memory=True)
+    log(f"bench: n={n} generating operands (pinned host), copying to HBM")
+    hA = torch.empty((M, K), dtype=torch.float32, pin_memory=True)
+    hB = torch.empty((K, N), dtype=torch.float32, pin_memory=True)
+    hC = torch.empty((M, N), dtype=torch.float32, pin_memory=True)
     synthgen.build() if synthgen._load() is None else None
-    synthgen.fill_uniform_pm1(1001 + 3, M, K, A.data_ptr())
-    synthgen.fill_uniform_pm1(2001 + 3, K, N, B.data_ptr())
+    synthgen.fill_uniform_pm1(1001 + 3, M, K, hA.data_ptr())
+    synthgen.fill_uniform_pm1(2001 + 3, K, N, hB.data_ptr())
     flops = 2.0 * M * N * K
-    if args.resident:
-        # Device-path profiling: the same inputs, resident in HBM.
-        A, B = A.to("cuda"), B.to("cuda")
+    if args.pinned_headline:
+        A, B, C = hA, hB, hC
+    else:
+        A, B = hA.to("cuda"), hB.to("cuda")
         C = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
 
     fastmm.set_profiling(True)
 
-    def run(depth, tile=args.tile, leaf=args.leaf):
-        return lambda: fastmm.gemm(M, N, K, A, B, C, depth=depth, leaf=leaf, tile=tile)
+    def run(depth, a=A, b=B, c=C):
+        return lambda: fastmm.gemm(M, N, K, a, b, c, depth=depth, leaf=args.leaf, tile=args.tile)
 
-    # Plain MFMA SGEMM (depth 0), same staging path.
+    # Plain MFMA SGEMM (depth 0) on the same operands.
     plain = None
     if not args.no_plain:
         log("bench: plain SGEMM (depth 0)")
         tot, ts = time_calls(run(0), args.steps, args.warmup)
         st = fastmm.get_stats()
         plain = {"ms_per_step": 1e3 * tot / args.steps, "value": flops / (tot / args.steps) / 1e9,
-                 "leaf_ms": st["leaf_ms"], "h2d_span_ms": st["h2d_ms"],
+                 "leaf_ms": st["leaf_ms"],
                  "leaf_tflops": st["leaf_flops"] / (st["leaf_ms"] * 1e-3) / 1e12}
         log(f"  plain: {plain}")
 
@@ -178,18 +184,15 @@ def main():
     else:
         best = depths[0]
     log(f"bench: Winograd depth {best}, {args.steps} timed steps")
-    leaf_ms, h2d_ms = [], []
+    leaf_ms = []
 
     def step():
         fastmm.gemm(M, N, K, A, B, C, depth=best, leaf=args.leaf, tile=args.tile)
-        s = fastmm.get_stats()
-        leaf_ms.append(s["leaf_ms"])
-        h2d_ms.append(s["h2d_ms"])
+        leaf_ms.append(fastmm.get_stats()["leaf_ms"])
 
     for _ in range(args.warmup):
         step()
     leaf_ms.clear()
-    h2d_ms.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -203,30 +206,14 @@ def main():
     # Parity of the last result: sampled rows + Freivalds against the oracle
     # (the oracle is the checker; the timed path never touches it).
     from oracle import checks
-    An = A.cpu().numpy()
-    Bn = B.cpu().numpy()
+    An = hA.numpy()
+    Bn = hB.numpy()
     Cn = C.cpu().numpy()
     rows = synthgen.row_sample(7004, M, 8)
     parity = {"sampled_rows_rel": checks.sampled_rows_rel(Cn, An, Bn, rows),
               "freivalds_rel": checks.freivalds_rel(Cn, An, Bn, synthgen.signs_pm1(7005, N)),
               "rows": int(rows.size), "tolerance": 1e-4}
     log(f"bench: parity {parity}")
-
-    # One GPU's share of the column-panel sharding (the paper's two-device
-    # split, eqs. (3)-(4), generalised): 1 x 8 panels (19456 x 19456 x 2432)
-    # and a 2 x 4 grid (9728 x 19456 x 4864), staged from the same pinned
-    # host operands (strided views), as many levels as the leaf cutoff allows.
-    shards = None
-    if n == 19456 and not args.resident and not args.no_shards:
-        shards = {}
-        for name, (sm, sn) in {"panel_1x8": (M, N // 8), "grid_2x4": (M // 2, N // 4)}.items():
-            fn = lambda: fastmm.gemm(sm, sn, K, A[:sm], B[:, :sn], C[:sm, :sn], depth=16,
-                                     leaf=args.leaf)
-            tot, ts = time_calls(fn, 3, 1)
-            sst = fastmm.get_stats()
-            shards[name] = {"M": sm, "N": sn, "K": K, "depth": sst["depth"], "ms": 1e3 * min(ts),
-                            "effective_GFLOPS": 2.0 * sm * sn * K / min(ts) / 1e9}
-        log(f"bench: shard shapes {shards}")
 
     # Dominant kernel: the grouped leaf GEMM.  Its launches are timed with
     # HIP events recorded by the library on the stream it launches them on.
@@ -235,71 +222,88 @@ def main():
     avg_launch = leaf_sum / n_launch
     flops_launch = st["leaf_flops"] / n_launch
     leaf_tflops = flops_launch / (avg_launch * 1e-3) / 1e12
+    traffic_ok = (TRAFFIC_BYTES_PER_LAUNCH is not None and not args.pinned_headline and best == 3
+                  and n == 19456 and args.tile == 0 and args.leaf == 1024)
     roofline = {"bound": "mfma", "kernel": "leaf_gemm_kernel<128,128,16,2,2> (grouped leaves)",
                 "achieved": leaf_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": leaf_tflops / PEAK_FP32_TFLOPS,
-                "traffic": TRAFFIC_BYTES_PER_LAUNCH if (best == 3 and n == 19456 and args.tile == 0
-                                                        and args.leaf == 1024) else None,
+                "traffic": TRAFFIC_BYTES_PER_LAUNCH if traffic_ok else None,
                 "flops_per_launch": flops_launch, "avg_launch_ms": avg_launch,
                 "launches_per_step": n_launch}
+    phases = {"leaf_ms": leaf_sum, "preadd_ms": st["preadd_ms"], "postadd_ms": st["postadd_ms"],
+              "add_bytes": st["add_bytes"], "transfer_bytes": st["transfer_bytes"]}
+    add_ms = st["preadd_ms"] + st["postadd_ms"]
+    if add_ms > 0:
+        phases["add_GBps"] = st["add_bytes"] / (add_ms * 1e-3) / 1e9
+        phases["add_frac_of_hbm_peak"] = phases["add_GBps"] / PEAK_HBM_GBS
 
-    # Context: the same product with device-resident operands (level-wise
-    # path, no transfers), with the addition kernels timed separately.
-    dev_ctx = None
-    if not args.no_device_context and not args.resident:
-        dA = A.to("cuda")
-        dB = B.to("cuda")
-        dC = torch.empty((M, N), dtype=torch.float32, device="cuda")
-        fastmm.gemm(M, N, K, dA, dB, dC, depth=best, leaf=args.leaf, tile=args.tile)
-        ts = []
-        for _ in range(2):
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            fastmm.gemm(M, N, K, dA, dB, dC, depth=best, leaf=args.leaf, tile=args.tile)
-            ts.append(time.perf_counter() - t)
-        sd = fastmm.get_stats()
-        add_ms = sd["preadd_ms"] + sd["postadd_ms"]
-        dev_ctx = {"ms": 1e3 * min(ts), "effective_GFLOPS": flops / min(ts) / 1e9,
-                   "leaf_ms": sd["leaf_ms"],
-                   "leaf_TFLOPs": sd["leaf_flops"] / (sd["leaf_ms"] * 1e-3) / 1e12,
-                   "preadd_ms": sd["preadd_ms"], "postadd_ms": sd["postadd_ms"],
-                   "add_bytes": sd["add_bytes"],
-                   "add_GBps": sd["add_bytes"] / (add_ms * 1e-3) / 1e9 if add_ms > 0 else None,
-                   "add_frac_of_hbm_peak": (sd["add_bytes"] / (add_ms * 1e-3) / 1e9 / PEAK_HBM_GBS)
-                   if add_ms > 0 else None}
-        # The paper's own algorithm: the classic eight-product recursion of
-        # Table 1 with its recursion point (leaves below 6016, i.e. leaf
-        # cutoff 3008), MFMA leaves, same operands.
-        fastmm.rmul(M, N, K, dA, dB, dC, depth=8, leaf=3008)
+    # Context: the paper's own algorithm, the classic eight-product recursion
+    # of Table 1 at its recursion point (leaves below 6016, i.e. leaf cutoff
+    # 3008), MFMA leaves, same operands.
+    classic = None
+    if not args.no_device_context and not args.pinned_headline:
+        fastmm.rmul(M, N, K, A, B, C, depth=8, leaf=3008)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        fastmm.rmul(M, N, K, dA, dB, dC, depth=8, leaf=3008)
+        fastmm.rmul(M, N, K, A, B, C, depth=8, leaf=3008)
         torch.cuda.synchronize()
         t = time.perf_counter() - t
-        dev_ctx["classic_recursion"] = {"ms": 1e3 * t, "effective_GFLOPS": flops / t / 1e9,
-                                        "depth": fastmm.get_stats()["depth"], "leaf": 3008}
-        del dA, dB, dC
-        torch.cuda.empty_cache()
-        log(f"bench: device-resident context {dev_ctx}")
+        classic = {"ms": 1e3 * t, "effective_GFLOPS": flops / t / 1e9,
+                   "depth": fastmm.get_stats()["depth"], "leaf": 3008}
+        log(f"bench: classic recursion {classic}")
+
+    # Context: the same products with operands in pinned host memory, the
+    # transfers inside the wall-clock (pipelined host path).
+    pinned = None
+    if not args.no_pinned and not args.pinned_headline:
+        ps = max(2, min(args.steps, 3))
+        tot, ts = time_calls(run(best, hA, hB, hC), ps, 1)
+        sp = fastmm.get_stats()
+        pinned = {"ms_per_step": 1e3 * tot / ps, "effective_GFLOPS": flops / (tot / ps) / 1e9,
+                  "depth": sp["depth"], "leaf_ms": sp["leaf_ms"],
+                  "leaf_TFLOPs_per_launch": sp["leaf_flops"] / (sp["leaf_ms"] * 1e-3) / 1e12,
+                  "leaf_launches": sp["leaf_launches"], "h2d_span_ms": sp["h2d_ms"],
+                  "transfer_bytes": sp["transfer_bytes"]}
+        if not args.no_plain:
+            tot, ts = time_calls(run(0, hA, hB, hC), ps, 1)
+            pinned["plain_ms_per_step"] = 1e3 * tot / ps
+            pinned["plain_effective_GFLOPS"] = flops / (tot / ps) / 1e9
+            pinned["speedup_vs_plain"] = pinned["plain_ms_per_step"] / pinned["ms_per_step"]
+        log(f"bench: pinned host {pinned}")
+
+    # One GPU's share of the column-panel sharding (the paper's two-device
+    # split, eqs. (3)-(4), generalised): 1 x 8 panels (19456 x 19456 x 2432)
+    # and a 2 x 4 grid (9728 x 19456 x 4864), staged from the pinned host
+    # operands (strided views), as many levels as the leaf cutoff allows.
+    shards = None
+    if n == 19456 and not args.no_shards and not args.pinned_headline:
+        shards = {}
+        for name, (sm, sn) in {"panel_1x8": (M, N // 8), "grid_2x4": (M // 2, N // 4)}.items():
+            fn = lambda: fastmm.gemm(sm, sn, K, hA[:sm], hB[:, :sn], hC[:sm, :sn], depth=16,
+                                     leaf=args.leaf)
+            tot, ts = time_calls(fn, 3, 1)
+            sst = fastmm.get_stats()
+            shards[name] = {"M": sm, "N": sn, "K": K, "depth": sst["depth"], "ms": 1e3 * min(ts),
+                            "effective_GFLOPS": 2.0 * sm * sn * K / min(ts) / 1e9}
+        log(f"bench: shard shapes {shards}")
+
     batched = None
-    if not args.no_batched and not args.resident:
+    if not args.no_batched and not args.pinned_headline:
         batched = batched_context(fastmm, torch)
         log(f"bench: batched context {batched}")
-    phases = {"h2d_span_ms": float(np.mean(h2d_ms)), "leaf_ms": leaf_sum,
-              "add_bytes": st["add_bytes"], "transfer_bytes": st["transfer_bytes"]}
 
     cpu = None
     if not args.no_cpu:
-        from oracle import classic
-        threads = classic.num_threads()
+        from oracle import classic as oracle_classic
+        threads = oracle_classic.num_threads()
         rows_c = synthgen.row_sample(7006, M, 32)
         t = time.perf_counter()
-        classic.gemm_rows(An, Bn, rows_c)
+        oracle_classic.gemm_rows(An, Bn, rows_c)
         per_row = (time.perf_counter() - t) / rows_c.size
         R = int(max(4, min(4096, args.cpu_seconds / max(per_row, 1e-6))))
         rows_c = synthgen.row_sample(7007, M, R)
         t = time.perf_counter()
-        classic.gemm_rows(An, Bn, rows_c)
+        oracle_classic.gemm_rows(An, Bn, rows_c)
         dt = time.perf_counter() - t
         cpu = {"value": 2.0 * rows_c.size * N * K / dt / 1e9, "unit": "GFLOPS", "cores": threads,
                "kind": "oracle",
@@ -307,22 +311,23 @@ def main():
                          f"OpenMP over rows), {dt:.1f} s"}
         log(f"bench: cpu {cpu}")
 
+    where = ("pinned host in/out (transfers timed)" if args.pinned_headline
+             else "operands resident in HBM")
     out = {
         "metric": METRIC, "value": value, "unit": "GFLOPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"FP32 Winograd-Strassen C=A*B, square n={n}, "
-                               + ("device-resident operands" if args.resident else
-                                  "pinned host in/out (transfers timed)")
-                               + f", depth {st['depth']}, leaf {args.leaf}",
+        "config": {"workload": f"FP32 Winograd-Strassen C=A*B, square n={n}, {where}, "
+                               f"depth {st['depth']}, leaf {args.leaf}",
                    "M": M, "N": N, "K": K, "depth": st["depth"], "leaf": args.leaf,
                    "tile": args.tile, "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu,
         "plain_sgemm": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms_per_step) if plain else None,
         "depth_probe_ms": {str(k): 1e3 * v for k, v in probe.items()},
-        "phases": phases, "device_resident": dev_ctx, "batched": batched, "shards": shards, "parity": parity,
+        "phases": phases, "classic_recursion": classic, "pinned_host": pinned,
+        "batched": batched, "shards": shards, "parity": parity,
     }
     print(json.dumps(out), flush=True)
 
