@@ -1,8 +1,10 @@
-"""Parity at the benchmark's full sizes, in the launch configuration bench.py
-times: operands in pinned host memory (transfers inside the call), square
-n = 19456 and the rectangular 19456 x 16384 x 12288 product.  The oracle
-cannot afford the full product on every run, so it checks seeded sampled rows
-exactly (FP64-accumulated) and Freivalds' probe C x = A (B x)."""
+"""Parity at the benchmark's full sizes: square n = 19456 with the operands in
+HBM (the launch configuration bench.py times for its headline: one
+level-wise call, one grouped leaf launch) and with the operands in pinned
+host memory (transfers inside the call, the benchmark's pinned_host block),
+and the rectangular 19456 x 16384 x 12288 product.  The oracle cannot afford
+the full product on every run, so it checks seeded sampled rows exactly
+(FP64-accumulated) and Freivalds' probe C x = A (B x)."""
 import numpy as np
 import pytest
 
@@ -20,16 +22,23 @@ def _pinned(shape):
     return torch.empty(shape, dtype=torch.float32, pin_memory=True)
 
 
-def _check(fastmm, M, N, K, depth, leaf, seed_a, seed_b, rows=24):
+def _check(fastmm, M, N, K, depth, leaf, seed_a, seed_b, rows=24, device=False):
     A = _pinned((M, K))
     B = _pinned((K, N))
     C = _pinned((M, N))
     synthgen.fill_uniform_pm1(seed_a, M, K, A.data_ptr())
     synthgen.fill_uniform_pm1(seed_b, K, N, B.data_ptr())
     C.fill_(float("nan"))
-    say(f"full size {M}x{K}x{N} depth={depth} leaf={leaf}")
-    fastmm.gemm(M, N, K, A, B, C, depth=depth, leaf=leaf, tile=0)
-    st = fastmm.get_stats()
+    say(f"full size {M}x{K}x{N} depth={depth} leaf={leaf} device={device}")
+    if device:
+        dA, dB, dC = A.to("cuda"), B.to("cuda"), C.to("cuda")
+        fastmm.gemm(M, N, K, dA, dB, dC, depth=depth, leaf=leaf, tile=0)
+        st = fastmm.get_stats()
+        C.copy_(dC)
+        del dA, dB, dC
+    else:
+        fastmm.gemm(M, N, K, A, B, C, depth=depth, leaf=leaf, tile=0)
+        st = fastmm.get_stats()
     An, Bn, Cn = A.numpy(), B.numpy(), C.numpy()
     assert np.isfinite(Cn).all()
     r = synthgen.row_sample(seed_a + 7, M, rows)
@@ -38,6 +47,19 @@ def _check(fastmm, M, N, K, depth, leaf, seed_a, seed_b, rows=24):
     say(f"  depth={st['depth']} sampled-rows rel={e_rows:.3e} freivalds rel={e_fv:.3e}")
     assert e_rows <= TOL and e_fv <= TOL
     return st
+
+
+def test_headline_square_19456_depth3_device(fastmm):
+    st = _check(fastmm, 19456, 19456, 19456, 3, 1024, 1001 + 3, 2001 + 3, device=True)
+    assert st["depth"] == 3
+    # level-wise: all 343 leaves in one grouped launch
+    assert st["leaves"] == 343 and st["leaf_launches"] == 1
+    assert abs(st["leaf_flops"] - 2 * 19456**3 * (7 / 8) ** 3) < 1e-6 * 2 * 19456**3
+
+
+def test_plain_square_19456_device(fastmm):
+    st = _check(fastmm, 19456, 19456, 19456, 0, 1024, 1001 + 3, 2001 + 3, rows=12, device=True)
+    assert st["depth"] == 0 and st["leaf_launches"] == 1
 
 
 def test_headline_square_19456_depth3_pinned(fastmm):
