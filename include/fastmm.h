@@ -75,7 +75,17 @@ enum {
    * hi*hi + hi*lo + lo*hi accumulated in FP32 on the BF16 matrix cores):
    * about 2^-16 relative accuracy per product instead of FP32's 2^-24.  The
    * quadrant additions stay FP32. */
-  FASTMM_TILE_BF16X3_128x128 = 8
+  FASTMM_TILE_BF16X3_128x128 = 8,
+  /* Precision form of the leaf, never chosen by the planner: 128x128 tiles in
+   * scaled split-FP16 arithmetic.  Each row of a leaf's left operand and each
+   * column of its right operand is scaled by a power of two that brings its
+   * largest magnitude into [2^14, 2^15) (a pass over the operands before the
+   * leaf launch, exponents kept in the workspace), every scaled element is
+   * split into hi + lo FP16, the products hi*hi + hi*lo + lo*hi are
+   * accumulated in FP32 on the FP16 matrix cores and the scales are undone
+   * on the result: about 2^-21 relative accuracy per product.  Not offered
+   * by fastmm_rmul (FASTMM_ERROR_NOT_SUPPORTED). */
+  FASTMM_TILE_FP16X3_128x128 = 9
 };
 
 typedef struct {

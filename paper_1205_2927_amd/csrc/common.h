@@ -29,6 +29,10 @@ struct GemmDesc {
   int32_t tiles_n;          // ceil(c_cols / BN) for the launch's tile shape
   int32_t tile_begin;       // first tile of this problem within the launch
   int32_t beta;             // 0: C = A B; 1: C += A B
+  // Scaled FP16 leaf only: power-of-two exponents of the a_rows rows of A
+  // and the b_cols columns of B (written by its scale pass); else unused.
+  int32_t* ea;
+  int32_t* eb;
 };
 
 // One node of a pre-addition launch: reads the four quadrants of a parent
@@ -173,7 +177,8 @@ enum TileId {
   kTile256x256w8 = 6,   // 8 wavefronts
   kTile128x256 = 7,
   kTileBf16x3 = 8,      // 128x128, split-BF16 arithmetic (precision form)
-  kNumTiles = 9,
+  kTileFp16x3 = 9,      // 128x128, scaled split-FP16 arithmetic (precision form)
+  kNumTiles = 10,
 };
 
 struct TileShape {
@@ -191,6 +196,7 @@ inline TileShape tile_shape(int id) {
     case kTile256x256w8: return {256, 256};
     case kTile128x256: return {128, 256};
     case kTileBf16x3: return {128, 128};
+    case kTileFp16x3: return {128, 128};
     default: throw Error(kInvalidValue, "unknown tile id " + std::to_string(id));
   }
 }
@@ -224,6 +230,11 @@ void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_ti
                       hipStream_t stream, int xcd_chunk = 0, int* queue = nullptr);
 void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
                         hipStream_t stream, int xcd_chunk = 0);
+// The scaled FP16 form: a scale pass over every descriptor's operands (rows
+// of A up to max_a_rows, columns of B up to max_b_cols; each descriptor's
+// ea / eb must hold a_rows / b_cols ints), then the leaf launch.
+void launch_leaf_fp16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
+                        hipStream_t stream, int xcd_chunk, int max_a_rows, int max_b_cols);
 void launch_preadd(int side, const PreAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
                    hipStream_t stream);
 // quad < 0: all four result quadrants; 0..3: only C11, C12, C21 or C22

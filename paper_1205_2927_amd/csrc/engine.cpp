@@ -206,6 +206,10 @@ size_t problem_temp_bytes(const Problem& p) {
   }
   for (int l = 1; l <= p.depth; ++l)
     floats += align_up((size_t)pow7(l) * dims[l].m * dims[l].n, kAlignFloats);
+  // Scaled FP16 leaves: one int exponent per row of A and per column of B of
+  // every leaf.
+  if (p.tile == kTileFp16x3)
+    floats += align_up((size_t)pow7(p.depth) * (dims[p.depth].m + dims[p.depth].n), kAlignFloats);
   return floats * sizeof(float);
 }
 
@@ -277,8 +281,15 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     const Dims lf = dims[d];
     const int64_t nleaves = pow7(d);
     const TileShape ts = tile_shape(p.tile);
+    int32_t* exps = p.tile == kTileFp16x3
+                        ? reinterpret_cast<int32_t*>(carve((size_t)nleaves * (lf.m + lf.n)))
+                        : nullptr;
     for (int64_t x = 0; x < nleaves; ++x) {
       GemmDesc g{};
+      if (exps) {
+        g.ea = exps + x * (lf.m + lf.n);
+        g.eb = g.ea + lf.m;
+      }
       g.A = Av[x].p;
       g.lda = Av[x].ld;
       g.B = Bv[x].p;
@@ -433,7 +444,17 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
   if (profile) FASTMM_HIP(hipEventRecord(L.ev[2], L.stream));
   if (leaf_begin) FASTMM_HIP(hipEventRecord(leaf_begin, L.stream));
   for (int t = 0; t < kNumTiles; ++t) {
-    if (s.leaf_tiles_total[t] > 0) {
+    if (s.leaf_tiles_total[t] <= 0) continue;
+    if (t == kTileFp16x3) {
+      int max_rows = 0, max_cols = 0;
+      for (const auto& g : s.leaf[t]) {
+        max_rows = std::max(max_rows, (int)g.a_rows);
+        max_cols = std::max(max_cols, (int)g.b_cols);
+      }
+      launch_leaf_fp16x3(s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t],
+                         L.stream, s.xcd_chunk[t], max_rows, max_cols);
+      launches += 2;
+    } else {
       launch_leaf_gemm(t, s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t],
                        L.stream, s.xcd_chunk[t], s.persistent ? L.leaf_queue : nullptr);
       ++launches;

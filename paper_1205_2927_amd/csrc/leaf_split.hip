@@ -1,0 +1,412 @@
+// Leaf products in split 16-bit arithmetic on the 16-bit matrix cores: the
+// precision forms of the leaf, selected explicitly, never substituted for
+// the FP32 leaf.
+//
+// Each FP32 operand element x is split into two 16-bit numbers, hi = r(x)
+// and lo = r(x - hi) (round to nearest even), and the product a*b is taken
+// as hi_a*hi_b + hi_a*lo_b + lo_a*hi_b (lo*lo dropped) with every term
+// accumulated in FP32 by a 32x32x16 MFMA.
+//
+// * Split BF16 ("bf16x3"; Henry, Tang and Heinecke, "Leveraging the bfloat16
+//   Artificial Intelligence Datatype For Higher-Precision Computations",
+//   ARITH 2019): hi and lo are BF16, so x = hi + lo to a relative 2^-17 and
+//   each product is good to about 2^-16.  BF16 has FP32's exponent range: no
+//   scaling is needed.
+// * Scaled split FP16 ("fp16x3"; the hi/lo FP16 split of Ootomo and Yokota,
+//   "Recovering single precision accuracy from Tensor Cores while
+//   surpassing the FP32 theoretical peak performance", IJHPCA 2022): hi and
+//   lo are FP16 (11-bit significands), so x = hi + lo to a relative 2^-22,
+//   but FP16 spans only 2^-24..2^16.  Every row r of the leaf's A operand and
+//   every column c of its B operand therefore carries a power-of-two scale:
+//   leaf_scale_kernel stores exponents e_A[r], e_B[c] that bring the row's
+//   (column's) largest magnitude into [2^14, 2^15), the tile splits
+//   x * 2^-e instead of x, and the epilogue multiplies the accumulated sum by
+//   2^(e_A[r] + e_B[c]).  Powers of two factor out of the sum over k, so the
+//   scaling itself is exact.  With the largest element at 2^14..2^15, a lo
+//   part can only become subnormal (or vanish) for elements more than 2^17
+//   below their row's (column's) largest one, whose contribution to a
+//   product is below 2^-39 of the row-times-column bound: Ootomo and Yokota's
+//   extra 2^11 factor on lo, and the second accumulator it needs, buy
+//   nothing here, and one FP32 accumulator holds all three terms.
+//
+// Tiling mirrors the FP32 leaf kernel (128x128 macro tile, 4 wavefronts of
+// 64x64, grouped launch with the same descriptors and XCD-aware walk) with
+// K-slabs of 32: global FP32 loads (branch-free buffer loads, zero outside
+// the valid extent) are split in registers and stored to LDS as hi and lo
+// arrays with k contiguous ([m][k] for A, [n][k] for B), so one 16-byte LDS
+// read gives the 8 consecutive k a lane supplies to a 32x32x16 step.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace fastmm {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+enum SplitFormat { kSplitBf16 = 0, kSplitFp16 = 1 };
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc16(const float* p, int bytes) {
+  const uint64_t a = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  float* q = reinterpret_cast<float*>(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(q, (short)0, __builtin_amdgcn_readfirstlane(bytes),
+                                           0x00020000);
+}
+
+// BF16 bits of x rounded to nearest even (finite inputs).
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(unsigned short h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+
+// hi and lo halves of four values; for FP16 the values are first scaled by
+// 2^-e (e = 0 for BF16).
+template <int FMT>
+__device__ __forceinline__ void split4(float4 v, int e, u16x4& hi, u16x4& lo) {
+  const float x[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (FMT == kSplitBf16) {
+      const unsigned short h = bf16_rne(x[i]);
+      hi[i] = h;
+      lo[i] = bf16_rne(x[i] - bf16_to_f32(h));
+    } else {
+      const float y = __builtin_ldexpf(x[i], -e);
+      const _Float16 h = (_Float16)y;
+      hi[i] = __builtin_bit_cast(unsigned short, h);
+      lo[i] = __builtin_bit_cast(unsigned short, (_Float16)(y - (float)h));
+    }
+  }
+}
+
+template <int FMT>
+__device__ __forceinline__ f32x16 mfma16(u16x8 a, u16x8 b, f32x16 c) {
+  if constexpr (FMT == kSplitBf16)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+// Exponent e with m * 2^-e in [2^14, 2^15); 0 for a zero, NaN or infinite m
+// (non-finite inputs then stay non-finite through the split).
+__device__ __forceinline__ int scale_exponent(float m) {
+  if (!(m > 0.f) || !(m <= 3.402823466e38f)) return 0;
+  return __builtin_amdgcn_frexp_expf(m) - 15;
+}
+
+__device__ __forceinline__ float wave_max(float m) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  return m;
+}
+
+constexpr int kScaleRowsPerBlock = 16;   // 4 rows per wavefront
+constexpr int kScaleColsPerBlock = 256;  // one column per thread
+
+}  // namespace
+
+// Scale exponents of the FP16 form, one block range per descriptor:
+// blocks [0, a_blocks) of a descriptor's range take 16 rows of A each (max
+// over the kmax reduction columns), blocks [a_blocks, per_desc) take 256
+// columns of B each (max over the kmax reduction rows).  Only valid rows and
+// columns are read and written.
+template <bool VEC>
+__global__ void __launch_bounds__(256)
+leaf_scale_kernel(const GemmDesc* __restrict__ descs, int a_blocks, int per_desc) {
+  const GemmDesc& d = descs[blockIdx.x / per_desc];
+  const int blk = blockIdx.x % per_desc;
+  const int kmax = d.kmax;
+  const int tid = threadIdx.x;
+  if (blk < a_blocks) {
+    const int lane = tid & 63, wave = tid >> 6;
+    const int row0 = blk * kScaleRowsPerBlock + wave * 4;
+    for (int rr = 0; rr < 4; ++rr) {
+      const int r = row0 + rr;
+      if (r >= d.a_rows) break;
+      const float* a = d.A + (int64_t)r * d.lda;
+      float m = 0.f;
+      if (VEC) {
+        for (int k = 4 * lane; k < kmax; k += 256) {
+          const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(a + k));
+          m = fmaxf(m, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+        }
+      } else {
+        for (int k = lane; k < kmax; k += 64) m = fmaxf(m, fabsf(a[k]));
+      }
+      m = wave_max(m);
+      if (lane == 0) d.ea[r] = scale_exponent(m);
+    }
+  } else {
+    const int c = (blk - a_blocks) * kScaleColsPerBlock + tid;
+    if (c >= d.b_cols) return;
+    const float* b = d.B + c;
+    const int64_t ldb = d.ldb;
+    float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
+    int k = 0;
+    for (; k + 4 <= kmax; k += 4) {
+      m0 = fmaxf(m0, fabsf(b[(int64_t)k * ldb]));
+      m1 = fmaxf(m1, fabsf(b[(int64_t)(k + 1) * ldb]));
+      m2 = fmaxf(m2, fabsf(b[(int64_t)(k + 2) * ldb]));
+      m3 = fmaxf(m3, fabsf(b[(int64_t)(k + 3) * ldb]));
+    }
+    for (; k < kmax; ++k) m0 = fmaxf(m0, fabsf(b[(int64_t)k * ldb]));
+    d.eb[c] = scale_exponent(fmaxf(fmaxf(m0, m1), fmaxf(m2, m3)));
+  }
+}
+
+template <int FMT, bool VEC>
+__global__ void __launch_bounds__(256)
+leaf_split_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles, int xcd_chunk) {
+  constexpr int BM = 128, BN = 128, BK = 32;
+  constexpr int WM = 64, WN = 64, FM = 2, FN = 2;
+  constexpr int LDK = BK + 8;  // 16-bit elements per LDS row (80 bytes: conflict-free 16-byte reads)
+  constexpr bool kScaled = FMT == kSplitFp16;
+
+  __shared__ __attribute__((aligned(16))) unsigned short Ah[2][BM * LDK], Al[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) unsigned short Bh[2][BN * LDK], Bl[2][BN * LDK];
+
+  // Tile of this workgroup: the same XCD mapping and grouped walk as the FP32 leaf.
+  const int logical = leaf_tile_of_block(blockIdx.x, gridDim.x, xcd_chunk);
+  if (logical >= total_tiles) return;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= logical) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc& d = descs[lo];
+  const float* __restrict__ A = d.A;
+  const float* __restrict__ B = d.B;
+  float* __restrict__ C = d.C;
+  const int64_t lda = d.lda, ldb = d.ldb, ldc = d.ldc;
+  const int a_rows = d.a_rows, b_cols = d.b_cols, kmax = d.kmax;
+  const int c_rows = d.c_rows, c_cols = d.c_cols;
+  const int tiles_n = d.tiles_n;
+  const int beta = d.beta;
+  const int tiles_m = (c_rows + BM - 1) / BM;
+  const int lt = logical - d.tile_begin;
+  constexpr int GROUP = 8;
+  const int group_tiles = GROUP * tiles_n;
+  const int g = lt / group_tiles;
+  const int first_m = g * GROUP;
+  const int gm = min(tiles_m - first_m, GROUP);
+  const int in_g = lt - g * group_tiles;
+  const int tm = (first_m + in_g % gm) * BM;
+  const int tn = (in_g / gm) * BN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int lr = lane & 31, lh = lane >> 5;
+
+  // A: thread loads rows a_r + 32 i (i = 0..3), columns a_c..a_c+3.
+  const int a_r = tid / 8, a_c = (tid % 8) * 4;
+  // B: thread loads column b_n, k-rows b_k..b_k+15 (4-byte loads, coalesced
+  // across the wave), and writes them as one row of the [n][k] arrays: the
+  // lanes of a store then write consecutive rows, which fall on distinct
+  // LDS banks (four columns per thread gave 8-way bank conflicts).
+  const int b_n = tid & (BN - 1), b_k = (tid / BN) * 16;
+
+  const int rv = min(BM, a_rows - tm);
+  const int cv = min(BN, b_cols - tn);
+  const float* a_tile = A + (int64_t)tm * lda;
+  const float* b_tile = B + tn;
+  constexpr int kOOB = 0x7FFFFFF0;
+
+  // Scale exponents of the rows and the column this thread splits.
+  int ea_ld[4] = {0, 0, 0, 0};
+  int eb_ld = 0;
+  if constexpr (kScaled) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (a_r + 32 * i < rv) ea_ld[i] = d.ea[tm + a_r + 32 * i];
+    if (b_n < cv) eb_ld = d.eb[tn + b_n];
+  }
+
+  float4 ra[4];
+  float rb[16];
+  auto load_slab = [&](int k0) {
+    const int kv = min(BK, kmax - k0);
+    const uint32_t a_bytes =
+        (rv > 0 && kv > 0) ? (uint32_t)(((int64_t)(rv - 1) * lda + kv) * 4) : 0u;
+    const uint32_t b_bytes =
+        (cv > 0 && kv > 0) ? (uint32_t)(((int64_t)(kv - 1) * ldb + cv) * 4) : 0u;
+    const __amdgpu_buffer_rsrc_t ar = make_rsrc16(a_tile + k0, (int)a_bytes);
+    const __amdgpu_buffer_rsrc_t br = make_rsrc16(b_tile + (int64_t)k0 * ldb, (int)b_bytes);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = a_r + 32 * i;
+      const int base = (r * (int)lda + a_c) * 4;
+      if (VEC) {
+        const int off = (r < rv && a_c < kv) ? base : kOOB;
+        ra[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(ar, off, 0, 0));
+      } else {
+        float e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int off = (r < rv && a_c + q < kv) ? base + 4 * q : kOOB;
+          e[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ar, off, 0, 0));
+        }
+        ra[i] = make_float4(e[0], e[1], e[2], e[3]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int k = b_k + i;
+      const int off = (k < kv && b_n < cv) ? (k * (int)ldb + b_n) * 4 : kOOB;
+      rb[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(br, off, 0, 0));
+    }
+  };
+
+  auto store_slab = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      u16x4 h, l;
+      split4<FMT>(ra[i], ea_ld[i], h, l);
+      const int o = (a_r + 32 * i) * LDK + a_c;
+      *reinterpret_cast<u16x4*>(&Ah[buf][o]) = h;
+      *reinterpret_cast<u16x4*>(&Al[buf][o]) = l;
+    }
+    // B: the 16 k of column b_n go to row b_n of the [n][k] arrays, 8 at a
+    // time (16-byte stores).
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      u16x4 h0, l0, h1, l1;
+      split4<FMT>(make_float4(rb[8 * q], rb[8 * q + 1], rb[8 * q + 2], rb[8 * q + 3]), eb_ld, h0, l0);
+      split4<FMT>(make_float4(rb[8 * q + 4], rb[8 * q + 5], rb[8 * q + 6], rb[8 * q + 7]), eb_ld, h1, l1);
+      const u16x8 h = {h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+      const u16x8 l = {l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+      const int o = b_n * LDK + b_k + 8 * q;
+      *reinterpret_cast<u16x8*>(&Bh[buf][o]) = h;
+      *reinterpret_cast<u16x8*>(&Bl[buf][o]) = l;
+    }
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int nk = (kmax + BK - 1) / BK;
+  if (nk > 0) {
+    load_slab(0);
+    store_slab(0);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) load_slab((kt + 1) * BK);
+#pragma unroll
+    for (int g16 = 0; g16 < BK / 16; ++g16) {
+      // Lane half h supplies k = 16 g16 + 8 h + e (e = 0..7) for both operands.
+      const int kb = g16 * 16 + lh * 8;
+      u16x8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int o = (wm + 32 * i + lr) * LDK + kb;
+        ah[i] = *reinterpret_cast<const u16x8*>(&Ah[cur][o]);
+        al[i] = *reinterpret_cast<const u16x8*>(&Al[cur][o]);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int o = (wn + 32 * j + lr) * LDK + kb;
+        bh[j] = *reinterpret_cast<const u16x8*>(&Bh[cur][o]);
+        bl[j] = *reinterpret_cast<const u16x8*>(&Bl[cur][o]);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acc[i][j] = mfma16<FMT>(al[i], bh[j], acc[i][j]);
+          acc[i][j] = mfma16<FMT>(ah[i], bl[j], acc[i][j]);
+          acc[i][j] = mfma16<FMT>(ah[i], bh[j], acc[i][j]);
+        }
+    }
+    if (more) store_slab(cur ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: register r of block (i, j) holds row 8*(r/4) + 4*(lane/32) + r%4
+  // and column lane%32 of that 32x32 block.  The FP16 form undoes the row
+  // and column scales here.
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = tn + wn + 32 * j + lr;
+      if (col >= c_cols) continue;
+      int ec = 0;
+      if constexpr (kScaled) ec = col < b_cols ? d.eb[col] : 0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = tm + wm + 32 * i + 8 * (r >> 2) + 4 * lh + (r & 3);
+        if (row < c_rows) {
+          float v = acc[i][j][r];
+          if constexpr (kScaled) v = __builtin_ldexpf(v, ec + (row < a_rows ? d.ea[row] : 0));
+          float* cp = C + (int64_t)row * ldc + col;
+          *cp = beta ? *cp + v : v;
+        }
+      }
+    }
+}
+
+void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
+                        hipStream_t stream, int xcd_chunk) {
+  if (total_tiles <= 0) return;
+  dim3 grid(total_tiles), block(256);
+  if (vec)
+    hipLaunchKernelGGL((leaf_split_kernel<kSplitBf16, true>), grid, block, 0, stream, d_descs, ndesc,
+                       total_tiles, xcd_chunk);
+  else
+    hipLaunchKernelGGL((leaf_split_kernel<kSplitBf16, false>), grid, block, 0, stream, d_descs, ndesc,
+                       total_tiles, xcd_chunk);
+  FASTMM_HIP(hipGetLastError());
+}
+
+int leaf_scale_blocks(int a_rows, int b_cols) {
+  return (a_rows + kScaleRowsPerBlock - 1) / kScaleRowsPerBlock +
+         (b_cols + kScaleColsPerBlock - 1) / kScaleColsPerBlock;
+}
+
+void launch_leaf_fp16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
+                        hipStream_t stream, int xcd_chunk, int max_a_rows, int max_b_cols) {
+  if (total_tiles <= 0) return;
+  const int a_blocks = (max_a_rows + kScaleRowsPerBlock - 1) / kScaleRowsPerBlock;
+  const int per_desc = leaf_scale_blocks(max_a_rows, max_b_cols);
+  if ((int64_t)per_desc * ndesc > INT32_MAX) throw Error(kNotSupported, "scale launch too large");
+  if (per_desc > 0) {
+    dim3 sgrid(per_desc * ndesc), sblock(256);
+    if (vec)
+      hipLaunchKernelGGL((leaf_scale_kernel<true>), sgrid, sblock, 0, stream, d_descs, a_blocks, per_desc);
+    else
+      hipLaunchKernelGGL((leaf_scale_kernel<false>), sgrid, sblock, 0, stream, d_descs, a_blocks, per_desc);
+    FASTMM_HIP(hipGetLastError());
+  }
+  dim3 grid(total_tiles), block(256);
+  if (vec)
+    hipLaunchKernelGGL((leaf_split_kernel<kSplitFp16, true>), grid, block, 0, stream, d_descs, ndesc,
+                       total_tiles, xcd_chunk);
+  else
+    hipLaunchKernelGGL((leaf_split_kernel<kSplitFp16, false>), grid, block, 0, stream, d_descs, ndesc,
+                       total_tiles, xcd_chunk);
+  FASTMM_HIP(hipGetLastError());
+}
+
+}  // namespace fastmm

@@ -44,6 +44,8 @@ void rmul_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
   validate_gemm_args(M, N, K, A, lda, B, ldb, C, ldc, depth);
   if (depth < 0) throw Error(kInvalidValue, "depth must be >= 0 for the classic recursion");
   if (tile < 0 || tile >= kNumTiles) throw Error(kInvalidValue, "unknown tile id");
+  if (tile == kTileFp16x3)
+    throw Error(kNotSupported, "the scaled FP16 leaf is not available in the classic recursion");
   ensure_init(L);
   fastmm_stats_t st{};
   st.h2d_ms = st.preadd_ms = st.leaf_ms = st.postadd_ms = st.d2h_ms = st.total_ms = -1.0;

@@ -1,9 +1,13 @@
-"""Precision form of the leaf (split BF16, "bf16x3"): products of hi/lo BF16
-halves accumulated in FP32 on the BF16 matrix cores; quadrant additions stay
-FP32.  Checked against the FP64 oracle: exact on integers the split
-represents exactly, and the relative error reported per result for uniform
-and log-uniform inputs (the accuracy is about 2^-16 per product instead of
-FP32's 2^-24, so the bounds here are looser than the FP32 leaf's)."""
+"""Precision forms of the leaf: split BF16 ("bf16x3", hi/lo BF16 halves on
+the BF16 matrix cores) and scaled split FP16 ("fp16x3", each row of a leaf's
+A and column of its B scaled by a power of two, then split into hi/lo FP16
+halves on the FP16 matrix cores); products accumulate in FP32 and the
+quadrant additions stay FP32.  Checked against the FP64 oracle: exact on
+integers the split represents exactly, the relative error reported per
+result for uniform and log-uniform inputs (bf16x3: about 2^-16 per product;
+fp16x3: about 2^-21, the FP32 leaf's level), and for fp16x3 the scaling
+itself: exact equivariance under power-of-two row and column scalings, and
+inputs far outside FP16's range."""
 import numpy as np
 import pytest
 
@@ -14,13 +18,16 @@ from tests.gpu_util import dev, empty_dev, host, ints, say, uniform
 
 pytestmark = pytest.mark.gpu
 BF = 8  # FASTMM_TILE_BF16X3_128x128
+FP = 9  # FASTMM_TILE_FP16X3_128x128
 
 
+@pytest.mark.parametrize("tile", [BF, FP])
 @pytest.mark.parametrize("m,k,n,depth", [(256, 256, 256, 0), (257, 131, 383, 0), (300, 200, 100, 2),
                                          (512, 512, 512, 3)])
-def test_bf16x3_exact_on_small_integers(fastmm, m, k, n, depth):
-    # Integers of magnitude <= 3 have an exact BF16 hi part and zero lo part;
-    # with every partial sum below 2^24 the result is exact.
+def test_split_exact_on_small_integers(fastmm, m, k, n, depth, tile):
+    # Integers of magnitude <= 256 have an exact BF16 (and FP16) hi part and
+    # zero lo part, also after fp16x3's power-of-two scaling; with every
+    # partial sum below 2^24 the result is exact.
     A = ints(141 + m, m, k, -3, 3)
     B = ints(142 + n, k, n, -3, 3)
     cert = W.Certificate()
@@ -33,39 +40,127 @@ def test_bf16x3_exact_on_small_integers(fastmm, m, k, n, depth):
     ref = W.winograd(A.astype(np.int64), B.astype(np.int64), depth, 1, cert, leaf_fn=leaf)
     assert cert.exact_in_fp32 and leaf_max[0] <= 256
     C = empty_dev(m, n)
-    fastmm.gemm(m, n, k, dev(A), dev(B), C, depth=depth, leaf=1, tile=BF)
+    fastmm.gemm(m, n, k, dev(A), dev(B), C, depth=depth, leaf=1, tile=tile)
     assert np.array_equal(host(C).astype(np.int64), ref)
 
 
+# (tile, n, depth, bound on the relative Frobenius error)
+ERROR_CASES = [(BF, 512, 0, 5e-5), (BF, 1024, 2, 2e-4), (BF, 768, 1, 1e-4),
+               (FP, 512, 0, 2e-6), (FP, 1024, 2, 5e-6), (FP, 768, 1, 3e-6), (FP, 1000, 3, 1e-5)]
+
+
 @pytest.mark.parametrize("dist", ["uniform", "loguniform"])
-@pytest.mark.parametrize("n,depth,bound", [(512, 0, 5e-5), (1024, 2, 2e-4), (768, 1, 1e-4)])
-def test_bf16x3_error_vs_oracle(fastmm, dist, n, depth, bound):
+@pytest.mark.parametrize("tile,n,depth,bound", ERROR_CASES)
+def test_split_error_vs_oracle(fastmm, dist, tile, n, depth, bound):
     gen = synthgen.uniform_pm1 if dist == "uniform" else synthgen.loguniform
     A = gen(1001 + 4, n, n)
     B = gen(2001 + 4, n, n)
     C = empty_dev(n, n)
-    fastmm.gemm(n, n, n, dev(A), dev(B), C, depth=depth, leaf=1, tile=BF)
+    fastmm.gemm(n, n, n, dev(A), dev(B), C, depth=depth, leaf=1, tile=tile)
     ref = classic.gemm(A, B)
     e = checks.rel_frob(host(C), ref)
     # the FP32 leaf on the same inputs, for the record
     C32 = empty_dev(n, n)
     fastmm.gemm(n, n, n, dev(A), dev(B), C32, depth=depth, leaf=1, tile=0)
     e32 = checks.rel_frob(host(C32), ref)
-    say(f"  bf16x3 {dist} n={n} depth={depth}: rel_frob={e:.3e} (fp32 leaf {e32:.3e})")
+    say(f"  tile {tile} {dist} n={n} depth={depth}: rel_frob={e:.3e} (fp32 leaf {e32:.3e})")
     assert e <= bound
+    if tile == FP:  # FP32-level: within a small factor of the FP32 leaf
+        assert e <= 2 * e32
 
 
+@pytest.mark.parametrize("tile,bound", [(BF, 2e-4), (FP, 2e-5)])
 @pytest.mark.parametrize("n", [8192, 16384])
-def test_config4_depth2_sampled(fastmm, n):
+def test_split_depth2_sampled(fastmm, n, tile, bound):
     # n = 8192 and 16384, depth 2, both input distributions.
+    rows = synthgen.row_sample(7008, n, 12)
+    x = synthgen.signs_pm1(7009, n)
     for dist, gen in [("uniform", synthgen.uniform_pm1), ("loguniform", synthgen.loguniform)]:
         A = gen(1001 + 4, n, n)
         B = gen(2001 + 4, n, n)
-        C = empty_dev(n, n)
-        fastmm.gemm(n, n, n, dev(A), dev(B), C, depth=2, leaf=1, tile=BF)
+        dA, dB, C = dev(A), dev(B), empty_dev(n, n)
+        fastmm.gemm(n, n, n, dA, dB, C, depth=2, leaf=1, tile=tile)
         got = host(C)
-        rows = synthgen.row_sample(7008, n, 12)
         e_rows = checks.sampled_rows_rel(got, A, B, rows)
-        e_fv = checks.freivalds_rel(got, A, B, synthgen.signs_pm1(7009, n))
-        say(f"  split-BF16 {dist} n={n}: sampled-rows rel={e_rows:.3e} freivalds rel={e_fv:.3e}")
-        assert e_rows <= 2e-4 and e_fv <= 2e-4
+        e_fv = checks.freivalds_rel(got, A, B, x)
+        say(f"  tile {tile} {dist} n={n}: sampled-rows rel={e_rows:.3e} freivalds rel={e_fv:.3e}")
+        assert e_rows <= bound and e_fv <= bound
+        if tile == FP:  # FP32-level: within a small factor of the FP32 leaf
+            fastmm.gemm(n, n, n, dA, dB, C, depth=2, leaf=1, tile=0)
+            e32 = checks.sampled_rows_rel(host(C), A, B, rows)
+            say(f"    fp32 leaf sampled-rows rel={e32:.3e}")
+            assert e_rows <= 2 * e32
+        del dA, dB, C
+
+
+def _pow2_scaled(X, row_exp=None, col_exp=None):
+    Y = X.astype(np.float64)
+    if row_exp is not None:
+        Y = np.ldexp(Y, row_exp[:, None])
+    if col_exp is not None:
+        Y = np.ldexp(Y, col_exp[None, :])
+    return Y.astype(np.float32)
+
+
+@pytest.mark.parametrize("m,k,n", [(300, 200, 257), (129, 515, 640)])
+def test_fp16x3_row_column_scaling_is_exact(fastmm, m, k, n):
+    # Depth 0: a leaf's scales follow its operands' rows and columns, so
+    # scaling row i of A by 2^r_i and column j of B by 2^c_j scales C[i, j] by
+    # exactly 2^(r_i + c_j), bit for bit.
+    A, B = uniform(3501, m, k), uniform(3502, k, n)
+    r = synthgen.int_range(3503, m, 1, -40, 40)[:, 0].astype(np.int64)
+    c = synthgen.int_range(3504, 1, n, -30, 30)[0].astype(np.int64)
+    C1, C2 = empty_dev(m, n), empty_dev(m, n)
+    fastmm.gemm(m, n, k, dev(A), dev(B), C1, depth=0, tile=FP)
+    fastmm.gemm(m, n, k, dev(_pow2_scaled(A, row_exp=r)), dev(_pow2_scaled(B, col_exp=c)), C2,
+                depth=0, tile=FP)
+    assert np.array_equal(host(C2), _pow2_scaled(host(C1), row_exp=r, col_exp=c))
+
+
+@pytest.mark.parametrize("depth", [1, 2])
+def test_fp16x3_global_scaling_is_exact(fastmm, depth):
+    # Any depth: a power of two on all of A (B) passes exactly through the
+    # FP32 quadrant additions and the per-row (per-column) scales.
+    n = 1100
+    A, B = uniform(3511, n, n), uniform(3512, n, n)
+    C1, C2 = empty_dev(n, n), empty_dev(n, n)
+    fastmm.gemm(n, n, n, dev(A), dev(B), C1, depth=depth, leaf=1, tile=FP)
+    fastmm.gemm(n, n, n, dev(np.ldexp(A, 60)), dev(np.ldexp(B, -70)), C2, depth=depth, leaf=1,
+                tile=FP)
+    assert np.array_equal(host(C2), np.ldexp(host(C1), -10))
+
+
+@pytest.mark.parametrize("depth,row_spread", [(0, 20), (2, 0)])
+def test_fp16x3_outside_fp16_range(fastmm, depth, row_spread):
+    # Magnitudes near 1e30 and 1e-25, far outside FP16's 6e-8..65504.  At
+    # depth 0 the rows of A also differ by up to 2^+-20 and every row is
+    # checked on its own.  (Deeper, the quadrant additions mix rows of
+    # different magnitude, which costs the small rows accuracy in any
+    # arithmetic, FP32 included: there the whole matrix is checked.)
+    m, k, n = 640, 700, 520
+    r = synthgen.int_range(3521, m, 1, -row_spread, row_spread)[:, 0].astype(np.int64)
+    A = _pow2_scaled(uniform(3522, m, k) * np.float32(1e30), row_exp=r)
+    B = uniform(3523, k, n) * np.float32(1e-25)
+    C = empty_dev(m, n)
+    fastmm.gemm(m, n, k, dev(A), dev(B), C, depth=depth, leaf=1, tile=FP)
+    got = host(C)
+    ref = classic.gemm(A, B)
+    e_row = np.max(np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1))
+    e = checks.rel_frob(got, ref)
+    say(f"  fp16x3 outside FP16 range, depth {depth}: max row rel={e_row:.3e} rel_frob={e:.3e}")
+    assert np.isfinite(got).all() and e <= 3e-6
+    if depth == 0:
+        assert e_row <= 2e-6
+
+
+def test_fp16x3_host_operands(fastmm):
+    # Pinned host operands: the transfer-pipelined path with the FP16 leaf.
+    import torch
+    m, k, n = 1000, 900, 1100
+    A, B = uniform(3531, m, k), uniform(3532, k, n)
+    Ah, Bh = torch.from_numpy(A).pin_memory(), torch.from_numpy(B).pin_memory()
+    Ch = torch.full((m, n), float("nan")).pin_memory()
+    fastmm.gemm(m, n, k, Ah, Bh, Ch, depth=2, leaf=1, tile=FP)
+    e = checks.rel_frob(Ch.numpy(), classic.gemm(A, B))
+    say(f"  fp16x3 host operands: rel_frob={e:.3e}")
+    assert e <= 2e-6
