@@ -29,8 +29,13 @@ struct GemmDesc {
   int32_t tiles_n;          // ceil(c_cols / BN) for the launch's tile shape
   int32_t tile_begin;       // first tile of this problem within the launch
   int32_t beta;             // 0: C = A B; 1: C += A B
-  // Scaled FP16 leaf only: power-of-two exponents of the a_rows rows of A
-  // and the b_cols columns of B (written by its scale pass); else unused.
+  // Split-precision leaves only (else unused): the packed hi/lo operands
+  // (leaf_packed_bytes in all, B's part from pa + leaf_packed_a_bytes) and,
+  // for the scaled FP16 form, power-of-two exponents of the a_rows rows of A
+  // and the b_cols columns of B, eb followed by ceil(kmax / 256) x b_cols
+  // floats of scratch (leaf_scale_bytes in all).
+  void* pa;
+  void* pb;
   int32_t* ea;
   int32_t* eb;
 };
@@ -185,6 +190,11 @@ struct TileShape {
   int bm, bn;
 };
 
+// Macro tile and wavefront grid of the split-precision leaves on packed
+// operands (tile ids kTileBf16x3 and kTileFp16x3 of the level-wise engine).
+constexpr int kSplitTileM = 256, kSplitTileN = 256;
+constexpr int kSplitWavesM = 4, kSplitWavesN = 2;
+
 inline TileShape tile_shape(int id) {
   switch (id) {
     case kTile128x128: return {128, 128};
@@ -195,8 +205,8 @@ inline TileShape tile_shape(int id) {
     case kTile256x128w8: return {256, 128};
     case kTile256x256w8: return {256, 256};
     case kTile128x256: return {128, 256};
-    case kTileBf16x3: return {128, 128};
-    case kTileFp16x3: return {128, 128};
+    case kTileBf16x3: return {kSplitTileM, kSplitTileN};
+    case kTileFp16x3: return {kSplitTileM, kSplitTileN};
     default: throw Error(kInvalidValue, "unknown tile id " + std::to_string(id));
   }
 }
@@ -230,11 +240,20 @@ void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_ti
                       hipStream_t stream, int xcd_chunk = 0, int* queue = nullptr);
 void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
                         hipStream_t stream, int xcd_chunk = 0);
-// The scaled FP16 form: a scale pass over every descriptor's operands (rows
-// of A up to max_a_rows, columns of B up to max_b_cols; each descriptor's
-// ea / eb must hold a_rows / b_cols ints), then the leaf launch.
-void launch_leaf_fp16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
-                        hipStream_t stream, int xcd_chunk, int max_a_rows, int max_b_cols);
+// Split-precision leaves on packed operands (tile kTileBf16x3 or
+// kTileFp16x3): for FP16 a scale pass (each descriptor's ea / eb hold a_rows
+// / b_cols ints), then a pass that packs both operands of every descriptor
+// into pa / pb, then the leaf.  ext: largest extents over the descriptors.
+struct LeafExtents {
+  int max_a_rows = 0, max_b_cols = 0, max_c_rows = 0, max_c_cols = 0, max_slabs = 0, max_kmax = 0;
+};
+// Bytes of the FP16 scale exponents and scratch of a rows x k by k x cols leaf.
+int64_t leaf_scale_bytes(int64_t rows, int64_t cols, int64_t k);
+// Bytes of the packed operands of a rows x k by k x cols leaf (A's part first).
+int64_t leaf_packed_bytes(int64_t rows, int64_t cols, int64_t k);
+int64_t leaf_packed_a_bytes(int64_t rows, int64_t k);
+void launch_leaf_packed(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
+                        hipStream_t stream, int xcd_chunk, const LeafExtents& ext);
 void launch_preadd(int side, const PreAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
                    hipStream_t stream);
 // quad < 0: all four result quadrants; 0..3: only C11, C12, C21 or C22

@@ -206,10 +206,16 @@ size_t problem_temp_bytes(const Problem& p) {
   }
   for (int l = 1; l <= p.depth; ++l)
     floats += align_up((size_t)pow7(l) * dims[l].m * dims[l].n, kAlignFloats);
-  // Scaled FP16 leaves: one int exponent per row of A and per column of B of
-  // every leaf.
+  // Split-precision leaves: both operands of every leaf packed as hi/lo
+  // 16-bit tiles; for FP16 also one int exponent per row of A and per
+  // column of B.
+  const Dims& lf = dims[p.depth];
+  if (p.tile == kTileBf16x3 || p.tile == kTileFp16x3)
+    floats += align_up((size_t)pow7(p.depth) * (size_t)leaf_packed_bytes(lf.m, lf.n, lf.k) / 4,
+                       kAlignFloats);
   if (p.tile == kTileFp16x3)
-    floats += align_up((size_t)pow7(p.depth) * (dims[p.depth].m + dims[p.depth].n), kAlignFloats);
+    floats += align_up((size_t)pow7(p.depth) * (size_t)leaf_scale_bytes(lf.m, lf.n, lf.k) / 4,
+                       kAlignFloats);
   return floats * sizeof(float);
 }
 
@@ -281,13 +287,21 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     const Dims lf = dims[d];
     const int64_t nleaves = pow7(d);
     const TileShape ts = tile_shape(p.tile);
+    const bool split = p.tile == kTileBf16x3 || p.tile == kTileFp16x3;
+    const int64_t packed = split ? leaf_packed_bytes(lf.m, lf.n, lf.k) : 0;
+    char* packs = split ? reinterpret_cast<char*>(carve((size_t)(nleaves * packed / 4))) : nullptr;
+    const int64_t scale_ints = leaf_scale_bytes(lf.m, lf.n, lf.k) / 4;
     int32_t* exps = p.tile == kTileFp16x3
-                        ? reinterpret_cast<int32_t*>(carve((size_t)nleaves * (lf.m + lf.n)))
+                        ? reinterpret_cast<int32_t*>(carve((size_t)(nleaves * scale_ints)))
                         : nullptr;
     for (int64_t x = 0; x < nleaves; ++x) {
       GemmDesc g{};
+      if (packs) {
+        g.pa = packs + x * packed;
+        g.pb = packs + x * packed + leaf_packed_a_bytes(lf.m, lf.k);
+      }
       if (exps) {
-        g.ea = exps + x * (lf.m + lf.n);
+        g.ea = exps + x * scale_ints;
         g.eb = g.ea + lf.m;
       }
       g.A = Av[x].p;
@@ -445,15 +459,19 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
   if (leaf_begin) FASTMM_HIP(hipEventRecord(leaf_begin, L.stream));
   for (int t = 0; t < kNumTiles; ++t) {
     if (s.leaf_tiles_total[t] <= 0) continue;
-    if (t == kTileFp16x3) {
-      int max_rows = 0, max_cols = 0;
+    if (t == kTileBf16x3 || t == kTileFp16x3) {
+      LeafExtents ext;
       for (const auto& g : s.leaf[t]) {
-        max_rows = std::max(max_rows, (int)g.a_rows);
-        max_cols = std::max(max_cols, (int)g.b_cols);
+        ext.max_a_rows = std::max(ext.max_a_rows, (int)g.a_rows);
+        ext.max_b_cols = std::max(ext.max_b_cols, (int)g.b_cols);
+        ext.max_c_rows = std::max(ext.max_c_rows, (int)g.c_rows);
+        ext.max_c_cols = std::max(ext.max_c_cols, (int)g.c_cols);
+        ext.max_slabs = std::max(ext.max_slabs, (int)((g.kmax + 31) / 32));
+        ext.max_kmax = std::max(ext.max_kmax, (int)g.kmax);
       }
-      launch_leaf_fp16x3(s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t],
-                         L.stream, s.xcd_chunk[t], max_rows, max_cols);
-      launches += 2;
+      launch_leaf_packed(t, s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t],
+                         L.stream, s.xcd_chunk[t], ext);
+      launches += t == kTileFp16x3 ? 3 : 2;
     } else {
       launch_leaf_gemm(t, s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t],
                        L.stream, s.xcd_chunk[t], s.persistent ? L.leaf_queue : nullptr);

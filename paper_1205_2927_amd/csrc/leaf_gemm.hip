@@ -402,8 +402,8 @@ void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_ti
     case kTile256x256w8: launch_t<256, 256, 16, 2, 4>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
     case kTile128x256: launch_t<128, 256, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
     case kTileBf16x3: launch_leaf_bf16x3(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk); break;
-    case kTileFp16x3:  // needs the operand extents for its scale pass
-      throw Error(kInvalidValue, "the scaled FP16 leaf is launched by launch_leaf_fp16x3");
+    case kTileFp16x3:  // needs packed-operand storage and the operand extents
+      throw Error(kInvalidValue, "the scaled FP16 leaf is launched by launch_leaf_packed");
     default: throw Error(kInvalidValue, "unknown tile id");
   }
 }

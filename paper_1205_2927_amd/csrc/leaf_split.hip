@@ -114,16 +114,19 @@ __device__ __forceinline__ float wave_max(float m) {
   return m;
 }
 
-constexpr int kScaleRowsPerBlock = 16;   // 4 rows per wavefront
-constexpr int kScaleColsPerBlock = 256;  // one column per thread
+constexpr int kScaleRowsPerBlock = 4;    // one row of A per wavefront
+constexpr int kScaleColsPerBlock = 256;  // one column of B per thread
+constexpr int kScaleRowsPerPart = 256;   // rows of B per partial column maximum
 
 }  // namespace
 
-// Scale exponents of the FP16 form, one block range per descriptor:
-// blocks [0, a_blocks) of a descriptor's range take 16 rows of A each (max
-// over the kmax reduction columns), blocks [a_blocks, per_desc) take 256
-// columns of B each (max over the kmax reduction rows).  Only valid rows and
-// columns are read and written.
+// Scale exponents of the FP16 form, one block range per descriptor.
+// Blocks [0, a_blocks) take 4 rows of A each, one per wavefront (max over
+// the kmax reduction columns), and store e_A.  Blocks [a_blocks, per_desc)
+// take 256 columns of B by 256 rows each and store the partial maxima in the
+// scratch after e_B (ceil(kmax / 256) x b_cols floats); leaf_scale_b_kernel
+// then reduces them to e_B.  Splitting B's reduction keeps enough loads in
+// flight: one thread per column walking all kmax rows is latency-bound.
 template <bool VEC>
 __global__ void __launch_bounds__(256)
 leaf_scale_kernel(const GemmDesc* __restrict__ descs, int a_blocks, int per_desc) {
@@ -133,39 +136,62 @@ leaf_scale_kernel(const GemmDesc* __restrict__ descs, int a_blocks, int per_desc
   const int tid = threadIdx.x;
   if (blk < a_blocks) {
     const int lane = tid & 63, wave = tid >> 6;
-    const int row0 = blk * kScaleRowsPerBlock + wave * 4;
-    for (int rr = 0; rr < 4; ++rr) {
-      const int r = row0 + rr;
-      if (r >= d.a_rows) break;
-      const float* a = d.A + (int64_t)r * d.lda;
-      float m = 0.f;
-      if (VEC) {
-        for (int k = 4 * lane; k < kmax; k += 256) {
-          const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(a + k));
-          m = fmaxf(m, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
-        }
-      } else {
-        for (int k = lane; k < kmax; k += 64) m = fmaxf(m, fabsf(a[k]));
+    const int r = blk * kScaleRowsPerBlock + wave;
+    if (r >= d.a_rows) return;
+    const float* a = d.A + (int64_t)r * d.lda;
+    float m0 = 0.f, m1 = 0.f;
+    if (VEC) {
+      int k = 4 * lane;
+      for (; k + 256 < kmax; k += 512) {
+        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(a + k));
+        const f32x4 w = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(a + k + 256));
+        m0 = fmaxf(m0, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+        m1 = fmaxf(m1, fmaxf(fmaxf(fabsf(w[0]), fabsf(w[1])), fmaxf(fabsf(w[2]), fabsf(w[3]))));
       }
-      m = wave_max(m);
-      if (lane == 0) d.ea[r] = scale_exponent(m);
+      if (k < kmax) {
+        const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(a + k));
+        m0 = fmaxf(m0, fmaxf(fmaxf(fabsf(v[0]), fabsf(v[1])), fmaxf(fabsf(v[2]), fabsf(v[3]))));
+      }
+    } else {
+      for (int k = lane; k < kmax; k += 64) m0 = fmaxf(m0, fabsf(a[k]));
     }
+    const float m = wave_max(fmaxf(m0, m1));
+    if (lane == 0) d.ea[r] = scale_exponent(m);
   } else {
-    const int c = (blk - a_blocks) * kScaleColsPerBlock + tid;
+    const int parts = (kmax + kScaleRowsPerPart - 1) / kScaleRowsPerPart;
+    const int col_blocks = (d.b_cols + kScaleColsPerBlock - 1) / kScaleColsPerBlock;
+    const int u = blk - a_blocks;
+    if (u >= col_blocks * parts) return;
+    const int p = u / col_blocks;
+    const int c = (u - p * col_blocks) * kScaleColsPerBlock + tid;
     if (c >= d.b_cols) return;
-    const float* b = d.B + c;
+    const int k0 = p * kScaleRowsPerPart;
+    const int k1 = min(kmax, k0 + kScaleRowsPerPart);
     const int64_t ldb = d.ldb;
-    float m0 = 0.f, m1 = 0.f, m2 = 0.f, m3 = 0.f;
+    const float* b = d.B + (int64_t)k0 * ldb + c;
+    float m[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int k = 0;
-    for (; k + 4 <= kmax; k += 4) {
-      m0 = fmaxf(m0, fabsf(b[(int64_t)k * ldb]));
-      m1 = fmaxf(m1, fabsf(b[(int64_t)(k + 1) * ldb]));
-      m2 = fmaxf(m2, fabsf(b[(int64_t)(k + 2) * ldb]));
-      m3 = fmaxf(m3, fabsf(b[(int64_t)(k + 3) * ldb]));
-    }
-    for (; k < kmax; ++k) m0 = fmaxf(m0, fabsf(b[(int64_t)k * ldb]));
-    d.eb[c] = scale_exponent(fmaxf(fmaxf(m0, m1), fmaxf(m2, m3)));
+    const int n = k1 - k0;
+    for (; k + 8 <= n; k += 8)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) m[i] = fmaxf(m[i], fabsf(b[(int64_t)(k + i) * ldb]));
+    for (; k < n; ++k) m[0] = fmaxf(m[0], fabsf(b[(int64_t)k * ldb]));
+    const float mx = fmaxf(fmaxf(fmaxf(m[0], m[1]), fmaxf(m[2], m[3])), fmaxf(fmaxf(m[4], m[5]), fmaxf(m[6], m[7])));
+    reinterpret_cast<float*>(d.eb + d.b_cols)[(int64_t)p * d.b_cols + c] = mx;
   }
+}
+
+// e_B[c] from the partial column maxima of leaf_scale_kernel.
+__global__ void __launch_bounds__(256)
+leaf_scale_b_kernel(const GemmDesc* __restrict__ descs, int per_desc) {
+  const GemmDesc& d = descs[blockIdx.x / per_desc];
+  const int c = (blockIdx.x % per_desc) * 256 + threadIdx.x;
+  if (c >= d.b_cols) return;
+  const int parts = (d.kmax + kScaleRowsPerPart - 1) / kScaleRowsPerPart;
+  const float* part = reinterpret_cast<const float*>(d.eb + d.b_cols);
+  float m = 0.f;
+  for (int p = 0; p < parts; ++p) m = fmaxf(m, part[(int64_t)p * d.b_cols + c]);
+  d.eb[c] = scale_exponent(m);
 }
 
 template <int FMT, bool VEC>
@@ -367,6 +393,272 @@ leaf_split_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles
     }
 }
 
+// ---------------------------------------------------------------------------
+// Packed form.  A pass over every leaf's operands (leaf_pack_kernel) writes
+// them once as hi/lo 16-bit tiles, in exactly the order the leaf's LDS holds
+// them, so that the leaf (leaf_packed_kernel) copies slabs straight into LDS
+// and runs nothing but MFMAs: the register-split kernel above splits each A
+// slab once per column of tiles and each B slab once per row of tiles, about
+// as many VALU cycles as MFMA cycles.
+//
+// Packed layout of one leaf operand (A, or B read as B^T): blocks of 128 rows
+// of A (columns of B) by 32 k, zero beyond the valid extent; block (t, s) of
+// tile t and slab s at byte (t * slabs + s) * 16384, slabs = ceil(kmax / 32).
+// In a block the hi half (8 KB) comes first, then the lo half, each 128 rows
+// of 64 bytes; row r keeps k = 8c..8c+7 (16 bytes) in 16-byte slot
+// c ^ ((r >> 2) & 3), which makes the 16-byte fragment reads of the MFMA
+// loop free of LDS bank conflicts.
+namespace {
+constexpr int kPackRows = 128;
+constexpr int kPackK = 32;
+constexpr int kPackHalfBytes = kPackRows * kPackK * 2;   // 8 KB
+constexpr int kPackBlockBytes = 2 * kPackHalfBytes;      // 16 KB
+constexpr int kPackSlabsPerGroup = 4;                    // slabs per pack workgroup
+
+__device__ __forceinline__ int pack_slot(int r, int c) { return r * 64 + ((c ^ ((r >> 2) & 3)) << 4); }
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc_bytes(const void* p, int bytes) {
+  return make_rsrc16(reinterpret_cast<const float*>(p), bytes);
+}
+}  // namespace
+
+// One workgroup per (operand side, tile, group of 4 slabs) of a descriptor:
+// units [0, a_units) of a descriptor's range pack A, [a_units, per_desc)
+// pack B.  Each thread splits 8 consecutive k of one row (column) per step.
+template <int FMT, bool VEC>
+__global__ void __launch_bounds__(256)
+leaf_pack_kernel(const GemmDesc* __restrict__ descs, int a_units, int per_desc) {
+  const GemmDesc& d = descs[blockIdx.x / per_desc];
+  int u = blockIdx.x % per_desc;
+  const int kmax = d.kmax;
+  const int slabs = (kmax + kPackK - 1) / kPackK;
+  const int groups = (slabs + kPackSlabsPerGroup - 1) / kPackSlabsPerGroup;
+  const bool side_a = u < a_units;
+  if (!side_a) u -= a_units;
+  const int tiles = side_a ? (d.c_rows + kPackRows - 1) / kPackRows : (d.c_cols + kPackRows - 1) / kPackRows;
+  if (u >= tiles * groups) return;
+  const int t = u / groups;
+  const int s0 = (u - t * groups) * kPackSlabsPerGroup;
+  const int s1 = min(s0 + kPackSlabsPerGroup, slabs);
+  char* out = reinterpret_cast<char*>(side_a ? d.pa : d.pb) + (int64_t)t * slabs * kPackBlockBytes;
+  const int tid = threadIdx.x;
+  if (side_a) {
+    const int rv = min(kPackRows, d.a_rows - t * kPackRows);
+    const float* a = d.A + (int64_t)t * kPackRows * d.lda;
+    for (int s = s0; s < s1; ++s) {
+      const int k0 = s * kPackK;
+      const int kv = min(kPackK, kmax - k0);
+      char* blk = out + (int64_t)s * kPackBlockBytes;
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const int q = it * 256 + tid;
+        const int r = q >> 2, c = q & 3;
+        float4 x0 = make_float4(0.f, 0.f, 0.f, 0.f), x1 = x0;
+        int e = 0;
+        if (r < rv) {
+          const float* src = a + (int64_t)r * d.lda + k0 + 8 * c;
+          if (VEC && 8 * c + 8 <= kv) {
+            x0 = *reinterpret_cast<const float4*>(src);
+            x1 = *reinterpret_cast<const float4*>(src + 4);
+          } else {
+            float v[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) v[i] = (8 * c + i < kv) ? src[i] : 0.f;
+            x0 = make_float4(v[0], v[1], v[2], v[3]);
+            x1 = make_float4(v[4], v[5], v[6], v[7]);
+          }
+          if constexpr (FMT == kSplitFp16) e = d.ea[t * kPackRows + r];
+        }
+        u16x4 h0, l0, h1, l1;
+        split4<FMT>(x0, e, h0, l0);
+        split4<FMT>(x1, e, h1, l1);
+        const int o = pack_slot(r, c);
+        *reinterpret_cast<u16x8*>(blk + o) = u16x8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+        *reinterpret_cast<u16x8*>(blk + kPackHalfBytes + o) =
+            u16x8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+      }
+    }
+  } else {
+    const int cv = min(kPackRows, d.b_cols - t * kPackRows);
+    const int64_t ldb = d.ldb;
+    const float* b = d.B + (int64_t)t * kPackRows;
+    for (int s = s0; s < s1; ++s) {
+      const int k0 = s * kPackK;
+      const int kv = min(kPackK, kmax - k0);
+      char* blk = out + (int64_t)s * kPackBlockBytes;
+#pragma unroll
+      for (int it = 0; it < 2; ++it) {
+        const int q = it * 256 + tid;
+        const int n = q & (kPackRows - 1), c = q >> 7;  // lanes take consecutive columns
+        float v[8];
+        int e = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          v[i] = (n < cv && 8 * c + i < kv) ? b[(int64_t)(k0 + 8 * c + i) * ldb + n] : 0.f;
+        if constexpr (FMT == kSplitFp16) e = n < cv ? d.eb[t * kPackRows + n] : 0;
+        u16x4 h0, l0, h1, l1;
+        split4<FMT>(make_float4(v[0], v[1], v[2], v[3]), e, h0, l0);
+        split4<FMT>(make_float4(v[4], v[5], v[6], v[7]), e, h1, l1);
+        const int o = pack_slot(n, c);
+        *reinterpret_cast<u16x8*>(blk + o) = u16x8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+        *reinterpret_cast<u16x8*>(blk + kPackHalfBytes + o) =
+            u16x8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+      }
+    }
+  }
+}
+
+// Leaf on packed operands: TM x TN tiles on WGM x WGN wavefronts, K-slabs
+// of 32 double-buffered in LDS (the slab's A blocks, then its B blocks, 16 KB
+// per 128 rows or columns), each slab copied straight from the packed blocks
+// into LDS by buffer loads with the LDS bit (1 KB per wavefront
+// instruction).  A tile reaching past the last packed block of an operand
+// reads zeros there (empty buffer range).
+template <int FMT, int TM, int TN, int WGM, int WGN>
+__global__ void __launch_bounds__(64 * WGM * WGN, 2)
+leaf_packed_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles, int xcd_chunk) {
+  constexpr int BK = kPackK;
+  constexpr int kWaves = WGM * WGN;
+  constexpr int WM = TM / WGM, WN = TN / WGN, FM = WM / 32, FN = WN / 32;
+  constexpr int kABlocks = TM / kPackRows, kBBlocks = TN / kPackRows;
+  constexpr int kStageBytes = (kABlocks + kBBlocks) * kPackBlockBytes;
+  constexpr int kChunks = kStageBytes / 1024;
+  static_assert(kChunks % kWaves == 0, "slab chunks must divide among the wavefronts");
+  constexpr bool kScaled = FMT == kSplitFp16;
+  __shared__ __attribute__((aligned(1024))) char lds0[kStageBytes];
+  __shared__ __attribute__((aligned(1024))) char lds1[kStageBytes];
+
+  const int logical = leaf_tile_of_block(blockIdx.x, gridDim.x, xcd_chunk);
+  if (logical >= total_tiles) return;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].tile_begin <= logical) lo = mid; else hi = mid - 1;
+  }
+  const GemmDesc& d = descs[lo];
+  float* __restrict__ C = d.C;
+  const int64_t ldc = d.ldc;
+  const int a_rows = d.a_rows, b_cols = d.b_cols, kmax = d.kmax;
+  const int c_rows = d.c_rows, c_cols = d.c_cols;
+  const int tiles_n = d.tiles_n;
+  const int beta = d.beta;
+  const int tiles_m = (c_rows + TM - 1) / TM;
+  const int lt = logical - d.tile_begin;
+  constexpr int GROUP = 8;
+  const int group_tiles = GROUP * tiles_n;
+  const int g = lt / group_tiles;
+  const int first_m = g * GROUP;
+  const int gm = min(tiles_m - first_m, GROUP);
+  const int in_g = lt - g * group_tiles;
+  const int tm = (first_m + in_g % gm) * TM;
+  const int tn = (in_g / gm) * TN;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave / WGN) * WM, wn = (wave % WGN) * WN;
+  const int lr = lane & 31, lh = lane >> 5;
+
+  const int slabs = (kmax + BK - 1) / BK;
+  const int pack_m = (c_rows + kPackRows - 1) / kPackRows;  // packed blocks of A per slab column
+  const int pack_n = (c_cols + kPackRows - 1) / kPackRows;
+  const char* pa = reinterpret_cast<const char*>(d.pa);
+  const char* pb = reinterpret_cast<const char*>(d.pb);
+
+  auto load_slab = [&](int s, char* __restrict__ dst) {
+#pragma unroll
+    for (int j = 0; j < kChunks / kWaves; ++j) {
+      const int q = j * kWaves + wave;  // 1 KB chunk of the stage (wavefront-uniform)
+      const int blk = q / 16;           // packed block of the stage: A blocks, then B blocks
+      const bool is_a = blk < kABlocks;
+      const int t = is_a ? tm / kPackRows + blk : tn / kPackRows + (blk - kABlocks);
+      const bool there = t < (is_a ? pack_m : pack_n);
+      const char* src = (is_a ? pa : pb) + ((int64_t)t * slabs + s) * kPackBlockBytes;
+      const __amdgpu_buffer_rsrc_t r = make_rsrc_bytes(src, there ? kPackBlockBytes : 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(
+          r, (__attribute__((address_space(3))) void*)(dst + q * 1024), 16, (q % 16) * 1024 + lane * 16,
+          0, 0, 0);
+    }
+  };
+  // Byte offset of the 16-byte fragment (row R of the stage's A rows, or
+  // column R of its B columns, k-chunk c) in a stage.
+  auto a_frag = [](int R, int c) { return (R / kPackRows) * kPackBlockBytes + pack_slot(R % kPackRows, c); };
+  auto b_frag = [](int R, int c) {
+    return (kABlocks + R / kPackRows) * kPackBlockBytes + pack_slot(R % kPackRows, c);
+  };
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  auto step = [&](const char* __restrict__ cur, char* __restrict__ next, int s) {
+    const bool more = s + 1 < slabs;
+    if (more) load_slab(s + 1, next);
+#pragma unroll
+    for (int g16 = 0; g16 < BK / 16; ++g16) {
+      const int c = g16 * 2 + lh;  // lane half h supplies k = 16 g16 + 8 h + 0..7
+      u16x8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int o = a_frag(wm + 32 * i + lr, c);
+        ah[i] = *reinterpret_cast<const u16x8*>(cur + o);
+        al[i] = *reinterpret_cast<const u16x8*>(cur + kPackHalfBytes + o);
+      }
+#pragma unroll
+      for (int j = 0; j < FN; ++j) {
+        const int o = b_frag(wn + 32 * j + lr, c);
+        bh[j] = *reinterpret_cast<const u16x8*>(cur + o);
+        bl[j] = *reinterpret_cast<const u16x8*>(cur + kPackHalfBytes + o);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          acc[i][j] = mfma16<FMT>(al[i], bh[j], acc[i][j]);
+          acc[i][j] = mfma16<FMT>(ah[i], bl[j], acc[i][j]);
+          acc[i][j] = mfma16<FMT>(ah[i], bh[j], acc[i][j]);
+        }
+    }
+    if (more) __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the next slab is in LDS
+    __syncthreads();
+  };
+
+  if (slabs > 0) {
+    load_slab(0, lds0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+  }
+  for (int s = 0; s < slabs; s += 2) {
+    step(lds0, lds1, s);
+    if (s + 1 < slabs) step(lds1, lds0, s + 1);
+  }
+
+  // Epilogue: register r of block (i, j) holds row 8*(r/4) + 4*(lane/32) + r%4
+  // and column lane%32 of that 32x32 block.
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int col = tn + wn + 32 * j + lr;
+      if (col >= c_cols) continue;
+      int ec = 0;
+      if constexpr (kScaled) ec = col < b_cols ? d.eb[col] : 0;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = tm + wm + 32 * i + 8 * (r >> 2) + 4 * lh + (r & 3);
+        if (row < c_rows) {
+          float v = acc[i][j][r];
+          if constexpr (kScaled) v = __builtin_ldexpf(v, ec + (row < a_rows ? d.ea[row] : 0));
+          float* cp = C + (int64_t)row * ldc + col;
+          *cp = beta ? *cp + v : v;
+        }
+      }
+    }
+}
+
 void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
                         hipStream_t stream, int xcd_chunk) {
   if (total_tiles <= 0) return;
@@ -380,32 +672,77 @@ void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, boo
   FASTMM_HIP(hipGetLastError());
 }
 
-int leaf_scale_blocks(int a_rows, int b_cols) {
-  return (a_rows + kScaleRowsPerBlock - 1) / kScaleRowsPerBlock +
-         (b_cols + kScaleColsPerBlock - 1) / kScaleColsPerBlock;
+int64_t leaf_packed_bytes(int64_t rows, int64_t cols, int64_t k) {
+  const int64_t slabs = (k + kPackK - 1) / kPackK;
+  return ((rows + kPackRows - 1) / kPackRows + (cols + kPackRows - 1) / kPackRows) * slabs *
+         kPackBlockBytes;
 }
 
-void launch_leaf_fp16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
-                        hipStream_t stream, int xcd_chunk, int max_a_rows, int max_b_cols) {
+int64_t leaf_scale_bytes(int64_t rows, int64_t cols, int64_t k) {
+  return 4 * (rows + cols + (k + kScaleRowsPerPart - 1) / kScaleRowsPerPart * cols);
+}
+
+int64_t leaf_packed_a_bytes(int64_t rows, int64_t k) {
+  return (rows + kPackRows - 1) / kPackRows * ((k + kPackK - 1) / kPackK) * kPackBlockBytes;
+}
+
+void launch_leaf_packed(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
+                        hipStream_t stream, int xcd_chunk, const LeafExtents& ext) {
   if (total_tiles <= 0) return;
-  const int a_blocks = (max_a_rows + kScaleRowsPerBlock - 1) / kScaleRowsPerBlock;
-  const int per_desc = leaf_scale_blocks(max_a_rows, max_b_cols);
-  if ((int64_t)per_desc * ndesc > INT32_MAX) throw Error(kNotSupported, "scale launch too large");
+  const bool fp16 = tile == kTileFp16x3;
+  if (!fp16 && tile != kTileBf16x3) throw Error(kInvalidValue, "not a split-precision tile");
+  // 1. FP16 only: scale exponents of the valid rows of A and columns of B.
+  if (fp16) {
+    const int a_blocks = (ext.max_a_rows + kScaleRowsPerBlock - 1) / kScaleRowsPerBlock;
+    const int64_t parts = (ext.max_kmax + kScaleRowsPerPart - 1) / kScaleRowsPerPart;
+    const int64_t col_blocks = (ext.max_b_cols + kScaleColsPerBlock - 1) / kScaleColsPerBlock;
+    const int64_t per_desc = a_blocks + col_blocks * parts;
+    if (per_desc * ndesc > INT32_MAX || col_blocks * ndesc > INT32_MAX)
+      throw Error(kNotSupported, "scale launch too large");
+    if (per_desc > 0) {
+      dim3 grid((unsigned)(per_desc * ndesc)), block(256);
+      if (vec)
+        hipLaunchKernelGGL((leaf_scale_kernel<true>), grid, block, 0, stream, d_descs, a_blocks, (int)per_desc);
+      else
+        hipLaunchKernelGGL((leaf_scale_kernel<false>), grid, block, 0, stream, d_descs, a_blocks, (int)per_desc);
+      FASTMM_HIP(hipGetLastError());
+    }
+    if (col_blocks > 0) {
+      dim3 grid((unsigned)(col_blocks * ndesc)), block(256);
+      hipLaunchKernelGGL(leaf_scale_b_kernel, grid, block, 0, stream, d_descs, (int)col_blocks);
+      FASTMM_HIP(hipGetLastError());
+    }
+  }
+  // 2. Pack both operands of every leaf.
+  const int64_t groups = (ext.max_slabs + kPackSlabsPerGroup - 1) / kPackSlabsPerGroup;
+  const int64_t a_units = (int64_t)((ext.max_c_rows + kPackRows - 1) / kPackRows) * groups;
+  const int64_t b_units = (int64_t)((ext.max_c_cols + kPackRows - 1) / kPackRows) * groups;
+  const int64_t per_desc = a_units + b_units;
+  if (per_desc * ndesc > INT32_MAX) throw Error(kNotSupported, "pack launch too large");
   if (per_desc > 0) {
-    dim3 sgrid(per_desc * ndesc), sblock(256);
-    if (vec)
-      hipLaunchKernelGGL((leaf_scale_kernel<true>), sgrid, sblock, 0, stream, d_descs, a_blocks, per_desc);
-    else
-      hipLaunchKernelGGL((leaf_scale_kernel<false>), sgrid, sblock, 0, stream, d_descs, a_blocks, per_desc);
+    dim3 grid((unsigned)(per_desc * ndesc)), block(256);
+    if (fp16) {
+      if (vec)
+        hipLaunchKernelGGL((leaf_pack_kernel<kSplitFp16, true>), grid, block, 0, stream, d_descs, (int)a_units, (int)per_desc);
+      else
+        hipLaunchKernelGGL((leaf_pack_kernel<kSplitFp16, false>), grid, block, 0, stream, d_descs, (int)a_units, (int)per_desc);
+    } else {
+      if (vec)
+        hipLaunchKernelGGL((leaf_pack_kernel<kSplitBf16, true>), grid, block, 0, stream, d_descs, (int)a_units, (int)per_desc);
+      else
+        hipLaunchKernelGGL((leaf_pack_kernel<kSplitBf16, false>), grid, block, 0, stream, d_descs, (int)a_units, (int)per_desc);
+    }
     FASTMM_HIP(hipGetLastError());
   }
-  dim3 grid(total_tiles), block(256);
-  if (vec)
-    hipLaunchKernelGGL((leaf_split_kernel<kSplitFp16, true>), grid, block, 0, stream, d_descs, ndesc,
-                       total_tiles, xcd_chunk);
+  // 3. The leaf itself.
+  constexpr int TM = kSplitTileM, TN = kSplitTileN, WGM = kSplitWavesM, WGN = kSplitWavesN;
+  dim3 grid(total_tiles), block(64 * WGM * WGN);
+  if (fp16)
+    hipLaunchKernelGGL((leaf_packed_kernel<kSplitFp16, TM, TN, WGM, WGN>), grid, block, 0, stream, d_descs,
+                       ndesc, total_tiles, xcd_chunk);
   else
-    hipLaunchKernelGGL((leaf_split_kernel<kSplitFp16, false>), grid, block, 0, stream, d_descs, ndesc,
-                       total_tiles, xcd_chunk);
+    hipLaunchKernelGGL((leaf_packed_kernel<kSplitBf16, TM, TN, WGM, WGN>), grid, block, 0, stream, d_descs,
+                       ndesc, total_tiles, xcd_chunk);
   FASTMM_HIP(hipGetLastError());
 }
 

@@ -60,7 +60,9 @@ void rmul_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
   split_spans(0, K, d, ks);
   split_spans(0, N, d, cs);
   const int nb = 1 << d;
-  const TileShape ts = tile_shape(tile);
+  // Split-BF16 leaves run here on the register-split kernel (128x128 tiles,
+  // no packed operands).
+  const TileShape ts = tile == kTileBf16x3 ? TileShape{128, 128} : tile_shape(tile);
 
   const size_t a_bytes = on_dev ? 0 : align_up((size_t)M * K * 4, 256);
   const size_t b_bytes = on_dev ? 0 : align_up((size_t)K * N * 4, 256);
