@@ -24,6 +24,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "effective GFLOPS (2MNK/wall-clock) n=19456 FP32 Winograd vs plain MFMA SGEMM"
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix peak
+PEAK_16BIT_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 matrix peak
+# --tile 8 / 9 time a split-precision form instead of the FP32 leaf: three
+# 16-bit products per FP32 product, so its FP32-equivalent ceiling is a third
+# of the 16-bit peak; its leaf phase is a pack pass (and for FP16 a scale
+# pass) plus the leaf kernel.
+SPLIT_FORMS = {8: ("bf16x3", "leaf_pack_kernel<0> + leaf_packed_kernel<0,256,256,4,2>"),
+               9: ("fp16x3", "leaf_scale_kernel + leaf_pack_kernel<1> + leaf_packed_kernel<1,256,256,4,2>")}
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per leaf launch (HBM-resident depth-3 call: one grouped launch of
 # 343 leaves of 2432 x 2432 x 2432) from the FETCH_SIZE and WRITE_SIZE counter
@@ -224,9 +231,11 @@ def main():
     leaf_tflops = flops_launch / (avg_launch * 1e-3) / 1e12
     traffic_ok = (TRAFFIC_BYTES_PER_LAUNCH is not None and not args.pinned_headline and best == 3
                   and n == 19456 and args.tile == 0 and args.leaf == 1024)
-    roofline = {"bound": "mfma", "kernel": "leaf_gemm_kernel<128,128,16,2,2> (grouped leaves)",
-                "achieved": leaf_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": leaf_tflops / PEAK_FP32_TFLOPS,
+    split = SPLIT_FORMS.get(args.tile)
+    peak = PEAK_16BIT_TFLOPS / 3 if split else PEAK_FP32_TFLOPS
+    roofline = {"bound": "mfma",
+                "kernel": split[1] if split else "leaf_gemm_kernel<128,128,16,2,2> (grouped leaves)",
+                "achieved": leaf_tflops, "peak": peak, "unit": "TFLOP/s", "frac": leaf_tflops / peak,
                 "traffic": TRAFFIC_BYTES_PER_LAUNCH if traffic_ok else None,
                 "flops_per_launch": flops_launch, "avg_launch_ms": avg_launch,
                 "launches_per_step": n_launch}
@@ -251,6 +260,28 @@ def main():
         classic = {"ms": 1e3 * t, "effective_GFLOPS": flops / t / 1e9,
                    "depth": fastmm.get_stats()["depth"], "leaf": 3008}
         log(f"bench: classic recursion {classic}")
+
+    # Context: the split-precision leaf forms (never the FP32 headline): split
+    # BF16 (tile 8) and scaled split FP16 (tile 9) leaves, plain and at the
+    # headline depth, same operands in HBM; sampled-row error against the
+    # oracle.  Leaf times include the forms' pack (and FP16 scale) passes.
+    precision = None
+    if not args.no_device_context and not args.pinned_headline:
+        precision = {}
+        rows_p = synthgen.row_sample(7008, M, 4)
+        for name, tile in (("bf16x3", 8), ("fp16x3", 9)):
+            for d in sorted({0, best}):
+                fn = lambda: fastmm.gemm(M, N, K, A, B, C, depth=d, leaf=args.leaf, tile=tile)
+                tot, ts = time_calls(fn, 3, 1)
+                sp = fastmm.get_stats()
+                Cp = C.cpu().numpy()
+                precision[f"{name}_depth{sp['depth']}"] = {
+                    "ms": 1e3 * min(ts), "effective_GFLOPS": flops / min(ts) / 1e9,
+                    "leaf_ms": sp["leaf_ms"],
+                    "leaf_TFLOPs_fp32_equivalent": sp["leaf_flops"] / (sp["leaf_ms"] * 1e-3) / 1e12,
+                    "sampled_rows_rel": checks.sampled_rows_rel(Cp, An, Bn, rows_p)}
+                del Cp
+        log(f"bench: precision forms {precision}")
 
     # Context: the same products with operands in pinned host memory, the
     # transfers inside the wall-clock (pipelined host path).
@@ -316,9 +347,10 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "GFLOPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": split[0] if split else "f32",
         "data": "synthetic",
         "config": {"workload": f"FP32 Winograd-Strassen C=A*B, square n={n}, {where}, "
+                               + (f"{split[0]} leaves, " if split else "") +
                                f"depth {st['depth']}, leaf {args.leaf}",
                    "M": M, "N": N, "K": K, "depth": st["depth"], "leaf": args.leaf,
                    "tile": args.tile, "parallelism": "single GPU"},
@@ -326,7 +358,8 @@ def main():
         "plain_sgemm": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms_per_step) if plain else None,
         "depth_probe_ms": {str(k): 1e3 * v for k, v in probe.items()},
-        "phases": phases, "classic_recursion": classic, "pinned_host": pinned,
+        "phases": phases, "classic_recursion": classic, "precision_forms": precision,
+        "pinned_host": pinned,
         "batched": batched, "shards": shards, "parity": parity,
     }
     print(json.dumps(out), flush=True)

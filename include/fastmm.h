@@ -70,22 +70,24 @@ enum {
   FASTMM_TILE_256x128_W8 = 5,  /* 256x128 on 8 wavefronts */
   FASTMM_TILE_256x256_W8 = 6,  /* 256x256 on 8 wavefronts */
   FASTMM_TILE_128x256 = 7,
-  /* Precision form of the leaf, never chosen by the planner: 128x128 tiles in
-   * split-BF16 arithmetic (each FP32 operand as hi + lo BF16, products
-   * hi*hi + hi*lo + lo*hi accumulated in FP32 on the BF16 matrix cores):
-   * about 2^-16 relative accuracy per product instead of FP32's 2^-24.  The
-   * quadrant additions stay FP32. */
-  FASTMM_TILE_BF16X3_128x128 = 8,
-  /* Precision form of the leaf, never chosen by the planner: 128x128 tiles in
-   * scaled split-FP16 arithmetic.  Each row of a leaf's left operand and each
-   * column of its right operand is scaled by a power of two that brings its
-   * largest magnitude into [2^14, 2^15) (a pass over the operands before the
-   * leaf launch, exponents kept in the workspace), every scaled element is
-   * split into hi + lo FP16, the products hi*hi + hi*lo + lo*hi are
-   * accumulated in FP32 on the FP16 matrix cores and the scales are undone
-   * on the result: about 2^-21 relative accuracy per product.  Not offered
-   * by fastmm_rmul (FASTMM_ERROR_NOT_SUPPORTED). */
-  FASTMM_TILE_FP16X3_128x128 = 9
+  /* Precision forms of the leaf, never chosen by the planner.  Each FP32
+   * operand element becomes hi + lo in 16 bits and every product is taken as
+   * hi*hi + hi*lo + lo*hi, accumulated in FP32 on the 16-bit matrix cores;
+   * the quadrant additions stay FP32.  fastmm_gemm_ex (device or host
+   * operands) first packs both operands of every leaf as hi/lo tiles
+   * (workspace about the size of the FP32 leaf operands) and runs 256x256
+   * tiles on them; fastmm_rmul runs BF16X3 on 128x128 tiles that
+   * split in registers and rejects FP16X3 (FASTMM_ERROR_NOT_SUPPORTED).
+   * BF16X3: split BF16, about 2^-16 relative accuracy per product instead of
+   * FP32's 2^-24.
+   * FP16X3: scaled split FP16.  Each row of a leaf's left operand and each
+   * column of its right operand is scaled by the power of two that brings
+   * its largest magnitude into [2^14, 2^15) (a pass over the operands before
+   * the leaf, exponents kept in the workspace), split into hi + lo FP16, and
+   * the scales are undone on the result: about 2^-21 relative accuracy per
+   * product. */
+  FASTMM_TILE_BF16X3 = 8,
+  FASTMM_TILE_FP16X3 = 9
 };
 
 typedef struct {

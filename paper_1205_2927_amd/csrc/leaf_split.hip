@@ -29,12 +29,16 @@
 //   extra 2^11 factor on lo, and the second accumulator it needs, buy
 //   nothing here, and one FP32 accumulator holds all three terms.
 //
-// Tiling mirrors the FP32 leaf kernel (128x128 macro tile, 4 wavefronts of
-// 64x64, grouped launch with the same descriptors and XCD-aware walk) with
-// K-slabs of 32: global FP32 loads (branch-free buffer loads, zero outside
-// the valid extent) are split in registers and stored to LDS as hi and lo
-// arrays with k contiguous ([m][k] for A, [n][k] for B), so one 16-byte LDS
-// read gives the 8 consecutive k a lane supplies to a 32x32x16 step.
+// Two kernels run these forms.  The level-wise engine packs every leaf's
+// operands once (leaf_pack_kernel) and runs leaf_packed_kernel, 256x256 tiles
+// that copy pre-split slabs straight into LDS.  The classic recursion, which
+// has no workspace for packed operands, runs split BF16 on
+// leaf_split_kernel: 128x128 tiles (4 wavefronts of 64x64, the FP32 leaf's
+// descriptors and XCD-aware walk) with K-slabs of 32 whose FP32 loads
+// (branch-free buffer loads, zero outside the valid extent) are split in
+// registers and stored to LDS as hi and lo arrays with k contiguous ([m][k]
+// for A, [n][k] for B).  In both, one 16-byte LDS read gives the 8
+// consecutive k a lane supplies to a 32x32x16 step.
 #include <hip/hip_runtime.h>
 
 #include "common.h"

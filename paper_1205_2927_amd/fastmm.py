@@ -25,12 +25,12 @@ AUTO = -1
 PLAN_DEFAULT, PLAN_MODEL, PLAN_EXHAUSTIVE = 0, 1, 2
 TILE_128x128, TILE_256x128, TILE_128x64, TILE_64x64 = 0, 1, 2, 3
 TILE_128x128_K32, TILE_256x128_W8, TILE_256x256_W8, TILE_128x256 = 4, 5, 6, 7
-TILE_BF16X3_128x128 = 8  # split-BF16 precision form of the leaf
-TILE_FP16X3_128x128 = 9  # scaled split-FP16 precision form of the leaf
+TILE_BF16X3 = 8  # split-BF16 precision form of the leaf (256x256 tiles on packed operands)
+TILE_FP16X3 = 9  # scaled split-FP16 precision form of the leaf (256x256 tiles on packed operands)
 TILES = {TILE_128x128: (128, 128), TILE_256x128: (256, 128), TILE_128x64: (128, 64),
          TILE_64x64: (64, 64), TILE_128x128_K32: (128, 128), TILE_256x128_W8: (256, 128),
-         TILE_256x256_W8: (256, 256), TILE_128x256: (128, 256), TILE_BF16X3_128x128: (128, 128),
-         TILE_FP16X3_128x128: (128, 128)}
+         TILE_256x256_W8: (256, 256), TILE_128x256: (128, 256), TILE_BF16X3: (256, 256),
+         TILE_FP16X3: (256, 256)}
 MLP_PARAMS = 4609
 
 # Every symbol include/fastmm.h declares.

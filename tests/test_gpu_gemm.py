@@ -172,7 +172,7 @@ def test_invalid_arguments_leave_c_untouched(fastmm):
         assert rc == fastmm.ERROR_INVALID_VALUE, args
         assert fastmm.last_error() != ""
         assert torch.all(C == 5.0).item()
-    assert fastmm.gemm_raw(8, 8, 8, a, 8, b, 8, c, 8, 0, 1, 9) == fastmm.ERROR_INVALID_VALUE
+    assert fastmm.gemm_raw(8, 8, 8, a, 8, b, 8, c, 8, 0, 1, 10) == fastmm.ERROR_INVALID_VALUE  # no tile 10
 
 
 def test_mixed_residency_not_supported(fastmm):

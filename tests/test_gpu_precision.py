@@ -17,8 +17,8 @@ from oracle import winograd as W
 from tests.gpu_util import dev, empty_dev, host, ints, say, uniform
 
 pytestmark = pytest.mark.gpu
-BF = 8  # FASTMM_TILE_BF16X3_128x128
-FP = 9  # FASTMM_TILE_FP16X3_128x128
+BF = 8  # FASTMM_TILE_BF16X3
+FP = 9  # FASTMM_TILE_FP16X3
 
 
 @pytest.mark.parametrize("tile", [BF, FP])

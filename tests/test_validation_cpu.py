@@ -45,7 +45,7 @@ def test_rmul_rejects():
     assert lib.fastmm_rmul(4, 4, 4, A, 4, B, 4, C, 4, -1, 1, 0) == INV
     assert lib.fastmm_rmul(4, 4, 4, A, 4, B, 4, C, 4, 1, 1, 99) == INV
     # the scaled FP16 leaf needs per-leaf scale storage the classic path lacks
-    assert lib.fastmm_rmul(4, 4, 4, A, 4, B, 4, C, 4, 1, 1, fastmm.TILE_FP16X3_128x128) == NSUP
+    assert lib.fastmm_rmul(4, 4, 4, A, 4, B, 4, C, 4, 1, 1, fastmm.TILE_FP16X3) == NSUP
     assert lib.fastmm_rmul(4, 4, 4, A, 2, B, 4, C, 4, 1, 1, 0) == INV
 
 
