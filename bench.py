@@ -103,6 +103,29 @@ def batched_context(fastmm, torch):
             "single_calls_ms": 1e3 * t_s, "single_calls_TFLOPS": flops / t_s / 1e12}
 
 
+def sweep(fastmm, torch, sizes):
+    """Dense n-sweep, device-resident, one JSON line per n: the plain MFMA
+    SGEMM, Winograd at the planner's default depth, and the paper's classic
+    eight-product recursion with its stop rule (recurse while the half is at
+    least 3008), the comparison behind the paper's saw-tooth curve of the
+    classic recursion (Section 4)."""
+    for n in sizes:
+        A = torch.empty((n, n), device="cuda").uniform_(-1, 1)
+        B = torch.empty((n, n), device="cuda").uniform_(-1, 1)
+        C = torch.empty((n, n), device="cuda")
+        flops = 2.0 * n ** 3
+        row = {"sweep_n": n}
+        for name, fn in (("plain", lambda: fastmm.gemm(n, n, n, A, B, C, depth=0)),
+                         ("winograd", lambda: fastmm.gemm(n, n, n, A, B, C, depth=-1)),
+                         ("classic", lambda: fastmm.rmul(n, n, n, A, B, C, depth=16, leaf=3008))):
+            tot, ts = time_calls(fn, 3, 1)
+            row[name + "_ms"] = 1e3 * min(ts)
+            row[name + "_GFLOPS"] = flops / min(ts) / 1e9
+            row[name + "_depth"] = fastmm.get_stats()["depth"]
+        print(json.dumps(row), flush=True)
+        del A, B, C
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +150,9 @@ def main():
                     help="time the pinned-host path in the main loop (profiling that path)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (calibrates HBM counters)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the headline: n-sweep of plain, Winograd and the classic "
+                         "recursion, one JSON line per n")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the sharded "
@@ -140,6 +166,10 @@ def main():
     from paper_1205_2927_amd import fastmm
 
     fastmm.load()
+    if args.sweep:
+        sizes = sorted(set(range(2048, 19457, 512)) | {6015, 6016, 12031, 12032})
+        sweep(fastmm, torch, sizes)
+        return
     if args.traffic_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
