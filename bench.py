@@ -167,7 +167,7 @@ def main():
 
     fastmm.load()
     if args.sweep:
-        sizes = sorted(set(range(2048, 19457, 512)) | {6015, 6016, 12031, 12032})
+        sizes = sorted(set(range(2048, 19457, 512)) | {6004, 6015, 6016, 10004, 12031, 12032, 14004})
         sweep(fastmm, torch, sizes)
         return
     if args.traffic_probe:

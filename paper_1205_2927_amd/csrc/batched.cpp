@@ -124,6 +124,7 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
 
   std::vector<Problem> probs;
   std::vector<int> idx;
+  std::vector<Staging> stg;
   size_t stage_bytes = 0, temp_bytes = 0;
   std::vector<size_t> a_off, b_off, c_off;
   for (int i = 0; i < count; ++i) {
@@ -145,14 +146,19 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
     }
     p.depth = p.K == 0 ? 0 : effective_depth(p.M, p.N, p.K, dep, lf);
     p.tile = tile;
-    if (!on_dev) {
-      a_off.push_back(stage_bytes);
-      stage_bytes += align_up((size_t)p.M * p.K * 4, 256);
-      b_off.push_back(stage_bytes);
-      stage_bytes += align_up((size_t)p.K * p.N * 4, 256);
-      c_off.push_back(stage_bytes);
-      stage_bytes += align_up((size_t)p.M * p.N * 4, 256);
-    }
+    // The same staging as a single call (so each result equals it bit for
+    // bit): host operands, and device operands the 16-byte path cannot read.
+    const Staging g = plan_staging(M[i], N[i], K[i], A[i], lda[i], B[i], ldb[i], on_dev == 1);
+    p.K = g.K4;
+    p.N = g.N4;
+    p.c_cols = N[i];
+    a_off.push_back(stage_bytes);
+    stage_bytes += g.a_bytes;
+    b_off.push_back(stage_bytes);
+    stage_bytes += g.b_bytes;
+    c_off.push_back(stage_bytes);
+    if (!on_dev) stage_bytes += align_up((size_t)M[i] * N[i] * 4, 256);
+    stg.push_back(g);
     temp_bytes += align_up(problem_temp_bytes(p), 256);
     probs.push_back(p);
     idx.push_back(i);
@@ -178,30 +184,22 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
   for (size_t j = 0; j < probs.size(); ++j) {
     Problem& p = probs[j];
     const int i = idx[j];
+    const Staging& g = stg[j];
+    float* dA = g.a ? reinterpret_cast<float*>(ws + a_off[j]) : const_cast<float*>(A[i]);
+    float* dB = g.b ? reinterpret_cast<float*>(ws + b_off[j]) : const_cast<float*>(B[i]);
+    p.A = dA;
+    p.B = dB;
+    p.lda = g.a ? std::max<int64_t>(g.K4, 1) : lda[i];
+    p.ldb = g.b ? g.N4 : ldb[i];
     if (on_dev) {
-      p.A = A[i];
-      p.B = B[i];
       p.C = C[i];
-      p.lda = lda[i];
-      p.ldb = ldb[i];
       p.ldc = ldc[i];
     } else {
-      float* dA = reinterpret_cast<float*>(ws + a_off[j]);
-      float* dB = reinterpret_cast<float*>(ws + b_off[j]);
-      p.A = dA;
-      p.B = dB;
       p.C = reinterpret_cast<float*>(ws + c_off[j]);
-      p.lda = std::max<int64_t>(p.K, 1);
-      p.ldb = p.N;
-      p.ldc = p.N;
-      if (p.K > 0) {
-        FASTMM_HIP(hipMemcpy2DAsync(dA, p.K * 4, A[i], lda[i] * 4, p.K * 4, p.M,
-                                    hipMemcpyHostToDevice, sm));
-        FASTMM_HIP(hipMemcpy2DAsync(dB, p.N * 4, B[i], ldb[i] * 4, p.N * 4, p.K,
-                                    hipMemcpyHostToDevice, sm));
-      }
+      p.ldc = N[i];
     }
-    if (p.K == 0) FASTMM_HIP(hipMemset2DAsync(p.C, p.ldc * 4, 0, p.N * 4, p.M, sm));
+    stage_operands(g, M[i], N[i], K[i], A[i], lda[i], B[i], ldb[i], dA, dB, sm);
+    if (p.K == 0) FASTMM_HIP(hipMemset2DAsync(p.C, p.ldc * 4, 0, N[i] * 4, p.M, sm));
   }
   // Problems with K == 0 are done; the rest go through the schedule.
   std::vector<Problem> work;
@@ -229,7 +227,7 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
     for (size_t j = 0; j < probs.size(); ++j) {
       const Problem& p = probs[j];
       const int i = idx[j];
-      FASTMM_HIP(hipMemcpy2DAsync(C[i], ldc[i] * 4, p.C, p.N * 4, p.N * 4, p.M,
+      FASTMM_HIP(hipMemcpy2DAsync(C[i], ldc[i] * 4, p.C, N[i] * 4, N[i] * 4, p.M,
                                   hipMemcpyDeviceToHost, sm));
     }
   }

@@ -156,9 +156,9 @@ int effective_depth(int64_t M, int64_t N, int64_t K, int depth, int64_t leaf) {
   int d = 0;
   int64_t m = M, k = K, n = N;
   while (splits(m, k, n, depth - d, leaf)) {
-    m = half_up(m);
-    k = half_up(k);
-    n = half_up(n);
+    m = split_half(m);
+    k = split_half(k);
+    n = split_half(n);
     ++d;
   }
   return d;
@@ -170,7 +170,7 @@ std::vector<Dims> level_dims(const Problem& p) {
   std::vector<Dims> dims{{p.M, p.K, p.N}};
   for (int l = 0; l < p.depth; ++l) {
     const Dims& d = dims.back();
-    dims.push_back({half_up(d.m), half_up(d.k), half_up(d.n)});
+    dims.push_back({split_half(d.m), split_half(d.k), split_half(d.n)});
   }
   return dims;
 }
@@ -599,14 +599,14 @@ size_t bfs_need(const Problem& p) {
 }
 
 size_t top_need(const Problem& p) {
-  const int64_t m2 = half_up(p.M), k2 = half_up(p.K), n2 = half_up(p.N);
+  const int64_t m2 = split_half(p.M), k2 = split_half(p.K), n2 = split_half(p.N);
   return align_up((size_t)4 * m2 * k2 * 4, 256) + align_up((size_t)4 * k2 * n2 * 4, 256) +
          align_up((size_t)7 * m2 * n2 * 4, 256) + 3 * 256;
 }
 
 // Sub-product i (P1..P7 = 0..6) of p, with p's S, T and P blocks at S, T, P.
 Problem child_problem(const Problem& p, int i, float* S, float* T, float* P) {
-  const int64_t m2 = half_up(p.M), k2 = half_up(p.K), n2 = half_up(p.N);
+  const int64_t m2 = split_half(p.M), k2 = split_half(p.K), n2 = split_half(p.N);
   const View a{p.A, p.lda, p.ar(), p.ac()}, b{p.B, p.ldb, p.br(), p.bc()};
   auto sv = [&](int j) { return View{S + j * m2 * k2, k2, m2, k2}; };
   auto tv = [&](int j) { return View{T + j * k2 * n2, n2, k2, n2}; };
@@ -668,7 +668,7 @@ void run_within(Library& L, const Problem& p, char* ws, size_t bytes, RunTotals&
   }
   if (p.depth == 0 || top_need(p) >= bytes)
     throw Error(kOutOfMemory, "workspace budget too small even for depth-first execution");
-  const int64_t m2 = half_up(p.M), k2 = half_up(p.K), n2 = half_up(p.N);
+  const int64_t m2 = split_half(p.M), k2 = split_half(p.K), n2 = split_half(p.N);
   size_t off = 0;
   auto take = [&](size_t b) {
     char* q = ws + off;
@@ -716,6 +716,33 @@ size_t workspace_budget(Library& L) {
 
 }  // namespace
 
+Staging plan_staging(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                     int64_t ldb, bool on_dev) {
+  Staging g;
+  g.K4 = (K + 3) / 4 * 4;
+  g.N4 = (N + 3) / 4 * 4;
+  g.a = !on_dev || !(aligned16(A) && lda % 4 == 0 && K % 4 == 0);
+  g.b = !on_dev || !(aligned16(B) && ldb % 4 == 0 && N % 4 == 0 && K % 4 == 0);
+  g.a_bytes = (g.a && K > 0) ? align_up((size_t)M * g.K4 * 4, 256) : 0;
+  g.b_bytes = (g.b && K > 0) ? align_up((size_t)g.K4 * g.N4 * 4, 256) : 0;
+  return g;
+}
+
+void stage_operands(const Staging& g, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                    const float* B, int64_t ldb, float* dA, float* dB, hipStream_t sm) {
+  if (K == 0) return;
+  const int64_t K4 = g.K4, N4 = g.N4;
+  if (g.a) {
+    if (K4 > K) FASTMM_HIP(hipMemset2DAsync(dA + K, K4 * 4, 0, (K4 - K) * 4, M, sm));
+    FASTMM_HIP(hipMemcpy2DAsync(dA, K4 * 4, A, lda * 4, K * 4, M, hipMemcpyDefault, sm));
+  }
+  if (g.b) {
+    if (N4 > N) FASTMM_HIP(hipMemset2DAsync(dB + N, N4 * 4, 0, (N4 - N) * 4, K, sm));
+    if (K4 > K) FASTMM_HIP(hipMemsetAsync(dB + K * N4, 0, (K4 - K) * N4 * 4, sm));
+    FASTMM_HIP(hipMemcpy2DAsync(dB, N4 * 4, B, ldb * 4, N * 4, K, hipMemcpyDefault, sm));
+  }
+}
+
 void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
                int tile) {
@@ -760,11 +787,24 @@ void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
     return;
   }
 
+  // Staging (plan_staging): host operands, and device operands the leaf's
+  // 16-byte load path cannot read, go to padded buffers in the workspace;
+  // the product then runs on the padded extents and C keeps N columns.
+  const Staging sg = plan_staging(M, N, K, A, lda, B, ldb, on_dev);
+  const bool stage_a = sg.a, stage_b = sg.b;
+  const int64_t lda_s = stage_a ? sg.K4 : lda, ldb_s = stage_b ? sg.N4 : ldb;
+  p.K = sg.K4;  // K4 > K only when both operands are staged
+  p.N = sg.N4;  // N4 > N only when B is staged
+  p.c_cols = N;
+
   // Workspace: [staged A | staged B | staged C | temporaries | descriptors].
-  const size_t a_bytes = on_dev ? 0 : align_up((size_t)M * K * 4, 256);
-  const size_t b_bytes = on_dev ? 0 : align_up((size_t)K * N * 4, 256);
+  const size_t a_bytes = sg.a_bytes;
+  const size_t b_bytes = sg.b_bytes;
   const size_t c_bytes = on_dev ? 0 : align_up((size_t)M * N * 4, 256);
   const size_t t_bytes = align_up(problem_temp_bytes(p), 256);
+  auto stage_in = [&](float* dA, float* dB, hipStream_t sm) {
+    stage_operands(sg, M, N, K, A, lda, B, ldb, dA, dB, sm);
+  };
 
   // Over budget: depth-first execution of the top levels.
   if (K > 0 && p.depth > 0) {
@@ -777,18 +817,15 @@ void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
                                       " bytes (depth-first) exceeds the budget of " +
                                       std::to_string(budget) + " (FASTMM_WORKSPACE_LIMIT or free memory)");
       char* ws = ensure_arena(L, budget);
-      float* dA = on_dev ? const_cast<float*>(A) : reinterpret_cast<float*>(ws);
-      float* dB = on_dev ? const_cast<float*>(B) : reinterpret_cast<float*>(ws + a_bytes);
+      float* dA = stage_a ? reinterpret_cast<float*>(ws) : const_cast<float*>(A);
+      float* dB = stage_b ? reinterpret_cast<float*>(ws + a_bytes) : const_cast<float*>(B);
       float* dC = on_dev ? C : reinterpret_cast<float*>(ws + a_bytes + b_bytes);
-      if (!on_dev) {
-        FASTMM_HIP(hipMemcpy2DAsync(dA, K * 4, A, lda * 4, K * 4, M, hipMemcpyHostToDevice, L.stream));
-        FASTMM_HIP(hipMemcpy2DAsync(dB, N * 4, B, ldb * 4, N * 4, K, hipMemcpyHostToDevice, L.stream));
-      }
+      stage_in(dA, dB, L.stream);
       p.A = dA;
       p.B = dB;
       p.C = dC;
-      p.lda = on_dev ? lda : K;
-      p.ldb = on_dev ? ldb : N;
+      p.lda = lda_s;
+      p.ldb = ldb_s;
       p.ldc = on_dev ? ldc : N;
       RunTotals rt;
       run_within(L, p, ws + stage, budget - stage, rt);
@@ -819,8 +856,8 @@ void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
     q.A = reinterpret_cast<const float*>(256);
     q.B = q.A;
     q.C = const_cast<float*>(q.A);
-    q.lda = on_dev ? lda : K;
-    q.ldb = on_dev ? ldb : N;
+    q.lda = lda_s;
+    q.ldb = ldb_s;
     q.ldc = on_dev ? ldc : N;
     build_schedule({q}, reinterpret_cast<char*>(256), s);
   }
@@ -828,27 +865,23 @@ void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
   char* ws = ensure_arena(L, a_bytes + b_bytes + c_bytes + t_bytes + d_bytes);
   char* desc_host = ensure_pinned(L, d_bytes);
 
-  float* dA = on_dev ? const_cast<float*>(A) : reinterpret_cast<float*>(ws);
-  float* dB = on_dev ? const_cast<float*>(B) : reinterpret_cast<float*>(ws + a_bytes);
+  float* dA = stage_a ? reinterpret_cast<float*>(ws) : const_cast<float*>(A);
+  float* dB = stage_b ? reinterpret_cast<float*>(ws + a_bytes) : const_cast<float*>(B);
   float* dC = on_dev ? C : reinterpret_cast<float*>(ws + a_bytes + b_bytes);
   p.A = dA;
   p.B = dB;
   p.C = dC;
-  p.lda = on_dev ? lda : K;
-  p.ldb = on_dev ? ldb : N;
+  p.lda = lda_s;
+  p.ldb = ldb_s;
   p.ldc = on_dev ? ldc : N;
   char* temps = ws + a_bytes + b_bytes + c_bytes;
   char* desc_dev = temps + t_bytes;
 
   hipStream_t sm = L.stream;
   if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[0], sm));
-  if (!on_dev) {
-    // Step (1) of the paper's leaf call: operands to the device.
-    if (K > 0) {
-      FASTMM_HIP(hipMemcpy2DAsync(dA, K * 4, A, lda * 4, K * 4, M, hipMemcpyHostToDevice, sm));
-      FASTMM_HIP(hipMemcpy2DAsync(dB, N * 4, B, ldb * 4, N * 4, K, hipMemcpyHostToDevice, sm));
-    }
-  }
+  // Step (1) of the paper's leaf call (operands to the device), or the
+  // alignment staging of device operands.
+  stage_in(dA, dB, sm);
   if (L.profiling) FASTMM_HIP(hipEventRecord(L.ev[5], sm));
   int launches = 0;
   if (K == 0) {

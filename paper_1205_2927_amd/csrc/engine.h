@@ -21,6 +21,16 @@ struct Dims {
 // Half extent of equation (1): quadrant 0 takes ceil(m/2).
 inline int64_t half_up(int64_t m) { return (m + 1) / 2; }
 
+// Quadrant extent the engine splits at: ceil(m/2), rounded up to a multiple
+// of 4 once it reaches 64.  Every temporary's rows and every quadrant offset
+// then stay 16-byte aligned, so the leaves keep their 16-byte load path; the
+// few extra rows or columns are virtual zeros, like quadrant 1's padding
+// for an odd extent (quadrant 1 keeps m minus this, at least 61).
+inline int64_t split_half(int64_t m) {
+  const int64_t h = (m + 1) / 2;
+  return h >= 64 ? (h + 3) / 4 * 4 : h;
+}
+
 // Stop rule: split iff levels remain and floor(min(m,k,n)/2) >= max(leaf,1).
 inline bool splits(int64_t m, int64_t k, int64_t n, int levels_left, int64_t leaf) {
   int64_t mn = m < k ? m : k;
@@ -149,6 +159,24 @@ size_t pipelined_need(int64_t M, int64_t N, int64_t K, int depth, int tile);
 void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const float* A,
                          int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
                          int depth, int tile, fastmm_stats_t& st);
+
+// Staging of one product's operands.  The leaf kernels' 16-byte load path
+// (slabs straight into LDS) needs 16-byte aligned rows and K, N multiples of
+// 4; without it every leaf of the launch takes the 4-byte path (23-30%
+// slower).  Host operands are always staged; device operands that miss
+// those conditions are copied once.  Staged A is M x K4 (lda K4), staged B
+// K4 x N4 (ldb N4), with K4, N4 = K, N rounded up to 4 and zeros beyond K
+// and N, so the product can run on the padded extents.
+struct Staging {
+  bool a = false, b = false;  // operand staged
+  int64_t K4 = 0, N4 = 0;
+  size_t a_bytes = 0, b_bytes = 0;  // workspace bytes of the staged copies
+};
+Staging plan_staging(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
+                     int64_t ldb, bool on_dev);
+// Enqueues the staging copies and zero padding (memsets: not for graphs).
+void stage_operands(const Staging& g, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                    const float* B, int64_t ldb, float* dA, float* dB, hipStream_t sm);
 
 // The single-product path behind fastmm_gemm_ex (caller holds L.mu).
 void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,

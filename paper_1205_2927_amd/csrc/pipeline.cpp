@@ -109,7 +109,7 @@ size_t pipelined_need(int64_t M, int64_t N, int64_t K, int depth, int tile) {
 void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const float* A,
                          int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
                          int depth, int tile, fastmm_stats_t& st) {
-  const int64_t m2 = half_up(M), k2 = half_up(K), n2 = half_up(N);
+  const int64_t m2 = split_half(M), k2 = split_half(K), n2 = split_half(N);
   const int64_t mb = M - m2, kb = K - k2, nb = N - n2;
   const bool wino = depth >= 1;
   const TileShape ts = tile_shape(tile);

@@ -27,13 +27,14 @@ struct Span {
   int64_t off, len;
 };
 
-// 2^levels consecutive spans of [0, n), halving with the ceil part first.
+// 2^levels consecutive spans of [0, n), halving with the larger part first
+// (split_half: ceil(n/2), rounded up to a multiple of 4 from 64 on).
 void split_spans(int64_t off, int64_t n, int levels, std::vector<Span>& out) {
   if (levels == 0) {
     out.push_back({off, n});
     return;
   }
-  const int64_t h = half_up(n);
+  const int64_t h = split_half(n);
   split_spans(off, h, levels - 1, out);
   split_spans(off + h, n - h, levels - 1, out);
 }
@@ -55,35 +56,37 @@ void rmul_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
   }
   const bool on_dev = operands_on_device(M, N, K, A, B, C);
   const int d = K == 0 ? 0 : effective_depth(M, N, K, depth, leaf);
+  // Staging as in the Winograd path (plan_staging).  The spans follow M, K
+  // and N; the last span of K (of N) also reads the staged zero padding up
+  // to K4 (N4), so that its extent stays a multiple of 4.
+  const Staging sg = plan_staging(M, N, K, A, lda, B, ldb, on_dev);
   std::vector<Span> rs, ks, cs;
   split_spans(0, M, d, rs);
   split_spans(0, K, d, ks);
   split_spans(0, N, d, cs);
+  auto padded = [](const Span& sp, int64_t n, int64_t n4) {
+    return sp.off + sp.len == n ? sp.len + (n4 - n) : sp.len;
+  };
   const int nb = 1 << d;
   // Split-BF16 leaves run here on the register-split kernel (128x128 tiles,
   // no packed operands).
   const TileShape ts = tile == kTileBf16x3 ? TileShape{128, 128} : tile_shape(tile);
 
-  const size_t a_bytes = on_dev ? 0 : align_up((size_t)M * K * 4, 256);
-  const size_t b_bytes = on_dev ? 0 : align_up((size_t)K * N * 4, 256);
+  const size_t a_bytes = sg.a_bytes;
+  const size_t b_bytes = sg.b_bytes;
   const size_t c_bytes = on_dev ? 0 : align_up((size_t)M * N * 4, 256);
   const size_t phase_desc = align_up((size_t)nb * nb * sizeof(GemmDesc), 256);
   const size_t d_bytes = phase_desc * nb;
   char* ws = ensure_arena(L, a_bytes + b_bytes + c_bytes + d_bytes);
   char* host = ensure_pinned(L, d_bytes);
-  const float* dA = on_dev ? A : reinterpret_cast<const float*>(ws);
-  const float* dB = on_dev ? B : reinterpret_cast<const float*>(ws + a_bytes);
+  float* dA = sg.a ? reinterpret_cast<float*>(ws) : const_cast<float*>(A);
+  float* dB = sg.b ? reinterpret_cast<float*>(ws + a_bytes) : const_cast<float*>(B);
   float* dC = on_dev ? C : reinterpret_cast<float*>(ws + a_bytes + b_bytes);
-  const int64_t la = on_dev ? lda : std::max<int64_t>(K, 1), lb = on_dev ? ldb : N,
+  const int64_t la = sg.a ? std::max<int64_t>(sg.K4, 1) : lda, lb = sg.b ? sg.N4 : ldb,
                 lc = on_dev ? ldc : N;
   char* ddesc = ws + a_bytes + b_bytes + c_bytes;
   hipStream_t sm = L.stream;
-  if (!on_dev && K > 0) {
-    FASTMM_HIP(hipMemcpy2DAsync(const_cast<float*>(dA), K * 4, A, lda * 4, K * 4, M,
-                                hipMemcpyHostToDevice, sm));
-    FASTMM_HIP(hipMemcpy2DAsync(const_cast<float*>(dB), N * 4, B, ldb * 4, N * 4, K,
-                                hipMemcpyHostToDevice, sm));
-  }
+  stage_operands(sg, M, N, K, A, lda, B, ldb, dA, dB, sm);
   // One descriptor array per reduction chunk p: every non-empty result block
   // (i, j) with A block (i, p), B block (p, j); chunk 0 overwrites.
   std::vector<int> totals(nb, 0), counts(nb, 0);
@@ -102,8 +105,8 @@ void rmul_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
         g.C = dC + rs[i].off * lc + cs[j].off;
         g.ldc = lc;
         g.a_rows = (int32_t)rs[i].len;
-        g.b_cols = (int32_t)cs[j].len;
-        g.kmax = (int32_t)ks[p].len;
+        g.b_cols = (int32_t)padded(cs[j], N, sg.N4);
+        g.kmax = (int32_t)padded(ks[p], K, sg.K4);
         g.c_rows = (int32_t)rs[i].len;
         g.c_cols = (int32_t)cs[j].len;
         g.tiles_n = (g.c_cols + ts.bn - 1) / ts.bn;
@@ -113,7 +116,7 @@ void rmul_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
         if (!(aligned16(g.A) && aligned16(g.B) && g.lda % 4 == 0 && g.ldb % 4 == 0 &&
               g.kmax % 4 == 0 && g.b_cols % 4 == 0))
           vecs[p] = 0;
-        st.leaf_flops += 2.0 * g.c_rows * g.c_cols * g.kmax;
+        st.leaf_flops += 2.0 * g.c_rows * g.c_cols * ks[p].len;
         v.push_back(g);
       }
     if (total > INT32_MAX) throw Error(kNotSupported, "leaf launch too large");

@@ -295,3 +295,32 @@ def test_depth_first_fallback_bitwise(fastmm, monkeypatch):
         if st["launches"] > bfs_launches:
             ok += 1
     assert ok >= 2
+
+
+@pytest.mark.parametrize("m,k,n,depth", [(301, 257, 203, 0), (513, 259, 387, 1), (700, 645, 1021, 2),
+                                         (1030, 1031, 1029, 3)])
+def test_misaligned_device_operands_staged(fastmm, m, k, n, depth):
+    # Device operands whose rows are not 16-byte aligned (base offset by one
+    # float, odd leading dimensions, K and N not multiples of 4) are staged
+    # into padded buffers: exact on certified integers, A and B untouched,
+    # nothing written outside C.
+    import torch
+    A = ints(141 + m, m, k)
+    B = ints(142 + n, k, n)
+    cert = W.Certificate()
+    ref = W.winograd(A.astype(np.int64), B.astype(np.int64), depth, 1, cert)
+    assert cert.exact_in_fp32
+    Abig = torch.zeros(m * (k + 3) + 1, device="cuda")
+    Bbig = torch.zeros(k * (n + 5) + 1, device="cuda")
+    Abig[1:].view(m, k + 3)[:, :k] = dev(A)
+    Bbig[1:].view(k, n + 5)[:, :n] = dev(B)
+    A0, B0 = Abig.clone(), Bbig.clone()
+    C = torch.full((m, n + 2), float("nan"), device="cuda")
+    say(f"misaligned device operands {m}x{k}x{n} depth={depth}")
+    fastmm.gemm(m, n, k, Abig.data_ptr() + 4, Bbig.data_ptr() + 4, C.data_ptr(), depth=depth,
+                leaf=1, lda=k + 3, ldb=n + 5, ldc=n + 2)
+    got = host(C)
+    assert np.array_equal(got[:, :n].astype(np.int64), ref)
+    assert np.all(np.isnan(got[:, n:]))
+    assert torch.equal(Abig, A0) and torch.equal(Bbig, B0)
+
