@@ -126,6 +126,40 @@ def sweep(fastmm, torch, sizes):
         del A, B, C
 
 
+def precision_config(fastmm, torch):
+    """The precision forms' own workload: n = 8192 and 16384, depth 2,
+    inputs uniform[-1, 1] and log-uniform magnitudes 2^-8..2^8 with random
+    signs; the FP32 leaf, split-BF16 and scaled split-FP16 leaves on the same
+    operands (in HBM), each timed (best of 3) and checked against the oracle
+    on sampled rows.  One JSON line per (n, distribution, leaf form)."""
+    import synthgen
+    from oracle import checks
+    fastmm.set_profiling(True)  # leaf-phase times from the library's HIP events
+    for n in (8192, 16384):
+        for dist in ("uniform", "loguniform"):
+            hA = torch.empty((n, n), dtype=torch.float32, pin_memory=True)
+            hB = torch.empty((n, n), dtype=torch.float32, pin_memory=True)
+            fill = synthgen.fill_uniform_pm1 if dist == "uniform" else synthgen.fill_loguniform
+            fill(1001 + 4, n, n, hA.data_ptr())
+            fill(2001 + 4, n, n, hB.data_ptr())
+            A, B = hA.to("cuda"), hB.to("cuda")
+            C = torch.empty((n, n), device="cuda")
+            rows = synthgen.row_sample(7008, n, 8)
+            for name, tile in (("fp32", 0), ("bf16x3", 8), ("fp16x3", 9)):
+                fn = lambda: fastmm.gemm(n, n, n, A, B, C, depth=2, leaf=1, tile=tile)
+                tot, ts = time_calls(fn, 3, 1)
+                st = fastmm.get_stats()
+                err = checks.sampled_rows_rel(C.cpu().numpy(), hA.numpy(), hB.numpy(), rows)
+                leaf_tf = st["leaf_flops"] / (st["leaf_ms"] * 1e-3) / 1e12
+                peak = PEAK_FP32_TFLOPS if tile == 0 else PEAK_16BIT_TFLOPS / 3
+                print(json.dumps({"precision_n": n, "dist": dist, "leaf_form": name, "depth": 2,
+                                  "ms": 1e3 * min(ts), "effective_GFLOPS": 2.0 * n ** 3 / min(ts) / 1e9,
+                                  "leaf_TFLOPs_fp32_equivalent": leaf_tf,
+                                  "leaf_frac_of_roofline": leaf_tf / peak,
+                                  "sampled_rows_rel": err}), flush=True)
+            del A, B, C, hA, hB
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -150,6 +184,9 @@ def main():
                     help="time the pinned-host path in the main loop (profiling that path)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (calibrates HBM counters)")
+    ap.add_argument("--precision-config", action="store_true",
+                    help="instead of the headline: the precision forms at n = 8192 and 16384, "
+                         "depth 2, uniform and log-uniform inputs, one JSON line each")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline: n-sweep of plain, Winograd and the classic "
                          "recursion, one JSON line per n")
@@ -166,6 +203,9 @@ def main():
     from paper_1205_2927_amd import fastmm
 
     fastmm.load()
+    if args.precision_config:
+        precision_config(fastmm, torch)
+        return
     if args.sweep:
         sizes = sorted(set(range(2048, 19457, 512)) | {6004, 6015, 6016, 10004, 12031, 12032, 14004})
         sweep(fastmm, torch, sizes)
@@ -309,6 +349,8 @@ def main():
                     "ms": 1e3 * min(ts), "effective_GFLOPS": flops / min(ts) / 1e9,
                     "leaf_ms": sp["leaf_ms"],
                     "leaf_TFLOPs_fp32_equivalent": sp["leaf_flops"] / (sp["leaf_ms"] * 1e-3) / 1e12,
+                    "leaf_frac_of_16bit_roofline":
+                        sp["leaf_flops"] / (sp["leaf_ms"] * 1e-3) / 1e12 / (PEAK_16BIT_TFLOPS / 3),
                     "sampled_rows_rel": checks.sampled_rows_rel(Cp, An, Bn, rows_p)}
                 del Cp
         log(f"bench: precision forms {precision}")
