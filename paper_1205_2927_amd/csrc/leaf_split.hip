@@ -486,6 +486,46 @@ leaf_pack_kernel(const GemmDesc* __restrict__ descs, int a_units, int per_desc) 
     const int cv = min(kPackRows, d.b_cols - t * kPackRows);
     const int64_t ldb = d.ldb;
     const float* b = d.B + (int64_t)t * kPackRows;
+    if constexpr (VEC) {
+      // Transposed through LDS: 16-byte loads along rows of B, then each
+      // thread gathers 8 k of one column and the wavefront writes 1 KB of
+      // packed rows at once (column-wise global writes ran at 3 TB/s).  Row
+      // k of the slab keeps column n at n ^ (8 * (k / 8)), which makes the
+      // gathers (lanes: 8 columns x 4 chunks) free of bank conflicts.
+      __shared__ __attribute__((aligned(16))) float bt[kPackK * kPackRows];
+      int e = 0;
+      for (int s = s0; s < s1; ++s) {
+        const int k0 = s * kPackK;
+        const int kv = min(kPackK, kmax - k0);
+        char* blk = out + (int64_t)s * kPackBlockBytes;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int kr = (tid >> 5) + 8 * i, n4 = 4 * (tid & 31);
+          float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (kr < kv && n4 < cv) x = *reinterpret_cast<const float4*>(b + (int64_t)(k0 + kr) * ldb + n4);
+          *reinterpret_cast<float4*>(&bt[kr * kPackRows + (n4 ^ (8 * (kr >> 3)))]) = x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+          const int q = it * 256 + tid;
+          const int n = q >> 2, c = q & 3;  // lanes: 16 columns x 4 chunks per wavefront
+          float v[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) v[i] = bt[(8 * c + i) * kPackRows + (n ^ (8 * c))];
+          if constexpr (FMT == kSplitFp16) e = n < cv ? d.eb[t * kPackRows + n] : 0;
+          u16x4 h0, l0, h1, l1;
+          split4<FMT>(make_float4(v[0], v[1], v[2], v[3]), e, h0, l0);
+          split4<FMT>(make_float4(v[4], v[5], v[6], v[7]), e, h1, l1);
+          const int o = pack_slot(n, c);
+          *reinterpret_cast<u16x8*>(blk + o) = u16x8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+          *reinterpret_cast<u16x8*>(blk + kPackHalfBytes + o) =
+              u16x8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+        }
+        __syncthreads();
+      }
+      return;
+    }
     for (int s = s0; s < s1; ++s) {
       const int k0 = s * kPackK;
       const int kv = min(kPackK, kmax - k0);
