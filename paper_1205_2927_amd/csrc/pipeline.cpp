@@ -109,8 +109,14 @@ size_t pipelined_need(int64_t M, int64_t N, int64_t K, int depth, int tile) {
 void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const float* A,
                          int64_t lda, const float* B, int64_t ldb, float* C, int64_t ldc,
                          int depth, int tile, fastmm_stats_t& st) {
-  const int64_t m2 = split_half(M), k2 = split_half(K), n2 = split_half(N);
-  const int64_t mb = M - m2, kb = K - k2, nb = N - n2;
+  // The device copies are padded as in plan_staging: A is M x K4 (ld K4),
+  // B is K4 x N4 and C is M x N4, zero beyond K and N, so that every leaf
+  // operand keeps 16-byte aligned rows.  The split and all device-side
+  // extents use K4 and N4; the copies move the K and N valid columns.
+  const int64_t K4 = (K + 3) / 4 * 4, N4 = (N + 3) / 4 * 4;
+  const int64_t m2 = split_half(M), k2 = split_half(K4), n2 = split_half(N4);
+  const int64_t mb = M - m2, kb = K4 - k2, nb = N4 - n2;
+  const int64_t kb_v = std::max<int64_t>(0, K - k2), nb_v = std::max<int64_t>(0, N - n2);
   const bool wino = depth >= 1;
   const TileShape ts = tile_shape(tile);
 
@@ -121,8 +127,8 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     off += align_up(bytes, 256);
     return o;
   };
-  const size_t oA = take((size_t)M * K * 4), oB = take((size_t)K * N * 4),
-               oC = take((size_t)M * N * 4);
+  const size_t oA = take((size_t)M * K4 * 4), oB = take((size_t)K4 * N4 * 4),
+               oC = take((size_t)M * N4 * 4);
   size_t oS = 0, oT = 0, oP = 0;
   if (wino) {
     oS = take((size_t)4 * m2 * k2 * 4);
@@ -165,10 +171,10 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   // Left operand of top-level product i (0..6), band b; right operand of i.
   auto left = [&](int i, const Band& b) -> V {
     switch (i) {
-      case 0: return {dA + b.r0 * K, K, b.rows, k2};                 // A11
-      case 1: return {dA + b.r0 * K + k2, K, b.rows, kb};            // A12
+      case 0: return {dA + b.r0 * K4, K4, b.rows, k2};               // A11
+      case 1: return {dA + b.r0 * K4 + k2, K4, b.rows, kb};          // A12
       case 2: return {S + 3 * ma + b.r0 * k2, k2, b.rows, k2};       // S4
-      case 3: return {dA + (m2 + b.r0) * K + k2, K, b.bot, kb};      // A22
+      case 3: return {dA + (m2 + b.r0) * K4 + k2, K4, b.bot, kb};    // A22
       case 4: return {S + 0 * ma + b.r0 * k2, k2, b.rows, k2};       // S1
       case 5: return {S + 1 * ma + b.r0 * k2, k2, b.rows, k2};       // S2
       default: return {S + 2 * ma + b.r0 * k2, k2, b.rows, k2};      // S3
@@ -176,9 +182,9 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   };
   auto right = [&](int i) -> V {
     switch (i) {
-      case 0: return {dB, N, k2, n2};                 // B11
-      case 1: return {dB + k2 * N, N, kb, n2};        // B21
-      case 2: return {dB + k2 * N + n2, N, kb, nb};   // B22
+      case 0: return {dB, N4, k2, n2};                  // B11
+      case 1: return {dB + k2 * N4, N4, kb, n2};        // B21
+      case 2: return {dB + k2 * N4 + n2, N4, kb, nb};   // B22
       case 3: return {T + 3 * tb, n2, k2, n2};        // T4
       case 4: return {T + 0 * tb, n2, k2, n2};        // T1
       case 5: return {T + 1 * tb, n2, k2, n2};        // T2
@@ -209,14 +215,14 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   auto plain_problem = [&](const Band& b, int half) {
     Problem p;
     p.M = b.rows;
-    p.K = K;
+    p.K = K4;
     p.N = half == 0 ? n2 : nb;
-    p.A = dA + b.r0 * K;
-    p.lda = K;
+    p.A = dA + b.r0 * K4;
+    p.lda = K4;
     p.B = dB + (half ? n2 : 0);
-    p.ldb = N;
-    p.C = dC + b.r0 * N + (half ? n2 : 0);
-    p.ldc = N;
+    p.ldb = N4;
+    p.C = dC + b.r0 * N4 + (half ? n2 : 0);
+    p.ldc = N4;
     p.depth = 0;
     p.tile = tile;
     return p;
@@ -369,10 +375,10 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       const Band& b = bands[bi];
       PostAddNode np{};
       np.P = P + b.r0 * n2;
-      np.dst = dC + b.r0 * N;
-      np.ld = N;
+      np.dst = dC + b.r0 * N4;
+      np.ld = N4;
       np.p_stride = pc;
-      np.bot_off = m2 * N;
+      np.bot_off = m2 * N4;
       np.top_rows = (int32_t)b.rows;
       np.bot_rows = (int32_t)b.bot;
       np.left_cols = (int32_t)n2;
@@ -395,6 +401,12 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   FASTMM_HIP(hipEventRecord(L.sync_ev[0], cs));
   FASTMM_HIP(hipStreamWaitEvent(hs, L.sync_ev[0], 0));
   FASTMM_HIP(hipStreamWaitEvent(ds, L.sync_ev[0], 0));
+  // Zero padding of the device copies, ahead of the copies on their stream.
+  if (K4 > K) {
+    FASTMM_HIP(hipMemset2DAsync(dA + K, K4 * 4, 0, (K4 - K) * 4, M, hs));
+    FASTMM_HIP(hipMemsetAsync(dB + K * N4, 0, (K4 - K) * N4 * 4, hs));
+  }
+  if (N4 > N) FASTMM_HIP(hipMemset2DAsync(dB + N, N4 * 4, 0, (N4 - N) * 4, K, hs));
   if (slot) FASTMM_HIP(hipMemcpyAsync(ddesc, host, 256 * slot, hipMemcpyHostToDevice, cs));
 
   // ---- inputs
@@ -405,10 +417,10 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   };
   auto a_band = [&](int qr, int qc, const Band& b) {
     const int64_t rows = qr ? b.bot : b.rows;
-    h2d_block(dA, K, A, lda, (qr ? m2 : 0) + b.r0, qc ? k2 : 0, rows, qc ? kb : k2, hs);
+    h2d_block(dA, K4, A, lda, (qr ? m2 : 0) + b.r0, qc ? k2 : 0, rows, qc ? kb_v : k2, hs);
   };
   auto b_quad = [&](int qr, int qc) {
-    h2d_block(dB, N, B, ldb, qr ? k2 : 0, qc ? n2 : 0, qr ? kb : k2, qc ? nb : n2, hs);
+    h2d_block(dB, N4, B, ldb, qr ? k2 : 0, qc ? n2 : 0, qr ? kb_v : k2, qc ? nb_v : n2, hs);
   };
 
   int launches = 0, nleaf = 0;
@@ -425,8 +437,8 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     hipEvent_t e = next_event();
     FASTMM_HIP(hipEventRecord(e, cs));
     FASTMM_HIP(hipStreamWaitEvent(ds, e, 0));
-    d2h_block(C, ldc, dC, N, (qr ? m2 : 0) + b.r0, qc ? n2 : 0, qr ? b.bot : b.rows,
-              qc ? nb : n2, ds);
+    d2h_block(C, ldc, dC, N4, (qr ? m2 : 0) + b.r0, qc ? n2 : 0, qr ? b.bot : b.rows,
+              qc ? nb_v : n2, ds);
   };
   auto post = [&](int q, int bi) {
     const Band& b = bands[bi];
@@ -474,10 +486,10 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       PreAddNode n{};
       if (side == 0) {
         const Band& b = bands[bi];
-        n.src = dA + b.r0 * K;
+        n.src = dA + b.r0 * K4;
         n.dst = S + b.r0 * k2;
-        n.ld = K;
-        n.bot_off = m2 * K;
+        n.ld = K4;
+        n.bot_off = m2 * K4;
         n.out_stride = ma;
         n.top_rows = (int32_t)b.rows;
         n.bot_rows = (int32_t)b.bot;
@@ -486,7 +498,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
         n.h_r = (int32_t)b.rows;
         n.h_c = (int32_t)k2;
       } else {
-        n = preadd_node(dB, N, K, N, k2, n2, T);
+        n = preadd_node(dB, N4, K4, N4, k2, n2, T);
       }
       n.mask = (int32_t)mask;
       const size_t o = next_slot();
@@ -536,12 +548,12 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     const int pivot = std::min(1, nband - 1);
     std::vector<hipEvent_t> ea(nband);
     hipEvent_t eBR = nullptr;
-    h2d_block(dB, N, B, ldb, 0, 0, K, n2, hs);
+    h2d_block(dB, N4, B, ldb, 0, 0, K, n2, hs);
     for (int bi = 0; bi < nband; ++bi) {
-      h2d_block(dA, K, A, lda, bands[bi].r0, 0, bands[bi].rows, K, hs);
+      h2d_block(dA, K4, A, lda, bands[bi].r0, 0, bands[bi].rows, K, hs);
       ea[bi] = arrive();
       if (bi == pivot) {
-        h2d_block(dB, N, B, ldb, 0, n2, K, nb, hs);
+        h2d_block(dB, N4, B, ldb, 0, n2, K, nb_v, hs);
         eBR = arrive();
       }
     }
@@ -551,7 +563,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       hipEvent_t e = next_event();
       FASTMM_HIP(hipEventRecord(e, cs));
       FASTMM_HIP(hipStreamWaitEvent(ds, e, 0));
-      d2h_block(C, ldc, dC, N, b.r0, half ? n2 : 0, b.rows, half ? nb : n2, ds);
+      d2h_block(C, ldc, dC, N4, b.r0, half ? n2 : 0, b.rows, half ? nb_v : n2, ds);
     };
     for (int bi = 0; bi < nband; ++bi) {
       wait(ea[bi]);
