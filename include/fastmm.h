@@ -126,10 +126,13 @@ typedef struct {
  * leaf: a node (m, k, n) splits iff levels remain and
  * floor(min(m, k, n) / 2) >= max(leaf, 1) (leaf = 3008 reproduces the
  * paper's recursion point 6016, Section 3.1).  depth > 16 is invalid.
- * C must not overlap A or B.  Dimensions above 2^31 - 1, lda above 2^21 or
- * ldb above 2^24 give FASTMM_ERROR_NOT_SUPPORTED (the leaf kernels address a
- * tile's slab with 32-bit offsets).  Every argument is checked before the
- * device is touched. */
+ * C must not overlap A or B.  M above 2^31 - 1, K or N above 2^31 - 4, lda
+ * above 2^21 or ldb above 2^24 give FASTMM_ERROR_NOT_SUPPORTED (the leaf
+ * kernels address a tile's slab with 32-bit offsets, and operands are
+ * padded to multiples of 4 columns).  Every argument is checked before the
+ * device is touched.  Device operands whose rows are not 16-byte aligned, or
+ * whose K or N is not a multiple of 4, are first copied into zero-padded
+ * workspace buffers (host operands always are): A and B are only read. */
 int fastmm_gemm(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, const float* B,
                 int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf);
 

@@ -531,8 +531,9 @@ bool overlaps(Range a, Range b) { return a.lo < a.hi && b.lo < b.hi && a.lo < b.
 void validate_gemm_args(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                         const float* B, int64_t ldb, const float* C, int64_t ldc, int depth) {
   if (M < 0 || N < 0 || K < 0) throw Error(kInvalidValue, "negative dimension");
-  if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
-    throw Error(kNotSupported, "dimension above 2^31-1");
+  // K and N leave room for the staging's rounding up to a multiple of 4.
+  if (M > INT32_MAX || N > INT32_MAX - 3 || K > INT32_MAX - 3)
+    throw Error(kNotSupported, "dimension above 2^31-1 (K or N above 2^31-4)");
   if (lda < std::max<int64_t>(1, K)) throw Error(kInvalidValue, "lda < max(1, K)");
   if (ldb < std::max<int64_t>(1, N)) throw Error(kInvalidValue, "ldb < max(1, N)");
   if (ldc < std::max<int64_t>(1, N)) throw Error(kInvalidValue, "ldc < max(1, N)");
@@ -721,6 +722,8 @@ Staging plan_staging(int64_t M, int64_t N, int64_t K, const float* A, int64_t ld
   Staging g;
   g.K4 = (K + 3) / 4 * 4;
   g.N4 = (N + 3) / 4 * 4;
+  if (g.K4 > INT32_MAX || g.N4 > INT32_MAX)
+    throw Error(kNotSupported, "K or N within 3 of 2^31: no room for the 16-byte padding");
   g.a = !on_dev || !(aligned16(A) && lda % 4 == 0 && K % 4 == 0);
   g.b = !on_dev || !(aligned16(B) && ldb % 4 == 0 && N % 4 == 0 && K % 4 == 0);
   g.a_bytes = (g.a && K > 0) ? align_up((size_t)M * g.K4 * 4, 256) : 0;

@@ -1,6 +1,7 @@
 """Argument validation of the C ABI, on the host: every check runs before the
 library touches the device, so these calls return their status without a GPU
-(addresses are never dereferenced).  Limits: dimensions up to 2^31 - 1, lda up
+(addresses are never dereferenced).  Limits: M up to 2^31 - 1, K and N up to
+2^31 - 4 (room to pad them to a multiple of 4), lda up
 to 2^21 and ldb up to 2^24 (32-bit byte offsets inside a leaf tile's slab)."""
 import pytest
 
@@ -27,6 +28,7 @@ def lib():
     ((4, 4, 4, A, 4, B, 4, A + 8, 4, 0, 1), INV, "overlaps"),
     ((4, 4, 4, A, 4, B, 4, B + 60, 4, 0, 1), INV, "overlaps"),
     ((1 << 31, 4, 4, A, 4, B, 4, C, 4, 0, 1), NSUP, "2^31"),
+    ((4, (1 << 31) - 2, 4, A, 4, B, 1 << 31, C, 1 << 31, 0, 1), NSUP, "2^31-4"),  # no room to pad N
     ((4, 4, 4, A, (1 << 21) + 1, B, 4, C, 4, 0, 1), NSUP, "lda above"),
     ((4, 4, 4, A, 4, B, (1 << 24) + 1, C, (1 << 24) + 1, 0, 1), NSUP, "ldb above"),
 ])
