@@ -332,15 +332,16 @@ def main():
         log(f"bench: classic recursion {classic}")
 
     # Context: the split-precision leaf forms (never the FP32 headline): split
-    # BF16 (tile 8) and scaled split FP16 (tile 9) leaves, plain and at the
-    # headline depth, same operands in HBM; sampled-row error against the
-    # oracle.  Leaf times include the forms' pack (and FP16 scale) passes.
+    # BF16 (tile 8) and scaled split FP16 (tile 9) leaves, plain and at depth
+    # 2 (their workload's depth), same operands in HBM; sampled-row error
+    # against the oracle.  Leaf times include the forms' pack (and FP16
+    # scale) passes.
     precision = None
     if not args.no_device_context and not args.pinned_headline:
         precision = {}
         rows_p = synthgen.row_sample(7008, M, 4)
         for name, tile in (("bf16x3", 8), ("fp16x3", 9)):
-            for d in sorted({0, best}):
+            for d in (0, 2):
                 fn = lambda: fastmm.gemm(M, N, K, A, B, C, depth=d, leaf=args.leaf, tile=tile)
                 tot, ts = time_calls(fn, 3, 1)
                 sp = fastmm.get_stats()
