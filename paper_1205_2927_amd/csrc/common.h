@@ -29,6 +29,7 @@ struct GemmDesc {
   int32_t tiles_n;          // ceil(c_cols / BN) for the launch's tile shape
   int32_t tile_begin;       // first tile of this problem within the launch
   int32_t beta;             // 0: C = A B; 1: C += A B
+  int32_t prepacked;        // split-precision leaves: pa / pb already written
   // Split-precision leaves only (else unused): the packed hi/lo operands
   // (leaf_packed_bytes in all, B's part from pa + leaf_packed_a_bytes) and,
   // for the scaled FP16 form, power-of-two exponents of the a_rows rows of A
@@ -57,6 +58,23 @@ struct PreAddNode {
   int32_t h_r, h_c;               // rows of this node, quadrant width
   int32_t block_begin;            // first workgroup of this node within the launch
   int32_t mask;                   // outputs to write (bit q-1 for S_q / T_q); 0 = all
+};
+
+// One node of a fused pre-addition and pack launch (split-BF16 leaves, last
+// level of the recursion): the parent operand's quadrants (geometry as in
+// PreAddNode; dst, out_stride and mask unused) are combined into S1..S4
+// (T1..T4) in FP32 exactly as the pre-addition kernel does, and the seven
+// leaf operands of the node -- A side: A11, A12, S4, A22, S1, S2, S3; B side:
+// B11, B21, B22, T4, T1, T2, T3 -- are written straight in the packed layout
+// of the split-precision leaf (leaf_pack_kernel's), never as FP32.
+struct PackNode {
+  PreAddNode q;
+  void* dst[7];         // packed operand of leaf i of the node
+  int32_t slabs[7];     // its K-slabs of 32: ceil(kmax / 32)
+  int32_t tiles;        // 128-row (A) or 128-column (B) tiles of every output
+  int32_t max_slabs;    // largest of slabs[]
+  int32_t unit_begin;   // first workgroup of this node within the launch
+  int32_t pad_;
 };
 
 // Quadrants (bit 0 = X11, 1 = X12, 2 = X21, 3 = X22) that pre-addition
@@ -246,7 +264,13 @@ void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, boo
 // into pa / pb, then the leaf.  ext: largest extents over the descriptors.
 struct LeafExtents {
   int max_a_rows = 0, max_b_cols = 0, max_c_rows = 0, max_c_cols = 0, max_slabs = 0, max_kmax = 0;
+  bool any_unpacked = true;  // some descriptor still needs the pack pass
 };
+// Workgroups of a fused pre-addition and pack node (4 K-slabs per workgroup).
+int pack_node_units(const PackNode& n);
+// side 0: A operands, 1: B operands; nodes with unit_begin prefixes.
+void launch_preadd_pack(int side, const PackNode* d_nodes, int nnodes, int total_units,
+                        hipStream_t stream);
 // Bytes of the FP16 scale exponents and scratch of a rows x k by k x cols leaf.
 int64_t leaf_scale_bytes(int64_t rows, int64_t cols, int64_t k);
 // Bytes of the packed operands of a rows x k by k x cols leaf (A's part first).

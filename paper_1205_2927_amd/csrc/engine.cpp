@@ -221,6 +221,10 @@ size_t problem_temp_bytes(const Problem& p) {
 
 void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
   s = Schedule();
+  // Split-BF16 leaves take the last level's pre-additions and the pack pass
+  // in one fused pass (FASTMM_FUSED_PACK=0: the two passes, for comparison).
+  const char* fe = std::getenv("FASTMM_FUSED_PACK");
+  const bool fuse_allowed = !(fe && fe[0] == '0');
   int maxd = 0;
   for (const auto& p : probs) maxd = std::max(maxd, p.depth);
   s.max_depth = maxd;
@@ -240,6 +244,14 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     const int d = p.depth;
     std::vector<View> Av{{p.A, p.lda, p.ar(), p.ac()}}, Bv{{p.B, p.ldb, p.br(), p.bc()}};
     size_t t_off = 0;  // floats into p.b_tree
+    // Fused pre-addition and pack (split-BF16 leaves, depth >= 1, no shared
+    // B tree): nodes of the last level whose quadrants allow 16-byte access.
+    const bool fuse = fuse_allowed && p.tile == kTileBf16x3 && d >= 1 && !p.b_tree;
+    struct Fused {
+      int64_t x;
+      PreAddNode a, b;
+    };
+    std::vector<Fused> fused;
     // Pre-additions, level by level; the next level's operands are views
     // of this level's operands or of the new S / T blocks.
     for (int l = 0; l < d; ++l) {
@@ -258,9 +270,14 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
       for (int64_t x = 0; x < nodes; ++x) {
         const View& a = Av[x];
         const View& b = Bv[x];
-        s.preA[l].push_back(preadd_node(a.p, a.ld, a.vrows, a.vcols, c.m, c.k, S + x * 4 * sa));
-        if (!p.b_tree_ready)
-          s.preB[l].push_back(preadd_node(b.p, b.ld, b.vrows, b.vcols, c.k, c.n, T + x * 4 * tb));
+        const PreAddNode na = preadd_node(a.p, a.ld, a.vrows, a.vcols, c.m, c.k, S + x * 4 * sa);
+        const PreAddNode nb = preadd_node(b.p, b.ld, b.vrows, b.vcols, c.k, c.n, T + x * 4 * tb);
+        if (fuse && l == d - 1 && pre_vec_ok(na) && pre_vec_ok(nb)) {
+          fused.push_back({x, na, nb});
+        } else {
+          s.preA[l].push_back(na);
+          if (!p.b_tree_ready) s.preB[l].push_back(nb);
+        }
         const View a11 = quadrant(a, 0, 0, c.m, c.k), a12 = quadrant(a, 0, 1, c.m, c.k),
                    a22 = quadrant(a, 1, 1, c.m, c.k);
         const View b11 = quadrant(b, 0, 0, c.k, c.n), b21 = quadrant(b, 1, 0, c.k, c.n),
@@ -287,6 +304,7 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     const Dims lf = dims[d];
     const int64_t nleaves = pow7(d);
     const TileShape ts = tile_shape(p.tile);
+    const size_t leaf_base = s.leaf[p.tile].size();
     const bool split = p.tile == kTileBf16x3 || p.tile == kTileFp16x3;
     const int64_t packed = split ? leaf_packed_bytes(lf.m, lf.n, lf.k) : 0;
     char* packs = split ? reinterpret_cast<char*>(carve((size_t)(nleaves * packed / 4))) : nullptr;
@@ -324,6 +342,28 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
       }
       g.tiles_n = (g.c_cols + ts.bn - 1) / ts.bn;
       s.leaf[p.tile].push_back(g);
+    }
+    // Fused nodes: the seven leaves of node x are leaf_base + 7 x + i.
+    for (const Fused& f : fused) {
+      PackNode na{}, nb{};
+      na.q = f.a;
+      nb.q = f.b;
+      na.tiles = (int32_t)((lf.m + 127) / 128);
+      nb.tiles = (int32_t)((lf.n + 127) / 128);
+      for (int i = 0; i < 7; ++i) {
+        GemmDesc& g = s.leaf[p.tile][leaf_base + 7 * f.x + i];
+        g.prepacked = 1;
+        na.dst[i] = g.pa;
+        nb.dst[i] = g.pb;
+        na.slabs[i] = nb.slabs[i] = (g.kmax + 31) / 32;
+        na.max_slabs = std::max(na.max_slabs, na.slabs[i]);
+      }
+      nb.max_slabs = na.max_slabs;
+      s.pack[0].push_back(na);
+      s.pack[1].push_back(nb);
+      // 7 packed outputs instead of 4 FP32 ones (same bytes per element)
+      const Dims& c = dims[d];
+      s.add_bytes += 12.0 * c.m * c.k + 12.0 * c.k * c.n;
     }
     s.leaves += nleaves;
     s.leaf_flops += (double)nleaves * 2.0 * lf.m * lf.n * lf.k;
@@ -370,6 +410,15 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     }
     if (b > INT32_MAX) throw Error(kNotSupported, "post-addition launch too large");
   }
+  for (int side = 0; side < 2; ++side) {
+    int64_t u = 0;
+    for (auto& n : s.pack[side]) {
+      n.unit_begin = (int32_t)u;
+      u += pack_node_units(n);
+    }
+    if (u > INT32_MAX) throw Error(kNotSupported, "fused pack launch too large");
+    s.pack_units[side] = (int)u;
+  }
   s.leaf_tiles_total.assign(kNumTiles, 0);
   for (int t = 0; t < kNumTiles; ++t) {
     s.vec_leaf[t] = true;
@@ -409,6 +458,7 @@ size_t schedule_desc_bytes(const Schedule& s) {
     b += align_up(s.post[l].size() * sizeof(PostAddNode), 256);
   }
   for (int t = 0; t < kNumTiles; ++t) b += align_up(s.leaf[t].size() * sizeof(GemmDesc), 256);
+  for (int side = 0; side < 2; ++side) b += align_up(s.pack[side].size() * sizeof(PackNode), 256);
   return b;
 }
 
@@ -442,6 +492,9 @@ void upload_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host) {
   }
   for (int t = 0; t < kNumTiles; ++t)
     s.d_leaf[t] = reinterpret_cast<const GemmDesc*>(put(s.leaf[t].data(), s.leaf[t].size() * sizeof(GemmDesc)));
+  for (int side = 0; side < 2; ++side)
+    s.d_pack[side] = reinterpret_cast<const PackNode*>(
+        put(s.pack[side].data(), s.pack[side].size() * sizeof(PackNode)));
   if (off) FASTMM_HIP(hipMemcpyAsync(desc_dev, desc_host, off, hipMemcpyHostToDevice, L.stream));
 }
 
@@ -455,6 +508,11 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
     if (ba) { launch_preadd(0, s.d_preA[l], (int)s.preA[l].size(), ba, s.vec_preA[l], L.stream); ++launches; }
     if (bb) { launch_preadd(1, s.d_preB[l], (int)s.preB[l].size(), bb, s.vec_preB[l], L.stream); ++launches; }
   }
+  for (int side = 0; side < 2; ++side)
+    if (s.pack_units[side] > 0) {
+      launch_preadd_pack(side, s.d_pack[side], (int)s.pack[side].size(), s.pack_units[side], L.stream);
+      ++launches;
+    }
   if (profile) FASTMM_HIP(hipEventRecord(L.ev[2], L.stream));
   if (leaf_begin) FASTMM_HIP(hipEventRecord(leaf_begin, L.stream));
   for (int t = 0; t < kNumTiles; ++t) {
@@ -469,9 +527,13 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
         ext.max_slabs = std::max(ext.max_slabs, (int)((g.kmax + 31) / 32));
         ext.max_kmax = std::max(ext.max_kmax, (int)g.kmax);
       }
+      ext.any_unpacked = false;
+      for (const auto& g : s.leaf[t])
+        if (!g.prepacked) ext.any_unpacked = true;
       launch_leaf_packed(t, s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t],
                          L.stream, s.xcd_chunk[t], ext);
-      launches += t == kTileFp16x3 ? 3 : 2;
+      // scale passes (FP16), the pack pass unless every operand is prepacked, the leaf
+      launches += (t == kTileFp16x3 ? 2 : 0) + (ext.any_unpacked ? 1 : 0) + 1;
     } else {
       launch_leaf_gemm(t, s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t],
                        L.stream, s.xcd_chunk[t], s.persistent ? L.leaf_queue : nullptr);

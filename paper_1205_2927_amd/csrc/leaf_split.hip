@@ -433,6 +433,7 @@ template <int FMT, bool VEC>
 __global__ void __launch_bounds__(256)
 leaf_pack_kernel(const GemmDesc* __restrict__ descs, int a_units, int per_desc) {
   const GemmDesc& d = descs[blockIdx.x / per_desc];
+  if (d.prepacked) return;  // written by the fused pre-addition and pack pass
   int u = blockIdx.x % per_desc;
   const int kmax = d.kmax;
   const int slabs = (kmax + kPackK - 1) / kPackK;
@@ -549,6 +550,159 @@ leaf_pack_kernel(const GemmDesc* __restrict__ descs, int a_units, int per_desc) 
             u16x8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
       }
     }
+  }
+}
+
+// Eight consecutive floats of a quadrant row, zero outside the valid extent
+// (ok: row valid; c: first column; vcols: valid columns).
+__device__ __forceinline__ void load8(const float* p, bool ok, int c, int vcols, float* v) {
+  if (ok && c + 7 < vcols) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    const float4 b = *reinterpret_cast<const float4*>(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+    v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = (ok && c + e < vcols) ? p[e] : 0.f;
+  }
+}
+
+__device__ __forceinline__ float4 load4q(const float* p, bool ok, int c, int vcols) {
+  if (ok && c + 3 < vcols) return *reinterpret_cast<const float4*>(p);
+  return make_float4((ok && c < vcols) ? p[0] : 0.f, (ok && c + 1 < vcols) ? p[1] : 0.f,
+                     (ok && c + 2 < vcols) ? p[2] : 0.f, (ok && c + 3 < vcols) ? p[3] : 0.f);
+}
+
+// Split 8 values and store them as the hi and lo 16-byte slots of a packed
+// block (BF16).
+__device__ __forceinline__ void store_packed8(char* blk, int slot, const float* v) {
+  u16x4 h0, l0, h1, l1;
+  split4<kSplitBf16>(make_float4(v[0], v[1], v[2], v[3]), 0, h0, l0);
+  split4<kSplitBf16>(make_float4(v[4], v[5], v[6], v[7]), 0, h1, l1);
+  *reinterpret_cast<u16x8*>(blk + slot) = u16x8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
+  *reinterpret_cast<u16x8*>(blk + kPackHalfBytes + slot) =
+      u16x8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
+}
+
+template <typename Node>
+__device__ __forceinline__ int find_unit_node(const Node* __restrict__ nodes, int nnodes, int b) {
+  int lo = 0, hi = nnodes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (nodes[mid].unit_begin <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Fused last-level pre-addition and pack, A side: a workgroup takes 128 rows
+// of the node's quadrants by 4 K-slabs of 32; each thread reads 8 consecutive
+// k of one row from the four quadrants, forms S1..S4 with the pre-addition
+// kernel's FP32 chains (so the values are those the unfused path would
+// store), and writes all seven leaf operands' hi/lo slots.
+__global__ void __launch_bounds__(256) preadd_pack_a_kernel(const PackNode* __restrict__ nodes, int nnodes) {
+  const PackNode& n = nodes[find_unit_node(nodes, nnodes, blockIdx.x)];
+  const PreAddNode& q = n.q;
+  const int groups = (n.max_slabs + kPackSlabsPerGroup - 1) / kPackSlabsPerGroup;
+  const int u = blockIdx.x - n.unit_begin;
+  const int t = u / groups;
+  const int s0 = (u - t * groups) * kPackSlabsPerGroup;
+  const int s1 = min(s0 + kPackSlabsPerGroup, n.max_slabs);
+  const int tid = threadIdx.x;
+  for (int s = s0; s < s1; ++s) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int qi = it * 256 + tid;
+      const int r = qi >> 2, c = qi & 3;
+      const int row = t * kPackRows + r;
+      const int col = s * kPackK + 8 * c;
+      const float* top = q.src + (int64_t)row * q.ld;
+      const float* bot = q.src + q.bot_off + (int64_t)row * q.ld;
+      float x11[8], x12[8], x21[8], x22[8];
+      load8(top + col, row < q.top_rows, col, q.left_cols, x11);
+      load8(top + q.h_c + col, row < q.top_rows, col, q.right_cols, x12);
+      load8(bot + col, row < q.bot_rows, col, q.left_cols, x21);
+      load8(bot + q.h_c + col, row < q.bot_rows, col, q.right_cols, x22);
+      float s1v[8], s2v[8], s3v[8], s4v[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        // S1 = A21 + A22; S2 = S1 - A11; S3 = A11 - A21; S4 = A12 - S2
+        s1v[e] = x21[e] + x22[e];
+        s2v[e] = s1v[e] - x11[e];
+        s3v[e] = x11[e] - x21[e];
+        s4v[e] = x12[e] - s2v[e];
+      }
+      const float* outs[7] = {x11, x12, s4v, x22, s1v, s2v, s3v};
+      const int slot = pack_slot(r, c);
+#pragma unroll
+      for (int i = 0; i < 7; ++i)
+        if (s < n.slabs[i])
+          store_packed8(reinterpret_cast<char*>(n.dst[i]) + ((int64_t)t * n.slabs[i] + s) * kPackBlockBytes,
+                        slot, outs[i]);
+    }
+  }
+}
+
+// Fused last-level pre-addition and pack, B side: a workgroup takes 128
+// columns of the node's quadrants by 4 K-slabs of 32.  Each slab of the four
+// quadrants goes through LDS (16-byte row loads, XOR-swizzled rows as in the
+// pack pass); each thread then gathers 8 consecutive k of one column from
+// all four, forms T1..T4 with the pre-addition kernel's FP32 chains and
+// writes all seven leaf operands' hi/lo slots.
+__global__ void __launch_bounds__(256) preadd_pack_b_kernel(const PackNode* __restrict__ nodes, int nnodes) {
+  __shared__ __attribute__((aligned(16))) float bt[4][kPackK * kPackRows];
+  const PackNode& n = nodes[find_unit_node(nodes, nnodes, blockIdx.x)];
+  const PreAddNode& q = n.q;
+  const int groups = (n.max_slabs + kPackSlabsPerGroup - 1) / kPackSlabsPerGroup;
+  const int u = blockIdx.x - n.unit_begin;
+  const int t = u / groups;
+  const int s0 = (u - t * groups) * kPackSlabsPerGroup;
+  const int s1 = min(s0 + kPackSlabsPerGroup, n.max_slabs);
+  const int tid = threadIdx.x;
+  for (int s = s0; s < s1; ++s) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int kr = (tid >> 5) + 8 * i, n4 = 4 * (tid & 31);
+      const int row = s * kPackK + kr, col = t * kPackRows + n4;
+      const float* top = q.src + (int64_t)row * q.ld;
+      const float* bot = q.src + q.bot_off + (int64_t)row * q.ld;
+      const int o = kr * kPackRows + (n4 ^ (8 * (kr >> 3)));
+      *reinterpret_cast<float4*>(&bt[0][o]) = load4q(top + col, row < q.top_rows, col, q.left_cols);
+      *reinterpret_cast<float4*>(&bt[1][o]) = load4q(top + q.h_c + col, row < q.top_rows, col, q.right_cols);
+      *reinterpret_cast<float4*>(&bt[2][o]) = load4q(bot + col, row < q.bot_rows, col, q.left_cols);
+      *reinterpret_cast<float4*>(&bt[3][o]) = load4q(bot + q.h_c + col, row < q.bot_rows, col, q.right_cols);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int qi = it * 256 + tid;
+      const int col = qi >> 2, c = qi & 3;
+      float x11[8], x12[8], x21[8], x22[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int o = (8 * c + e) * kPackRows + (col ^ (8 * c));
+        x11[e] = bt[0][o];
+        x12[e] = bt[1][o];
+        x21[e] = bt[2][o];
+        x22[e] = bt[3][o];
+      }
+      float t1[8], t2[8], t3[8], t4[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        // T1 = B12 - B11; T2 = B22 - T1; T3 = B22 - B12; T4 = T2 - B21
+        t1[e] = x12[e] - x11[e];
+        t2[e] = x22[e] - t1[e];
+        t3[e] = x22[e] - x12[e];
+        t4[e] = t2[e] - x21[e];
+      }
+      const float* outs[7] = {x11, x21, x22, t4, t1, t2, t3};
+      const int slot = pack_slot(col, c);
+#pragma unroll
+      for (int i = 0; i < 7; ++i)
+        if (s < n.slabs[i])
+          store_packed8(reinterpret_cast<char*>(n.dst[i]) + ((int64_t)t * n.slabs[i] + s) * kPackBlockBytes,
+                        slot, outs[i]);
+    }
+    __syncthreads();
   }
 }
 
@@ -730,6 +884,21 @@ int64_t leaf_packed_a_bytes(int64_t rows, int64_t k) {
   return (rows + kPackRows - 1) / kPackRows * ((k + kPackK - 1) / kPackK) * kPackBlockBytes;
 }
 
+int pack_node_units(const PackNode& n) {
+  return n.tiles * ((n.max_slabs + kPackSlabsPerGroup - 1) / kPackSlabsPerGroup);
+}
+
+void launch_preadd_pack(int side, const PackNode* d_nodes, int nnodes, int total_units,
+                        hipStream_t stream) {
+  if (total_units <= 0 || nnodes <= 0) return;
+  dim3 grid(total_units), block(256);
+  if (side == 0)
+    hipLaunchKernelGGL(preadd_pack_a_kernel, grid, block, 0, stream, d_nodes, nnodes);
+  else
+    hipLaunchKernelGGL(preadd_pack_b_kernel, grid, block, 0, stream, d_nodes, nnodes);
+  FASTMM_HIP(hipGetLastError());
+}
+
 void launch_leaf_packed(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
                         hipStream_t stream, int xcd_chunk, const LeafExtents& ext) {
   if (total_tiles <= 0) return;
@@ -763,7 +932,7 @@ void launch_leaf_packed(int tile, const GemmDesc* d_descs, int ndesc, int total_
   const int64_t b_units = (int64_t)((ext.max_c_cols + kPackRows - 1) / kPackRows) * groups;
   const int64_t per_desc = a_units + b_units;
   if (per_desc * ndesc > INT32_MAX) throw Error(kNotSupported, "pack launch too large");
-  if (per_desc > 0) {
+  if (per_desc > 0 && ext.any_unpacked) {
     dim3 grid((unsigned)(per_desc * ndesc)), block(256);
     if (fp16) {
       if (vec)

@@ -164,3 +164,24 @@ def test_fp16x3_host_operands(fastmm):
     e = checks.rel_frob(Ch.numpy(), classic.gemm(A, B))
     say(f"  fp16x3 host operands: rel_frob={e:.3e}")
     assert e <= 2e-6
+
+
+@pytest.mark.parametrize("m,k,n,depth", [(1024, 1024, 1024, 1), (1000, 900, 1100, 2), (700, 645, 1021, 3),
+                                         (2048, 1536, 1792, 2)])
+def test_bf16x3_fused_pack_matches_two_passes(fastmm, monkeypatch, m, k, n, depth):
+    # Split-BF16 leaves at depth >= 1: the last level's pre-additions and the
+    # pack pass run as one fused pass; it forms the same FP32 sums as the
+    # pre-addition kernel, so the result equals the two-pass one bit for bit.
+    A, B = uniform(3601 + m, m, k), uniform(3602 + n, k, n)
+    dA, dB = dev(A), dev(B)
+    C1, C2 = empty_dev(m, n), empty_dev(m, n)
+    monkeypatch.delenv("FASTMM_FUSED_PACK", raising=False)
+    fastmm.gemm(m, n, k, dA, dB, C1, depth=depth, leaf=1, tile=BF)
+    fused_launches = fastmm.get_stats()["launches"]
+    monkeypatch.setenv("FASTMM_FUSED_PACK", "0")
+    fastmm.gemm(m, n, k, dA, dB, C2, depth=depth, leaf=1, tile=BF)
+    two_pass_launches = fastmm.get_stats()["launches"]
+    say(f"  fused pack {m}x{k}x{n} depth {depth}: launches {fused_launches} vs {two_pass_launches}")
+    assert np.array_equal(host(C1), host(C2))
+    assert fused_launches < two_pass_launches
+    assert checks.rel_frob(host(C1), classic.gemm(A, B)) <= 2e-4
