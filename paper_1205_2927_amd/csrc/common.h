@@ -70,6 +70,9 @@ struct PreAddNode {
 struct PackNode {
   PreAddNode q;
   void* dst[7];         // packed operand of leaf i of the node
+  int32_t* e[7];        // scaled FP16 only: the leaf's e_A (A side) or e_B (B side)
+  int32_t rows[7];      // its valid rows of A (A side) or columns of B (B side)
+  int32_t kmax[7];      // its reduction length
   int32_t slabs[7];     // its K-slabs of 32: ceil(kmax / 32)
   int32_t tiles;        // 128-row (A) or 128-column (B) tiles of every output
   int32_t max_slabs;    // largest of slabs[]
@@ -268,9 +271,18 @@ struct LeafExtents {
 };
 // Workgroups of a fused pre-addition and pack node (4 K-slabs per workgroup).
 int pack_node_units(const PackNode& n);
-// side 0: A operands, 1: B operands; nodes with unit_begin prefixes.
-void launch_preadd_pack(int side, const PackNode* d_nodes, int nnodes, int total_units,
+// side 0: A operands, 1: B operands; nodes with unit_begin prefixes.  fp16:
+// scaled split FP16 (the node's scale exponents must be in place).
+void launch_preadd_pack(int side, const PackNode* d_nodes, int nnodes, int total_units, bool fp16,
                         hipStream_t stream);
+// Scaled FP16 leaves: the fused nodes' scale exponents, from the parent
+// quadrants (rows of the seven A-side operands; column maxima of the seven
+// B-side operands in 256-row parts, then reduced per leaf over d_descs).
+// max_rows / max_kdim: largest node rows (A side) / reduction extent (B
+// side); max_cols: largest node columns (B side) and leaf b_cols.
+void launch_preadd_scale(const PackNode* d_a, int na, const PackNode* d_b, int nb, int max_rows,
+                         int max_cols, int max_kdim, const GemmDesc* d_descs, int ndesc,
+                         hipStream_t stream);
 // Bytes of the FP16 scale exponents and scratch of a rows x k by k x cols leaf.
 int64_t leaf_scale_bytes(int64_t rows, int64_t cols, int64_t k);
 // Bytes of the packed operands of a rows x k by k x cols leaf (A's part first).

@@ -246,7 +246,9 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     size_t t_off = 0;  // floats into p.b_tree
     // Fused pre-addition and pack (split-BF16 leaves, depth >= 1, no shared
     // B tree): nodes of the last level whose quadrants allow 16-byte access.
-    const bool fuse = fuse_allowed && p.tile == kTileBf16x3 && d >= 1 && !p.b_tree;
+    const bool fuse = fuse_allowed && (p.tile == kTileBf16x3 || p.tile == kTileFp16x3) && d >= 1 &&
+                      !p.b_tree;
+    const int fmt = p.tile == kTileFp16x3 ? 1 : 0;
     struct Fused {
       int64_t x;
       PreAddNode a, b;
@@ -355,12 +357,17 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
         g.prepacked = 1;
         na.dst[i] = g.pa;
         nb.dst[i] = g.pb;
+        na.e[i] = g.ea;
+        nb.e[i] = g.eb;
+        na.rows[i] = g.a_rows;
+        nb.rows[i] = g.b_cols;
+        na.kmax[i] = nb.kmax[i] = g.kmax;
         na.slabs[i] = nb.slabs[i] = (g.kmax + 31) / 32;
         na.max_slabs = std::max(na.max_slabs, na.slabs[i]);
       }
       nb.max_slabs = na.max_slabs;
-      s.pack[0].push_back(na);
-      s.pack[1].push_back(nb);
+      s.pack[fmt][0].push_back(na);
+      s.pack[fmt][1].push_back(nb);
       // 7 packed outputs instead of 4 FP32 ones (same bytes per element)
       const Dims& c = dims[d];
       s.add_bytes += 12.0 * c.m * c.k + 12.0 * c.k * c.n;
@@ -410,15 +417,16 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     }
     if (b > INT32_MAX) throw Error(kNotSupported, "post-addition launch too large");
   }
-  for (int side = 0; side < 2; ++side) {
-    int64_t u = 0;
-    for (auto& n : s.pack[side]) {
-      n.unit_begin = (int32_t)u;
-      u += pack_node_units(n);
+  for (int fmt = 0; fmt < 2; ++fmt)
+    for (int side = 0; side < 2; ++side) {
+      int64_t u = 0;
+      for (auto& n : s.pack[fmt][side]) {
+        n.unit_begin = (int32_t)u;
+        u += pack_node_units(n);
+      }
+      if (u > INT32_MAX) throw Error(kNotSupported, "fused pack launch too large");
+      s.pack_units[fmt][side] = (int)u;
     }
-    if (u > INT32_MAX) throw Error(kNotSupported, "fused pack launch too large");
-    s.pack_units[side] = (int)u;
-  }
   s.leaf_tiles_total.assign(kNumTiles, 0);
   for (int t = 0; t < kNumTiles; ++t) {
     s.vec_leaf[t] = true;
@@ -458,7 +466,8 @@ size_t schedule_desc_bytes(const Schedule& s) {
     b += align_up(s.post[l].size() * sizeof(PostAddNode), 256);
   }
   for (int t = 0; t < kNumTiles; ++t) b += align_up(s.leaf[t].size() * sizeof(GemmDesc), 256);
-  for (int side = 0; side < 2; ++side) b += align_up(s.pack[side].size() * sizeof(PackNode), 256);
+  for (int fmt = 0; fmt < 2; ++fmt)
+    for (int side = 0; side < 2; ++side) b += align_up(s.pack[fmt][side].size() * sizeof(PackNode), 256);
   return b;
 }
 
@@ -492,9 +501,10 @@ void upload_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host) {
   }
   for (int t = 0; t < kNumTiles; ++t)
     s.d_leaf[t] = reinterpret_cast<const GemmDesc*>(put(s.leaf[t].data(), s.leaf[t].size() * sizeof(GemmDesc)));
-  for (int side = 0; side < 2; ++side)
-    s.d_pack[side] = reinterpret_cast<const PackNode*>(
-        put(s.pack[side].data(), s.pack[side].size() * sizeof(PackNode)));
+  for (int fmt = 0; fmt < 2; ++fmt)
+    for (int side = 0; side < 2; ++side)
+      s.d_pack[fmt][side] = reinterpret_cast<const PackNode*>(
+          put(s.pack[fmt][side].data(), s.pack[fmt][side].size() * sizeof(PackNode)));
   if (off) FASTMM_HIP(hipMemcpyAsync(desc_dev, desc_host, off, hipMemcpyHostToDevice, L.stream));
 }
 
@@ -508,11 +518,27 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
     if (ba) { launch_preadd(0, s.d_preA[l], (int)s.preA[l].size(), ba, s.vec_preA[l], L.stream); ++launches; }
     if (bb) { launch_preadd(1, s.d_preB[l], (int)s.preB[l].size(), bb, s.vec_preB[l], L.stream); ++launches; }
   }
-  for (int side = 0; side < 2; ++side)
-    if (s.pack_units[side] > 0) {
-      launch_preadd_pack(side, s.d_pack[side], (int)s.pack[side].size(), s.pack_units[side], L.stream);
-      ++launches;
+  // Fused last-level pre-addition and pack of split-precision leaves; the
+  // scaled FP16 form first takes its scale exponents from the same quadrants.
+  if (!s.pack[1][0].empty()) {
+    int max_rows = 0, max_cols = 0, max_kdim = 0;
+    for (const auto& n : s.pack[1][0]) max_rows = std::max(max_rows, (int)n.q.h_r);
+    for (const auto& n : s.pack[1][1]) {
+      max_cols = std::max(max_cols, (int)n.q.h_c);
+      max_kdim = std::max(max_kdim, (int)n.q.h_r);
     }
+    launch_preadd_scale(s.d_pack[1][0], (int)s.pack[1][0].size(), s.d_pack[1][1],
+                        (int)s.pack[1][1].size(), max_rows, max_cols, max_kdim, s.d_leaf[kTileFp16x3],
+                        (int)s.leaf[kTileFp16x3].size(), L.stream);
+    launches += 3;
+  }
+  for (int fmt = 0; fmt < 2; ++fmt)
+    for (int side = 0; side < 2; ++side)
+      if (s.pack_units[fmt][side] > 0) {
+        launch_preadd_pack(side, s.d_pack[fmt][side], (int)s.pack[fmt][side].size(),
+                           s.pack_units[fmt][side], fmt == 1, L.stream);
+        ++launches;
+      }
   if (profile) FASTMM_HIP(hipEventRecord(L.ev[2], L.stream));
   if (leaf_begin) FASTMM_HIP(hipEventRecord(leaf_begin, L.stream));
   for (int t = 0; t < kNumTiles; ++t) {

@@ -83,11 +83,12 @@ struct Schedule {
   std::vector<const PreAddNode*> d_preA, d_preB;
   std::vector<const PostAddNode*> d_post;
   const GemmDesc* d_leaf[kNumTiles] = {};
-  // Split-BF16 leaves: fused last-level pre-addition and pack nodes (A, B),
-  // their workgroup totals and device copies.
-  std::vector<PackNode> pack[2];
-  int pack_units[2] = {0, 0};
-  const PackNode* d_pack[2] = {};
+  // Split-precision leaves: fused last-level pre-addition and pack nodes,
+  // [format: 0 split BF16, 1 scaled split FP16][side: 0 A, 1 B], their
+  // workgroup totals and device copies.
+  std::vector<PackNode> pack[2][2];
+  int pack_units[2][2] = {};
+  const PackNode* d_pack[2][2] = {};
   bool vec_leaf[kNumTiles] = {};  // set in build_schedule
   int xcd_chunk[kNumTiles] = {};  // leaf launch tile -> XCD mapping (leaf_tile_of_block)
   bool persistent = false;        // leaf launches take tiles from L.leaf_queue

@@ -135,6 +135,7 @@ template <bool VEC>
 __global__ void __launch_bounds__(256)
 leaf_scale_kernel(const GemmDesc* __restrict__ descs, int a_blocks, int per_desc) {
   const GemmDesc& d = descs[blockIdx.x / per_desc];
+  if (d.prepacked) return;  // scaled by the fused pass
   const int blk = blockIdx.x % per_desc;
   const int kmax = d.kmax;
   const int tid = threadIdx.x;
@@ -185,10 +186,12 @@ leaf_scale_kernel(const GemmDesc* __restrict__ descs, int a_blocks, int per_desc
   }
 }
 
-// e_B[c] from the partial column maxima of leaf_scale_kernel.
+// e_B[c] from the partial column maxima of leaf_scale_kernel (descriptors
+// with prepacked == which; the fused pass writes its own partials).
 __global__ void __launch_bounds__(256)
-leaf_scale_b_kernel(const GemmDesc* __restrict__ descs, int per_desc) {
+leaf_scale_b_kernel(const GemmDesc* __restrict__ descs, int per_desc, int which) {
   const GemmDesc& d = descs[blockIdx.x / per_desc];
+  if (d.prepacked != which) return;
   const int c = (blockIdx.x % per_desc) * 256 + threadIdx.x;
   if (c >= d.b_cols) return;
   const int parts = (d.kmax + kScaleRowsPerPart - 1) / kScaleRowsPerPart;
@@ -573,12 +576,13 @@ __device__ __forceinline__ float4 load4q(const float* p, bool ok, int c, int vco
                      (ok && c + 2 < vcols) ? p[2] : 0.f, (ok && c + 3 < vcols) ? p[3] : 0.f);
 }
 
-// Split 8 values and store them as the hi and lo 16-byte slots of a packed
-// block (BF16).
-__device__ __forceinline__ void store_packed8(char* blk, int slot, const float* v) {
+// Split 8 values (FP16: scaled by 2^-e) and store them as the hi and lo
+// 16-byte slots of a packed block.
+template <int FMT>
+__device__ __forceinline__ void store_packed8(char* blk, int slot, const float* v, int e) {
   u16x4 h0, l0, h1, l1;
-  split4<kSplitBf16>(make_float4(v[0], v[1], v[2], v[3]), 0, h0, l0);
-  split4<kSplitBf16>(make_float4(v[4], v[5], v[6], v[7]), 0, h1, l1);
+  split4<FMT>(make_float4(v[0], v[1], v[2], v[3]), e, h0, l0);
+  split4<FMT>(make_float4(v[4], v[5], v[6], v[7]), e, h1, l1);
   *reinterpret_cast<u16x8*>(blk + slot) = u16x8{h0[0], h0[1], h0[2], h0[3], h1[0], h1[1], h1[2], h1[3]};
   *reinterpret_cast<u16x8*>(blk + kPackHalfBytes + slot) =
       u16x8{l0[0], l0[1], l0[2], l0[3], l1[0], l1[1], l1[2], l1[3]};
@@ -599,6 +603,7 @@ __device__ __forceinline__ int find_unit_node(const Node* __restrict__ nodes, in
 // k of one row from the four quadrants, forms S1..S4 with the pre-addition
 // kernel's FP32 chains (so the values are those the unfused path would
 // store), and writes all seven leaf operands' hi/lo slots.
+template <int FMT>
 __global__ void __launch_bounds__(256) preadd_pack_a_kernel(const PackNode* __restrict__ nodes, int nnodes) {
   const PackNode& n = nodes[find_unit_node(nodes, nnodes, blockIdx.x)];
   const PreAddNode& q = n.q;
@@ -635,9 +640,11 @@ __global__ void __launch_bounds__(256) preadd_pack_a_kernel(const PackNode* __re
       const int slot = pack_slot(r, c);
 #pragma unroll
       for (int i = 0; i < 7; ++i)
-        if (s < n.slabs[i])
-          store_packed8(reinterpret_cast<char*>(n.dst[i]) + ((int64_t)t * n.slabs[i] + s) * kPackBlockBytes,
-                        slot, outs[i]);
+        if (s < n.slabs[i]) {
+          const int e = (FMT == kSplitFp16 && row < n.rows[i]) ? n.e[i][row] : 0;
+          store_packed8<FMT>(reinterpret_cast<char*>(n.dst[i]) + ((int64_t)t * n.slabs[i] + s) * kPackBlockBytes,
+                             slot, outs[i], e);
+        }
     }
   }
 }
@@ -648,6 +655,7 @@ __global__ void __launch_bounds__(256) preadd_pack_a_kernel(const PackNode* __re
 // pack pass); each thread then gathers 8 consecutive k of one column from
 // all four, forms T1..T4 with the pre-addition kernel's FP32 chains and
 // writes all seven leaf operands' hi/lo slots.
+template <int FMT>
 __global__ void __launch_bounds__(256) preadd_pack_b_kernel(const PackNode* __restrict__ nodes, int nnodes) {
   __shared__ __attribute__((aligned(16))) float bt[4][kPackK * kPackRows];
   const PackNode& n = nodes[find_unit_node(nodes, nnodes, blockIdx.x)];
@@ -696,14 +704,90 @@ __global__ void __launch_bounds__(256) preadd_pack_b_kernel(const PackNode* __re
       }
       const float* outs[7] = {x11, x21, x22, t4, t1, t2, t3};
       const int slot = pack_slot(col, c);
+      const int gcol = t * kPackRows + col;
 #pragma unroll
       for (int i = 0; i < 7; ++i)
-        if (s < n.slabs[i])
-          store_packed8(reinterpret_cast<char*>(n.dst[i]) + ((int64_t)t * n.slabs[i] + s) * kPackBlockBytes,
-                        slot, outs[i]);
+        if (s < n.slabs[i]) {
+          const int e = (FMT == kSplitFp16 && gcol < n.rows[i]) ? n.e[i][gcol] : 0;
+          store_packed8<FMT>(reinterpret_cast<char*>(n.dst[i]) + ((int64_t)t * n.slabs[i] + s) * kPackBlockBytes,
+                             slot, outs[i], e);
+        }
     }
     __syncthreads();
   }
+}
+
+// Scale exponents of the fused nodes (scaled FP16), A side: one wavefront
+// per row of a node streams the row of all four quadrants (16-byte loads),
+// forms S1..S4 as the pre-addition kernel does, and keeps the largest
+// magnitude of each of the seven leaf operands over that leaf's reduction
+// length; e_A of leaf i for the row follows.
+__global__ void __launch_bounds__(256) preadd_scale_a_kernel(const PackNode* __restrict__ nodes, int per_node) {
+  const PackNode& n = nodes[blockIdx.x / per_node];
+  const PreAddNode& q = n.q;
+  const int lane = threadIdx.x & 63;
+  const int row = (blockIdx.x % per_node) * 4 + (threadIdx.x >> 6);
+  if (row >= q.h_r) return;
+  const float* top = q.src + (int64_t)row * q.ld;
+  const float* bot = q.src + q.bot_off + (int64_t)row * q.ld;
+  const bool rt = row < q.top_rows, rb = row < q.bot_rows;
+  float m[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int k = 4 * lane; k < q.h_c; k += 256) {
+    const float4 a11 = load4q(top + k, rt, k, q.left_cols);
+    const float4 a12 = load4q(top + q.h_c + k, rt, k, q.right_cols);
+    const float4 a21 = load4q(bot + k, rb, k, q.left_cols);
+    const float4 a22 = load4q(bot + q.h_c + k, rb, k, q.right_cols);
+    const float x11[4] = {a11.x, a11.y, a11.z, a11.w}, x12[4] = {a12.x, a12.y, a12.z, a12.w};
+    const float x21[4] = {a21.x, a21.y, a21.z, a21.w}, x22[4] = {a22.x, a22.y, a22.z, a22.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float s1 = x21[e] + x22[e], s2 = s1 - x11[e], s3 = x11[e] - x21[e], s4 = x12[e] - s2;
+      const float v[7] = {x11[e], x12[e], s4, x22[e], s1, s2, s3};
+#pragma unroll
+      for (int i = 0; i < 7; ++i)
+        if (k + e < n.kmax[i]) m[i] = fmaxf(m[i], fabsf(v[i]));
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    const float mx = wave_max(m[i]);
+    if (lane == 0 && row < n.rows[i]) n.e[i][row] = scale_exponent(mx);
+  }
+}
+
+// B side: one thread per column of a node, over one 256-row part of the
+// reduction; the seven leaf operands' partial column maxima go to each
+// leaf's scratch after e_B (as leaf_scale_kernel's do) and
+// leaf_scale_b_kernel reduces them.
+__global__ void __launch_bounds__(256) preadd_scale_b_kernel(const PackNode* __restrict__ nodes, int per_node,
+                                                             int col_blocks) {
+  const PackNode& n = nodes[blockIdx.x / per_node];
+  const PreAddNode& q = n.q;
+  const int u = blockIdx.x % per_node;
+  const int p = u / col_blocks;
+  const int col = (u - p * col_blocks) * 256 + threadIdx.x;
+  if (col >= q.h_c) return;
+  const int k0 = p * kScaleRowsPerPart;
+  const int k1 = min(q.h_r, k0 + kScaleRowsPerPart);
+  if (k0 >= k1) return;
+  const bool cl = col < q.left_cols, cr = col < q.right_cols;
+  float m[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int k = k0; k < k1; ++k) {
+    const float* top = q.src + (int64_t)k * q.ld;
+    const float* bot = q.src + q.bot_off + (int64_t)k * q.ld;
+    const bool rt = k < q.top_rows, rb = k < q.bot_rows;
+    const float x11 = (rt && cl) ? top[col] : 0.f, x12 = (rt && cr) ? top[q.h_c + col] : 0.f;
+    const float x21 = (rb && cl) ? bot[col] : 0.f, x22 = (rb && cr) ? bot[q.h_c + col] : 0.f;
+    const float t1 = x12 - x11, t2 = x22 - t1, t3 = x22 - x12, t4 = t2 - x21;
+    const float v[7] = {x11, x21, x22, t4, t1, t2, t3};
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+      if (k < n.kmax[i]) m[i] = fmaxf(m[i], fabsf(v[i]));
+  }
+#pragma unroll
+  for (int i = 0; i < 7; ++i)
+    if (col < n.rows[i] && k0 < n.kmax[i])
+      reinterpret_cast<float*>(n.e[i] + n.rows[i])[(int64_t)p * n.rows[i] + col] = m[i];
 }
 
 // Leaf on packed operands: TM x TN tiles on WGM x WGN wavefronts, K-slabs
@@ -888,15 +972,42 @@ int pack_node_units(const PackNode& n) {
   return n.tiles * ((n.max_slabs + kPackSlabsPerGroup - 1) / kPackSlabsPerGroup);
 }
 
-void launch_preadd_pack(int side, const PackNode* d_nodes, int nnodes, int total_units,
+void launch_preadd_pack(int side, const PackNode* d_nodes, int nnodes, int total_units, bool fp16,
                         hipStream_t stream) {
   if (total_units <= 0 || nnodes <= 0) return;
   dim3 grid(total_units), block(256);
-  if (side == 0)
-    hipLaunchKernelGGL(preadd_pack_a_kernel, grid, block, 0, stream, d_nodes, nnodes);
-  else
-    hipLaunchKernelGGL(preadd_pack_b_kernel, grid, block, 0, stream, d_nodes, nnodes);
+  if (side == 0) {
+    if (fp16) hipLaunchKernelGGL(preadd_pack_a_kernel<kSplitFp16>, grid, block, 0, stream, d_nodes, nnodes);
+    else hipLaunchKernelGGL(preadd_pack_a_kernel<kSplitBf16>, grid, block, 0, stream, d_nodes, nnodes);
+  } else {
+    if (fp16) hipLaunchKernelGGL(preadd_pack_b_kernel<kSplitFp16>, grid, block, 0, stream, d_nodes, nnodes);
+    else hipLaunchKernelGGL(preadd_pack_b_kernel<kSplitBf16>, grid, block, 0, stream, d_nodes, nnodes);
+  }
   FASTMM_HIP(hipGetLastError());
+}
+
+void launch_preadd_scale(const PackNode* d_a, int na, const PackNode* d_b, int nb, int max_rows,
+                         int max_cols, int max_kdim, const GemmDesc* d_descs, int ndesc,
+                         hipStream_t stream) {
+  if (na > 0 && max_rows > 0) {
+    const int64_t per_node = (max_rows + 3) / 4;
+    if (per_node * na > INT32_MAX) throw Error(kNotSupported, "scale launch too large");
+    hipLaunchKernelGGL(preadd_scale_a_kernel, dim3((unsigned)(per_node * na)), dim3(256), 0, stream, d_a,
+                       (int)per_node);
+    FASTMM_HIP(hipGetLastError());
+  }
+  if (nb > 0 && max_cols > 0 && max_kdim > 0) {
+    const int64_t col_blocks = (max_cols + 255) / 256;
+    const int64_t per_node = col_blocks * ((max_kdim + kScaleRowsPerPart - 1) / kScaleRowsPerPart);
+    if (per_node * nb > INT32_MAX || col_blocks * ndesc > INT32_MAX)
+      throw Error(kNotSupported, "scale launch too large");
+    hipLaunchKernelGGL(preadd_scale_b_kernel, dim3((unsigned)(per_node * nb)), dim3(256), 0, stream, d_b,
+                       (int)per_node, (int)col_blocks);
+    FASTMM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(leaf_scale_b_kernel, dim3((unsigned)(col_blocks * ndesc)), dim3(256), 0, stream,
+                       d_descs, (int)col_blocks, 1);
+    FASTMM_HIP(hipGetLastError());
+  }
 }
 
 void launch_leaf_packed(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
@@ -905,7 +1016,7 @@ void launch_leaf_packed(int tile, const GemmDesc* d_descs, int ndesc, int total_
   const bool fp16 = tile == kTileFp16x3;
   if (!fp16 && tile != kTileBf16x3) throw Error(kInvalidValue, "not a split-precision tile");
   // 1. FP16 only: scale exponents of the valid rows of A and columns of B.
-  if (fp16) {
+  if (fp16 && ext.any_unpacked) {
     const int a_blocks = (ext.max_a_rows + kScaleRowsPerBlock - 1) / kScaleRowsPerBlock;
     const int64_t parts = (ext.max_kmax + kScaleRowsPerPart - 1) / kScaleRowsPerPart;
     const int64_t col_blocks = (ext.max_b_cols + kScaleColsPerBlock - 1) / kScaleColsPerBlock;
@@ -922,7 +1033,7 @@ void launch_leaf_packed(int tile, const GemmDesc* d_descs, int ndesc, int total_
     }
     if (col_blocks > 0) {
       dim3 grid((unsigned)(col_blocks * ndesc)), block(256);
-      hipLaunchKernelGGL(leaf_scale_b_kernel, grid, block, 0, stream, d_descs, (int)col_blocks);
+      hipLaunchKernelGGL(leaf_scale_b_kernel, grid, block, 0, stream, d_descs, (int)col_blocks, 0);
       FASTMM_HIP(hipGetLastError());
     }
   }

@@ -166,22 +166,31 @@ def test_fp16x3_host_operands(fastmm):
     assert e <= 2e-6
 
 
+@pytest.mark.parametrize("tile", [BF, FP])
 @pytest.mark.parametrize("m,k,n,depth", [(1024, 1024, 1024, 1), (1000, 900, 1100, 2), (700, 645, 1021, 3),
                                          (2048, 1536, 1792, 2)])
-def test_bf16x3_fused_pack_matches_two_passes(fastmm, monkeypatch, m, k, n, depth):
-    # Split-BF16 leaves at depth >= 1: the last level's pre-additions and the
-    # pack pass run as one fused pass; it forms the same FP32 sums as the
-    # pre-addition kernel, so the result equals the two-pass one bit for bit.
+def test_split_fused_pack_matches_two_passes(fastmm, monkeypatch, m, k, n, depth, tile):
+    # Split-precision leaves at depth >= 1: the last level's pre-additions and
+    # the pack pass (for FP16 also the scale pass) run fused, straight from
+    # the parent quadrants; they form the same FP32 sums as the pre-addition
+    # kernel and the same maxima, so the result equals the separate passes'
+    # bit for bit.
     A, B = uniform(3601 + m, m, k), uniform(3602 + n, k, n)
+    if tile == FP:  # rows and columns of very different magnitude exercise the scales
+        A = _pow2_scaled(A, row_exp=synthgen.int_range(3603, m, 1, -30, 30)[:, 0].astype(np.int64))
+        B = _pow2_scaled(B, col_exp=synthgen.int_range(3604, 1, n, -30, 30)[0].astype(np.int64))
     dA, dB = dev(A), dev(B)
     C1, C2 = empty_dev(m, n), empty_dev(m, n)
     monkeypatch.delenv("FASTMM_FUSED_PACK", raising=False)
-    fastmm.gemm(m, n, k, dA, dB, C1, depth=depth, leaf=1, tile=BF)
+    fastmm.gemm(m, n, k, dA, dB, C1, depth=depth, leaf=1, tile=tile)
     fused_launches = fastmm.get_stats()["launches"]
     monkeypatch.setenv("FASTMM_FUSED_PACK", "0")
-    fastmm.gemm(m, n, k, dA, dB, C2, depth=depth, leaf=1, tile=BF)
+    fastmm.gemm(m, n, k, dA, dB, C2, depth=depth, leaf=1, tile=tile)
     two_pass_launches = fastmm.get_stats()["launches"]
-    say(f"  fused pack {m}x{k}x{n} depth {depth}: launches {fused_launches} vs {two_pass_launches}")
+    say(f"  fused pack tile {tile} {m}x{k}x{n} depth {depth}: launches {fused_launches} vs {two_pass_launches}")
     assert np.array_equal(host(C1), host(C2))
-    assert fused_launches < two_pass_launches
-    assert checks.rel_frob(host(C1), classic.gemm(A, B)) <= 2e-4
+    if tile == BF:
+        assert fused_launches < two_pass_launches
+    assert np.isfinite(host(C1)).all()
+    if tile == BF:
+        assert checks.rel_frob(host(C1), classic.gemm(A, B)) <= 2e-4
