@@ -29,9 +29,13 @@
 //   extra 2^11 factor on lo, and the second accumulator it needs, buy
 //   nothing here, and one FP32 accumulator holds all three terms.
 //
-// Two kernels run these forms.  The level-wise engine packs every leaf's
-// operands once (leaf_pack_kernel) and runs leaf_packed_kernel, 256x256 tiles
-// that copy pre-split slabs straight into LDS.  The classic recursion, which
+// The level-wise engine packs every leaf's operands once (leaf_pack_kernel,
+// after leaf_scale_kernel for FP16) and runs leaf_packed_kernel, 256x256
+// tiles that copy pre-split slabs straight into LDS.  At the last level of a
+// recursion the packed operands come instead straight from the parent
+// quadrants (preadd_pack_a/b_kernel, after preadd_scale_a/b_kernel for
+// FP16), which form S1..S4 / T1..T4 as the pre-addition kernel does and
+// write all seven leaf operands of a node packed.  The classic recursion, which
 // has no workspace for packed operands, runs split BF16 on
 // leaf_split_kernel: 128x128 tiles (4 wavefronts of 64x64, the FP32 leaf's
 // descriptors and XCD-aware walk) with K-slabs of 32 whose FP32 loads
