@@ -617,6 +617,16 @@ __global__ void __launch_bounds__(256) preadd_pack_a_kernel(const PackNode* __re
   const int s0 = (u - t * groups) * kPackSlabsPerGroup;
   const int s1 = min(s0 + kPackSlabsPerGroup, n.max_slabs);
   const int tid = threadIdx.x;
+  // FP16: the exponents of the thread's two rows, for all seven operands.
+  int ex[2][7] = {};
+  if constexpr (FMT == kSplitFp16) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int row = t * kPackRows + ((it * 256 + tid) >> 2);
+#pragma unroll
+      for (int i = 0; i < 7; ++i) ex[it][i] = row < n.rows[i] ? n.e[i][row] : 0;
+    }
+  }
   for (int s = s0; s < s1; ++s) {
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
@@ -645,9 +655,8 @@ __global__ void __launch_bounds__(256) preadd_pack_a_kernel(const PackNode* __re
 #pragma unroll
       for (int i = 0; i < 7; ++i)
         if (s < n.slabs[i]) {
-          const int e = (FMT == kSplitFp16 && row < n.rows[i]) ? n.e[i][row] : 0;
           store_packed8<FMT>(reinterpret_cast<char*>(n.dst[i]) + ((int64_t)t * n.slabs[i] + s) * kPackBlockBytes,
-                             slot, outs[i], e);
+                             slot, outs[i], ex[it][i]);
         }
     }
   }
@@ -670,6 +679,16 @@ __global__ void __launch_bounds__(256) preadd_pack_b_kernel(const PackNode* __re
   const int s0 = (u - t * groups) * kPackSlabsPerGroup;
   const int s1 = min(s0 + kPackSlabsPerGroup, n.max_slabs);
   const int tid = threadIdx.x;
+  // FP16: the exponents of the thread's two columns, for all seven operands.
+  int ex[2][7] = {};
+  if constexpr (FMT == kSplitFp16) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int gcol = t * kPackRows + ((it * 256 + tid) >> 2);
+#pragma unroll
+      for (int i = 0; i < 7; ++i) ex[it][i] = gcol < n.rows[i] ? n.e[i][gcol] : 0;
+    }
+  }
   for (int s = s0; s < s1; ++s) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -708,14 +727,11 @@ __global__ void __launch_bounds__(256) preadd_pack_b_kernel(const PackNode* __re
       }
       const float* outs[7] = {x11, x21, x22, t4, t1, t2, t3};
       const int slot = pack_slot(col, c);
-      const int gcol = t * kPackRows + col;
 #pragma unroll
       for (int i = 0; i < 7; ++i)
-        if (s < n.slabs[i]) {
-          const int e = (FMT == kSplitFp16 && gcol < n.rows[i]) ? n.e[i][gcol] : 0;
+        if (s < n.slabs[i])
           store_packed8<FMT>(reinterpret_cast<char*>(n.dst[i]) + ((int64_t)t * n.slabs[i] + s) * kPackBlockBytes,
-                             slot, outs[i], e);
-        }
+                             slot, outs[i], ex[it][i]);
     }
     __syncthreads();
   }
