@@ -303,8 +303,11 @@ def main():
                   and n == 19456 and args.tile == 0 and args.leaf == 1024)
     split = SPLIT_FORMS.get(args.tile)
     peak = PEAK_16BIT_TFLOPS / 3 if split else PEAK_FP32_TFLOPS
-    roofline = {"bound": "mfma",
-                "kernel": split[1] if split else "leaf_gemm_kernel<128,128,16,2,2> (grouped leaves)",
+    if split and st["depth"] >= 1:  # the scale and pack passes run fused with the last pre-additions
+        kernel = f"leaf_packed_kernel<{args.tile - 8},256,256,4,2>"
+    else:
+        kernel = split[1] if split else "leaf_gemm_kernel<128,128,16,2,2> (grouped leaves)"
+    roofline = {"bound": "mfma", "kernel": kernel,
                 "achieved": leaf_tflops, "peak": peak, "unit": "TFLOP/s", "frac": leaf_tflops / peak,
                 "traffic": TRAFFIC_BYTES_PER_LAUNCH if traffic_ok else None,
                 "flops_per_launch": flops_launch, "avg_launch_ms": avg_launch,
