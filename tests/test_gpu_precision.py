@@ -194,3 +194,34 @@ def test_split_fused_pack_matches_two_passes(fastmm, monkeypatch, m, k, n, depth
     assert np.isfinite(host(C1)).all()
     if tile == BF:
         assert checks.rel_frob(host(C1), classic.gemm(A, B)) <= 2e-4
+
+
+@pytest.mark.parametrize("tile", [BF, FP])
+def test_split_depth_first_fallback_bitwise(fastmm, monkeypatch, tile):
+    # A workspace cap below the level-wise need (packed operands and scale
+    # exponents included): the top level runs depth first, each sub-product
+    # with its own fused last level; same tree and arithmetic, so the result
+    # is bit for bit the level-wise one.
+    import torch
+    n, depth = 1024, 3
+    A, B = dev(uniform(3701, n, n)), dev(uniform(3702, n, n))
+    C0 = empty_dev(n, n)
+    monkeypatch.delenv("FASTMM_WORKSPACE_LIMIT", raising=False)
+    fastmm.gemm(n, n, n, A, B, C0, depth=depth, leaf=1, tile=tile)
+    ref = host(C0)
+    bfs = fastmm.get_stats()["launches"]
+    done = 0
+    for limit in [120_000_000, 80_000_000, 60_000_000, 45_000_000]:
+        monkeypatch.setenv("FASTMM_WORKSPACE_LIMIT", str(limit))
+        C = torch.full((n, n), 7.0, device="cuda")
+        rc = fastmm.gemm_raw(n, n, n, A.data_ptr(), n, B.data_ptr(), n, C.data_ptr(), n, depth, 1, tile)
+        if rc == fastmm.ERROR_OUT_OF_MEMORY:
+            assert torch.all(C == 7.0).item()
+            break
+        assert rc == fastmm.SUCCESS, fastmm.last_error()
+        st = fastmm.get_stats()
+        say(f"  tile {tile} limit {limit}: launches {st['launches']} (level-wise {bfs})")
+        assert np.array_equal(host(C), ref)
+        if st["launches"] > bfs:
+            done += 1
+    assert done >= 1
