@@ -29,8 +29,8 @@ PEAK_16BIT_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 matrix peak
 # 16-bit products per FP32 product, so its FP32-equivalent ceiling is a third
 # of the 16-bit peak; its leaf phase is a pack pass (and for FP16 a scale
 # pass) plus the leaf kernel.
-SPLIT_FORMS = {8: ("bf16x3", "leaf_pack_kernel<0> + leaf_packed_kernel<0,256,256,4,2>"),
-               9: ("fp16x3", "leaf_scale_kernel + leaf_pack_kernel<1> + leaf_packed_kernel<1,256,256,4,2>")}
+SPLIT_FORMS = {8: ("bf16x3", "leaf_pack_kernel<0> + leaf_packed_kernel<0,256,256,4,4>"),
+               9: ("fp16x3", "leaf_scale_kernel + leaf_pack_kernel<1> + leaf_packed_kernel<1,256,256,4,4>")}
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per leaf launch (HBM-resident depth-3 call: one grouped launch of
 # 343 leaves of 2432 x 2432 x 2432) from the FETCH_SIZE and WRITE_SIZE counter
@@ -304,7 +304,7 @@ def main():
     split = SPLIT_FORMS.get(args.tile)
     peak = PEAK_16BIT_TFLOPS / 3 if split else PEAK_FP32_TFLOPS
     if split and st["depth"] >= 1:  # the scale and pack passes run fused with the last pre-additions
-        kernel = f"leaf_packed_kernel<{args.tile - 8},256,256,4,2>"
+        kernel = f"leaf_packed_kernel<{args.tile - 8},256,256,4,4>"
     else:
         kernel = split[1] if split else "leaf_gemm_kernel<128,128,16,2,2> (grouped leaves)"
     roofline = {"bound": "mfma", "kernel": kernel,

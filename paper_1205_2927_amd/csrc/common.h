@@ -214,7 +214,7 @@ struct TileShape {
 // Macro tile and wavefront grid of the split-precision leaves on packed
 // operands (tile ids kTileBf16x3 and kTileFp16x3 of the level-wise engine).
 constexpr int kSplitTileM = 256, kSplitTileN = 256;
-constexpr int kSplitWavesM = 4, kSplitWavesN = 2;
+constexpr int kSplitWavesM = 4, kSplitWavesN = 4;
 
 inline TileShape tile_shape(int id) {
   switch (id) {

@@ -815,9 +815,13 @@ __global__ void __launch_bounds__(256) preadd_scale_b_kernel(const PackNode* __r
 // per 128 rows or columns), each slab copied straight from the packed blocks
 // into LDS by buffer loads with the LDS bit (1 KB per wavefront
 // instruction).  A tile reaching past the last packed block of an operand
-// reads zeros there (empty buffer range).
+// reads zeros there (empty buffer range).  The two 64 KB slab buffers of a
+// 256x256 tile take the CU's LDS, so one workgroup runs per CU; 16
+// wavefronts of 64x64 (four per SIMD) hide the fragment reads far better than
+// 8 of 64x128 (the waves of one workgroup meet at every slab barrier):
+// +8-9% at n = 19456.
 template <int FMT, int TM, int TN, int WGM, int WGN>
-__global__ void __launch_bounds__(64 * WGM * WGN, 2)
+__global__ void __launch_bounds__(64 * WGM * WGN, WGM * WGN / 4)  // one workgroup per CU
 leaf_packed_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles, int xcd_chunk) {
   constexpr int BK = kPackK;
   constexpr int kWaves = WGM * WGN;
