@@ -22,22 +22,22 @@ def _pinned(shape):
     return torch.empty(shape, dtype=torch.float32, pin_memory=True)
 
 
-def _check(fastmm, M, N, K, depth, leaf, seed_a, seed_b, rows=24, device=False):
+def _check(fastmm, M, N, K, depth, leaf, seed_a, seed_b, rows=24, device=False, tile=0, tol=TOL):
     A = _pinned((M, K))
     B = _pinned((K, N))
     C = _pinned((M, N))
     synthgen.fill_uniform_pm1(seed_a, M, K, A.data_ptr())
     synthgen.fill_uniform_pm1(seed_b, K, N, B.data_ptr())
     C.fill_(float("nan"))
-    say(f"full size {M}x{K}x{N} depth={depth} leaf={leaf} device={device}")
+    say(f"full size {M}x{K}x{N} depth={depth} leaf={leaf} device={device} tile={tile}")
     if device:
         dA, dB, dC = A.to("cuda"), B.to("cuda"), C.to("cuda")
-        fastmm.gemm(M, N, K, dA, dB, dC, depth=depth, leaf=leaf, tile=0)
+        fastmm.gemm(M, N, K, dA, dB, dC, depth=depth, leaf=leaf, tile=tile)
         st = fastmm.get_stats()
         C.copy_(dC)
         del dA, dB, dC
     else:
-        fastmm.gemm(M, N, K, A, B, C, depth=depth, leaf=leaf, tile=0)
+        fastmm.gemm(M, N, K, A, B, C, depth=depth, leaf=leaf, tile=tile)
         st = fastmm.get_stats()
     An, Bn, Cn = A.numpy(), B.numpy(), C.numpy()
     assert np.isfinite(Cn).all()
@@ -45,7 +45,7 @@ def _check(fastmm, M, N, K, depth, leaf, seed_a, seed_b, rows=24, device=False):
     e_rows = checks.sampled_rows_rel(Cn, An, Bn, r)
     e_fv = checks.freivalds_rel(Cn, An, Bn, synthgen.signs_pm1(seed_b + 7, N))
     say(f"  depth={st['depth']} sampled-rows rel={e_rows:.3e} freivalds rel={e_fv:.3e}")
-    assert e_rows <= TOL and e_fv <= TOL
+    assert e_rows <= tol and e_fv <= tol
     return st
 
 
@@ -81,3 +81,14 @@ def test_square_19456_other_depths_pinned(fastmm, depth):
 def test_rectangular_19456x16384x12288_pinned(fastmm, depth, leaf):
     st = _check(fastmm, 19456, 12288, 16384, depth, leaf, 1001 + 3, 2001 + 3, rows=12)
     assert st["depth"] == depth
+
+
+@pytest.mark.parametrize("tile,depth,tol", [(8, 0, 2e-5), (8, 2, 1e-4), (9, 0, 5e-6), (9, 2, 2e-5)])
+def test_precision_forms_square_19456_device(fastmm, tile, depth, tol):
+    # The precision forms at the benchmark's size (its precision_forms
+    # block): split BF16 (tile 8) and scaled split FP16 (tile 9) at depth 0
+    # and at depth 2 with the fused last-level passes.
+    st = _check(fastmm, 19456, 19456, 19456, depth, 1024, 1001 + 3, 2001 + 3, rows=8, device=True,
+                tile=tile, tol=tol)
+    assert st["depth"] == depth and st["tile"] == tile
+
