@@ -55,7 +55,8 @@ enum { FASTMM_AUTO = -1 }; /* depth < 0 (or tile < 0): let the planner choose */
 
 /* Planner modes (fastmm_plan). */
 enum {
-  FASTMM_PLAN_DEFAULT = 0,   /* fixed rule: deepest split with leaf >= 1536 */
+  FASTMM_PLAN_DEFAULT = 0,   /* fixed rule: deepest split with leaf >= 1536; 64x64
+                                tiles when 128x128 ones would number under 512 */
   FASTMM_PLAN_MODEL = 1,     /* learned cost model; falls back to EXHAUSTIVE */
   FASTMM_PLAN_EXHAUSTIVE = 2 /* time every candidate on the device, cache it */
 };

@@ -142,7 +142,9 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
       if (rc != kSuccess) throw Error(rc, "planner failed");
       dep = pl.depth;
       lf = pl.leaf;
-      tile = pl.tile;
+      // The fixed rule's small-launch tile is for a product alone; the
+      // leaves of a batch share one launch, which the 128x128 tiles fill.
+      tile = L.plan_mode == FASTMM_PLAN_DEFAULT ? (int)kTile128x128 : pl.tile;
     }
     p.depth = p.K == 0 ? 0 : effective_depth(p.M, p.N, p.K, dep, lf);
     p.tile = tile;

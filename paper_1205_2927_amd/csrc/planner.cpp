@@ -8,7 +8,11 @@
 //               128x128 (the analogue of the paper's size thresholds and
 //               recursion point, set from measured Winograd-vs-classic
 //               crossovers on MI355X: the fastest depth leaves 1536..2432
-//               in every dimension for square n from 3072 to 19456);
+//               in every dimension for square n from 3072 to 19456); a
+//               launch that would have fewer than 512 tiles of 128x128
+//               (under half the device's 1024 workgroup slots) takes 64x64
+//               tiles instead (n = 1024: 0.081 against 0.129 ms, 1536:
+//               0.150 / 0.165, 2560: 0.361 / 0.384; a tie at 2048);
 //   EXHAUSTIVE  time every candidate (depth, tile) on the device with
 //               device-resident operands, keep the fastest; every timing is
 //               a record of the timing database;
@@ -223,8 +227,15 @@ int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_pl
     return kSuccess;
   }
   if (mode == FASTMM_PLAN_DEFAULT) {
-    *out = make_plan(effective_depth(M, N, K, 16, kDefaultLeaf), kTile128x128, -1.0,
-                     FASTMM_PLAN_DEFAULT);
+    const int d = effective_depth(M, N, K, 16, kDefaultLeaf);
+    int64_t m = M, n = N, leaves = 1;
+    for (int l = 0; l < d; ++l) {
+      m = split_half(m);
+      n = split_half(n);
+      leaves *= 7;
+    }
+    const int64_t tiles = leaves * ((m + 127) / 128) * ((n + 127) / 128);
+    *out = make_plan(d, tiles < 512 ? kTile64x64 : kTile128x128, -1.0, FASTMM_PLAN_DEFAULT);
     out->leaf = kDefaultLeaf;
     return kSuccess;
   }

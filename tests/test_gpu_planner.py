@@ -64,10 +64,12 @@ def test_mlp_adam_matches_oracle(fastmm):
 
 
 def test_default_rule(fastmm):
-    # deepest split whose leaf stays >= 1536 in every dimension
-    for n, d in [(19456, 3), (16384, 3), (8192, 2), (4096, 1), (3072, 1), (2048, 0), (512, 0)]:
+    # deepest split whose leaf stays >= 1536 in every dimension; 64x64 tiles
+    # when the leaf launch would have fewer than 512 tiles of 128x128
+    for n, d, t in [(19456, 3, 0), (16384, 3, 0), (8192, 2, 0), (4096, 1, 0), (3072, 1, 0),
+                    (2560, 0, 3), (2048, 0, 3), (512, 0, 3)]:
         p = fastmm.plan(n, n, n, fastmm.PLAN_DEFAULT)
-        assert (p.depth, p.leaf, p.tile, p.source) == (d, 1536, 0, fastmm.PLAN_DEFAULT), n
+        assert (p.depth, p.leaf, p.tile, p.source) == (d, 1536, t, fastmm.PLAN_DEFAULT), n
     p = fastmm.plan(19456, 12288, 16384, fastmm.PLAN_DEFAULT)  # leaves 2432 x 1536 x 2048
     assert p.depth == 3
 
