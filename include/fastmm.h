@@ -95,7 +95,9 @@ typedef struct {
   int depth;              /* Winograd levels to take (0 = plain MFMA SGEMM) */
   int64_t leaf;           /* leaf cutoff passed to fastmm_gemm */
   int tile;               /* FASTMM_TILE_* of the leaf kernel */
-  size_t workspace_bytes; /* device workspace the plan needs */
+  size_t workspace_bytes; /* device workspace of the plan's temporaries (S, T, P
+                             blocks, packed split-precision operands); staging
+                             copies of host or misaligned operands come on top */
   double predicted_ms;    /* model prediction or measured time; <0 unknown */
   int source;             /* FASTMM_PLAN_* mode that produced it */
 } fastmm_plan_t;

@@ -399,6 +399,19 @@ int fastmm_plan(int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out) {
     if (M < 0 || N < 0 || K < 0) throw Error(kInvalidValue, "negative dimension");
     const int rc = plan_choose(L, M, N, K, mode, out);
     if (rc != kSuccess) throw Error(rc, "planner failed");
+    // Temporaries of the level-wise schedule (K and N padded to 4 as staged
+    // operands would be); staging copies of host or misaligned operands
+    // come on top.
+    out->workspace_bytes = 0;
+    if (M > 0 && N > 0 && K > 0) {
+      Problem q;
+      q.M = M;
+      q.N = (N + 3) / 4 * 4;
+      q.K = (K + 3) / 4 * 4;
+      q.depth = out->depth;
+      q.tile = out->tile;
+      out->workspace_bytes = problem_temp_bytes(q);
+    }
   });
 }
 
