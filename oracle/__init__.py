@@ -18,6 +18,9 @@ Contents
   mlp       -- the planner's cost-model network in FP64: forward, analytic
                backward, Adam.
   checks    -- relative Frobenius error and the probabilistic checks.
+  split     -- the precision forms of the leaf (split BF16, scaled split
+               FP16) emulated in numpy, and Winograd's recursion over
+               them with FP32 additions.
 """
 from __future__ import annotations
 
