@@ -56,6 +56,13 @@ std::string signature(const Schedule& s) {
   for (int l = s.max_depth - 1; l >= 0; --l)
     o << "p" << (const void*)s.d_post[l] << ',' << s.post[l].size() << ',' << blocks_post(s.post[l])
       << ',' << (int)s.vec_post[l] << ';';
+  for (const auto& t : s.trees)
+    o << "t" << t.kind << ',' << t.level << ',' << t.levels << ',' << (const void*)t.d_nodes << ','
+      << t.nodes.size() << ',' << t.blocks << ';';
+  for (int fmt = 0; fmt < 2; ++fmt)
+    for (int side = 0; side < 2; ++side)
+      o << "k" << fmt << side << (const void*)s.d_pack[fmt][side] << ',' << s.pack[fmt][side].size()
+        << ',' << s.pack_units[fmt][side] << ';';
   return o.str();
 }
 

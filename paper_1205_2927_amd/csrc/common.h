@@ -109,6 +109,30 @@ struct PostAddNode {
   int32_t pad_;
 };
 
+// One node of a multi-level addition launch: L consecutive levels of the
+// recursion (L = 2 or 3) in one pass, for subtrees whose quadrant splits are
+// exact at every one of those levels (no clipped quadrant anywhere).  The
+// top node's operand (or product) is then a 2^L x 2^L grid of equal cells of
+// br x bc elements, and every S, T and P of the levels in between is a grid
+// of the same cells, so one thread can follow one element position through
+// all L levels.
+//   pre-additions: src = the top node's operand (leading dimension ld);
+//     dst[j] = the S (T) blocks of level l0 + j, all nodes of that level,
+//     node-major, four dense blocks per node (the level-wise layout);
+//     node = index of the top node within level l0.
+//   post-additions: src = the 7^L products of level l0 + L under this node
+//     (consecutive dense br x bc blocks); dst[0] = the node's product
+//     (leading dimension ld).
+struct TreeNode {
+  const float* src;
+  float* dst[3];
+  int64_t ld;
+  int64_t node;
+  int32_t br, bc;
+  int32_t block_begin;
+  int32_t pad_;
+};
+
 inline int32_t clamp_extent(int64_t v, int64_t hi) {
   return (int32_t)(v < 0 ? 0 : (v > hi ? hi : v));
 }
@@ -296,5 +320,19 @@ void launch_preadd(int side, const PreAddNode* d_nodes, int nnodes, int total_bl
 // (each by the same chain of operations as in the fused form).
 void launch_postadd(const PostAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
                     hipStream_t stream, int quad = -1);
+
+// Multi-level additions over TreeNode descriptors.  kind 0: A-side
+// pre-additions, 1: B-side pre-additions, 2: post-additions; levels 2 or 3.
+// Each thread takes tree_width(levels) consecutive elements of a cell: four
+// (16-byte accesses) for two levels; one for three, whose 64 inputs (pre) or
+// 64 outputs (post) per element already fill the registers.
+constexpr int kMaxTreeLevels = 3;
+constexpr int tree_width(int levels) { return levels >= 3 ? 1 : 4; }
+inline int64_t tree_blocks_for(int levels, int64_t br, int64_t bc) {
+  const int64_t groups = br * (bc / tree_width(levels));
+  return (groups + kAddThreadsPerBlock - 1) / kAddThreadsPerBlock;
+}
+void launch_tree_add(int kind, int levels, const TreeNode* d_nodes, int nnodes, int total_blocks,
+                     hipStream_t stream);
 
 }  // namespace fastmm

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -225,6 +226,24 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
   // in one fused pass (FASTMM_FUSED_PACK=0: the two passes, for comparison).
   const char* fe = std::getenv("FASTMM_FUSED_PACK");
   const bool fuse_allowed = !(fe && fe[0] == '0');
+  // Subtrees that split exactly take up to three levels of additions per
+  // launch (FASTMM_TREE_ADDS=1: one level per launch; 2: at most two).
+  const char* te = std::getenv("FASTMM_TREE_ADDS");
+  const int tree_max = (te && te[0] >= '0' && te[0] <= '9') ? std::min(kMaxTreeLevels, std::atoi(te))
+                                                            : kMaxTreeLevels;
+  auto add_tree = [&](int kind, int level, int levels, const TreeNode& tn) {
+    for (auto& t : s.trees)
+      if (t.kind == kind && t.level == level && t.levels == levels) {
+        t.nodes.push_back(tn);
+        return;
+      }
+    Schedule::TreeLaunch t;
+    t.kind = kind;
+    t.level = level;
+    t.levels = levels;
+    t.nodes.push_back(tn);
+    s.trees.push_back(std::move(t));
+  };
   int maxd = 0;
   for (const auto& p : probs) maxd = std::max(maxd, p.depth);
   s.max_depth = maxd;
@@ -254,6 +273,11 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
       PreAddNode a, b;
     };
     std::vector<Fused> fused;
+    // Level-wise nodes and bytes per level, and the S / T block bases; the
+    // launches are chosen once every level is known.
+    std::vector<std::vector<PreAddNode>> lvA(d), lvB(d);
+    std::vector<float*> Sb(d), Tb(d);
+    std::vector<double> byA(d, 0.0), byB(d, 0.0);
     // Pre-additions, level by level; the next level's operands are views
     // of this level's operands or of the new S / T blocks.
     for (int l = 0; l < d; ++l) {
@@ -277,8 +301,8 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
         if (fuse && l == d - 1 && pre_vec_ok(na) && pre_vec_ok(nb)) {
           fused.push_back({x, na, nb});
         } else {
-          s.preA[l].push_back(na);
-          if (!p.b_tree_ready) s.preB[l].push_back(nb);
+          lvA[l].push_back(na);
+          if (!p.b_tree_ready) lvB[l].push_back(nb);
         }
         const View a11 = quadrant(a, 0, 0, c.m, c.k), a12 = quadrant(a, 0, 1, c.m, c.k),
                    a22 = quadrant(a, 1, 1, c.m, c.k);
@@ -297,8 +321,73 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
       }
       Av.swap(nA);
       Bv.swap(nB);
-      s.add_bytes += (double)nodes * (32.0 * c.m * c.k + (p.b_tree_ready ? 0.0 : 32.0 * c.k * c.n));
+      Sb[l] = S;
+      Tb[l] = T;
+      byA[l] = (double)nodes * 32.0 * c.m * c.k;
+      byB[l] = p.b_tree_ready ? 0.0 : (double)nodes * 32.0 * c.k * c.n;
     }
+    // Group the levels from the bottom up: the deepest levels hold the most
+    // nodes, so they gain most from sharing a pass.  g[l] = levels of the
+    // launch whose top level is l (1: level-wise), 0 inside a group.
+    auto full_pre = [](const PreAddNode& n) {
+      return n.top_rows == n.h_r && n.bot_rows == n.h_r && n.left_cols == n.h_c &&
+             n.right_cols == n.h_c && pre_vec_ok(n);
+    };
+    auto group_levels = [&](int top, const std::function<bool(int)>& level_ok) {
+      std::vector<int> g(d, 1);
+      int hi = top;
+      while (hi > 0) {
+        int L = std::min(tree_max, hi);
+        auto range_ok = [&](int a, int b) {
+          for (int l = a; l < b; ++l)
+            if (!level_ok(l)) return false;
+          return true;
+        };
+        while (L > 1 && !range_ok(hi - L, hi)) --L;
+        L = std::max(L, 1);
+        for (int j = hi - L; j < hi; ++j) g[j] = 0;
+        g[hi - L] = L;
+        hi -= L;
+      }
+      return g;
+    };
+    // Pre-addition groups stop above a level fused with the pack pass.
+    const int pre_top = fuse ? d - 1 : d;
+    auto pre_side = [&](int kind, std::vector<std::vector<PreAddNode>>& lv,
+                        const std::vector<float*>& base, const std::vector<double>& by,
+                        std::vector<std::vector<PreAddNode>>& out) {
+      const std::vector<int> g = group_levels(pre_top, [&](int l) {
+        if ((int64_t)lv[l].size() != pow7(l)) return false;
+        for (const auto& n : lv[l])
+          if (!full_pre(n)) return false;
+        return true;
+      });
+      for (int l = 0; l < d; ++l) {
+        if (g[l] == 1) {
+          out[l].insert(out[l].end(), lv[l].begin(), lv[l].end());
+          s.add_bytes += by[l];
+        } else if (g[l] > 1) {
+          const int L = g[l];
+          const Dims& cell = dims[l + L];
+          const int64_t br = kind == 0 ? cell.m : cell.k, bc = kind == 0 ? cell.k : cell.n;
+          double cells = (double)(1 << (2 * L));  // the top operand, read once
+          for (int j = 0; j < L; ++j) cells += (double)pow7(j) * 4.0 * (double)(1 << (2 * (L - 1 - j)));
+          for (int64_t x = 0; x < (int64_t)lv[l].size(); ++x) {
+            TreeNode tn{};
+            tn.src = lv[l][x].src;
+            tn.ld = lv[l][x].ld;
+            for (int j = 0; j < L; ++j) tn.dst[j] = base[l + j];
+            tn.node = x;
+            tn.br = (int32_t)br;
+            tn.bc = (int32_t)bc;
+            add_tree(kind, l, L, tn);
+          }
+          s.add_bytes += (double)lv[l].size() * cells * 4.0 * (double)br * (double)bc;
+        }
+      }
+    };
+    pre_side(0, lvA, Sb, byA, s.preA);
+    if (!p.b_tree_ready) pre_side(1, lvB, Tb, byB, s.preB);
     // Product buffers P[l] (l = 1..d), 7^l blocks of m_l x n_l.
     std::vector<float*> P(d + 1, nullptr);
     for (int l = 1; l <= d; ++l) P[l] = carve((size_t)pow7(l) * dims[l].m * dims[l].n);
@@ -376,18 +465,49 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     s.leaf_flops += (double)nleaves * 2.0 * lf.m * lf.n * lf.k;
     s.leaf_dims = lf;
     // Post-additions, deepest level first.
+    std::vector<std::vector<PostAddNode>> lvP(d);
     for (int l = d - 1; l >= 0; --l) {
       const Dims c = dims[l + 1];
       const int64_t nodes = pow7(l);
       for (int64_t x = 0; x < nodes; ++x) {
         const float* pin = P[l + 1] + x * 7 * c.m * c.n;
         if (l == 0)
-          s.post[l].push_back(postadd_node(pin, c.m, c.n, p.C, p.ldc, p.cr(), p.cc()));
+          lvP[l].push_back(postadd_node(pin, c.m, c.n, p.C, p.ldc, p.cr(), p.cc()));
         else
-          s.post[l].push_back(postadd_node(pin, c.m, c.n, P[l] + x * dims[l].m * dims[l].n,
-                                           dims[l].n, dims[l].m, dims[l].n));
+          lvP[l].push_back(postadd_node(pin, c.m, c.n, P[l] + x * dims[l].m * dims[l].n,
+                                        dims[l].n, dims[l].m, dims[l].n));
       }
-      s.add_bytes += (double)nodes * 44.0 * c.m * c.n;
+    }
+    const std::vector<int> gp = group_levels(d, [&](int l) {
+      for (const auto& n : lvP[l])
+        if (!(n.top_rows == n.h_r && n.bot_rows == n.h_r && n.left_cols == n.h_c &&
+              n.right_cols == n.h_c && post_vec_ok(n)))
+          return false;
+      return true;
+    });
+    for (int l = d - 1; l >= 0; --l) {
+      const Dims c = dims[l + 1];
+      if (gp[l] == 1) {
+        s.post[l].insert(s.post[l].end(), lvP[l].begin(), lvP[l].end());
+        s.add_bytes += (double)lvP[l].size() * 44.0 * c.m * c.n;
+      } else if (gp[l] > 1) {
+        // The node's 7^L bottom products in, its product out.
+        const int L = gp[l];
+        const Dims& cell = dims[l + L];
+        const int64_t blocks = pow7(L);
+        for (int64_t x = 0; x < (int64_t)lvP[l].size(); ++x) {
+          TreeNode tn{};
+          tn.src = P[l + L] + x * blocks * cell.m * cell.n;
+          tn.dst[0] = lvP[l][x].dst;
+          tn.ld = lvP[l][x].ld;
+          tn.node = x;
+          tn.br = (int32_t)cell.m;
+          tn.bc = (int32_t)cell.n;
+          add_tree(2, l, L, tn);
+        }
+        s.add_bytes += (double)lvP[l].size() * (double)(blocks + (1 << (2 * L))) * 4.0 *
+                       (double)cell.m * (double)cell.n;
+      }
     }
   }
   s.temp_bytes = off * sizeof(float);
@@ -427,6 +547,15 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
       if (u > INT32_MAX) throw Error(kNotSupported, "fused pack launch too large");
       s.pack_units[fmt][side] = (int)u;
     }
+  for (auto& t : s.trees) {
+    int64_t b = 0;
+    for (auto& n : t.nodes) {
+      n.block_begin = (int32_t)b;
+      b += tree_blocks_for(t.levels, n.br, n.bc);
+    }
+    if (b > INT32_MAX) throw Error(kNotSupported, "multi-level addition launch too large");
+    t.blocks = (int)b;
+  }
   s.leaf_tiles_total.assign(kNumTiles, 0);
   for (int t = 0; t < kNumTiles; ++t) {
     s.vec_leaf[t] = true;
@@ -466,6 +595,7 @@ size_t schedule_desc_bytes(const Schedule& s) {
     b += align_up(s.post[l].size() * sizeof(PostAddNode), 256);
   }
   for (int t = 0; t < kNumTiles; ++t) b += align_up(s.leaf[t].size() * sizeof(GemmDesc), 256);
+  for (const auto& t : s.trees) b += align_up(t.nodes.size() * sizeof(TreeNode), 256);
   for (int fmt = 0; fmt < 2; ++fmt)
     for (int side = 0; side < 2; ++side) b += align_up(s.pack[fmt][side].size() * sizeof(PackNode), 256);
   return b;
@@ -501,6 +631,8 @@ void upload_schedule(Library& L, Schedule& s, char* desc_dev, char* desc_host) {
   }
   for (int t = 0; t < kNumTiles; ++t)
     s.d_leaf[t] = reinterpret_cast<const GemmDesc*>(put(s.leaf[t].data(), s.leaf[t].size() * sizeof(GemmDesc)));
+  for (auto& t : s.trees)
+    t.d_nodes = reinterpret_cast<const TreeNode*>(put(t.nodes.data(), t.nodes.size() * sizeof(TreeNode)));
   for (int fmt = 0; fmt < 2; ++fmt)
     for (int side = 0; side < 2; ++side)
       s.d_pack[fmt][side] = reinterpret_cast<const PackNode*>(
@@ -517,6 +649,11 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
     const int bb = add_total_blocks(s.preB[l]);
     if (ba) { launch_preadd(0, s.d_preA[l], (int)s.preA[l].size(), ba, s.vec_preA[l], L.stream); ++launches; }
     if (bb) { launch_preadd(1, s.d_preB[l], (int)s.preB[l].size(), bb, s.vec_preB[l], L.stream); ++launches; }
+    for (const auto& t : s.trees)
+      if (t.kind < 2 && t.level == l && t.blocks > 0) {
+        launch_tree_add(t.kind, t.levels, t.d_nodes, (int)t.nodes.size(), t.blocks, L.stream);
+        ++launches;
+      }
   }
   // Fused last-level pre-addition and pack of split-precision leaves; the
   // scaled FP16 form first takes its scale exponents from the same quadrants.
@@ -571,6 +708,11 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
   for (int l = s.max_depth - 1; l >= 0; --l) {
     const int bp = add_total_blocks(s.post[l]);
     if (bp) { launch_postadd(s.d_post[l], (int)s.post[l].size(), bp, s.vec_post[l], L.stream); ++launches; }
+    for (const auto& t : s.trees)
+      if (t.kind == 2 && t.level == l && t.blocks > 0) {
+        launch_tree_add(2, t.levels, t.d_nodes, (int)t.nodes.size(), t.blocks, L.stream);
+        ++launches;
+      }
   }
   if (profile) FASTMM_HIP(hipEventRecord(L.ev[4], L.stream));
   s.launches = launches;

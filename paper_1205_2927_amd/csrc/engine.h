@@ -89,6 +89,16 @@ struct Schedule {
   std::vector<PackNode> pack[2][2];
   int pack_units[2][2] = {};
   const PackNode* d_pack[2][2] = {};
+  // Multi-level additions (subtrees that split exactly at every level):
+  // one launch per kind (0 A-side pre, 1 B-side pre, 2 post), top level and
+  // number of levels; pre launches run with the level-wise ones of their
+  // top level, post launches with the post-additions of their top level.
+  struct TreeLaunch {
+    int kind = 0, level = 0, levels = 0, blocks = 0;
+    std::vector<TreeNode> nodes;
+    const TreeNode* d_nodes = nullptr;
+  };
+  std::vector<TreeLaunch> trees;
   bool vec_leaf[kNumTiles] = {};  // set in build_schedule
   int xcd_chunk[kNumTiles] = {};  // leaf launch tile -> XCD mapping (leaf_tile_of_block)
   bool persistent = false;        // leaf launches take tiles from L.leaf_queue

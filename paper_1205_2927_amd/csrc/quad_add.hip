@@ -176,6 +176,240 @@ postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Several levels in one pass.  Where a subtree splits exactly at each of L
+// levels, one element position of the bottom cell grid meets the same
+// position of every S, T and P block in it: a thread loads the 4^L values of
+// its position in the top operand, forms the S (T) blocks of every level in
+// registers and writes each once; a post-addition thread loads its
+// position in the 7^L bottom products and writes the 4^L results.  The chains
+// are the single-level ones, operand for operand, so results are bit for bit
+// those of the level-by-level launches; what disappears is the traffic of
+// the levels in between (each S or T block of an inner level read back, each
+// inner product written and read back).
+
+template <int W>
+struct Vw {
+  float v[W];
+};
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+
+template <int W>
+__device__ __forceinline__ Vw<W> ldw(const float* p) {
+  Vw<W> r;
+  if constexpr (W == 4) {
+    const nt_f4 t = __builtin_nontemporal_load(reinterpret_cast<const nt_f4*>(p));
+    r.v[0] = t.x; r.v[1] = t.y; r.v[2] = t.z; r.v[3] = t.w;
+  } else if constexpr (W == 2) {
+    const nt_f2 t = __builtin_nontemporal_load(reinterpret_cast<const nt_f2*>(p));
+    r.v[0] = t.x; r.v[1] = t.y;
+  } else {
+    r.v[0] = __builtin_nontemporal_load(p);
+  }
+  return r;
+}
+
+template <int W>
+__device__ __forceinline__ void stw(float* p, const Vw<W>& x) {
+  if constexpr (W == 4) {
+    const nt_f4 t = {x.v[0], x.v[1], x.v[2], x.v[3]};
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_f4*>(p));
+  } else if constexpr (W == 2) {
+    const nt_f2 t = {x.v[0], x.v[1]};
+    __builtin_nontemporal_store(t, reinterpret_cast<nt_f2*>(p));
+  } else {
+    __builtin_nontemporal_store(x.v[0], p);
+  }
+}
+
+template <int W>
+__device__ __forceinline__ Vw<W> vadd(const Vw<W>& a, const Vw<W>& b) {
+  Vw<W> r;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r.v[i] = a.v[i] + b.v[i];
+  return r;
+}
+
+template <int W>
+__device__ __forceinline__ Vw<W> vsub(const Vw<W>& a, const Vw<W>& b) {
+  Vw<W> r;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r.v[i] = a.v[i] - b.v[i];
+  return r;
+}
+
+// One pre-addition level of a subtree.  X: the node's operand as a 2^J x 2^J
+// grid (this thread's element of each cell).  Writes S1..S4 (T1..T4) of the
+// node -- level base dst[REL], node index `node` -- and recurses into the
+// seven children's operands in product order (A side: A11, A12, S4, A22,
+// S1, S2, S3; B side: B11, B21, B22, T4, T1, T2, T3).
+template <int SIDE, int J, int REL, int W>
+__device__ __forceinline__ void tree_pre(const Vw<W> (&X)[1 << J][1 << J], const TreeNode& nd,
+                                         int64_t node, int r, int c) {
+  constexpr int H = 1 << (J - 1);
+  Vw<W> S[4][H][H];
+#pragma unroll
+  for (int u = 0; u < H; ++u)
+#pragma unroll
+    for (int v = 0; v < H; ++v) {
+      const Vw<W>& x11 = X[u][v];
+      const Vw<W>& x12 = X[u][v + H];
+      const Vw<W>& x21 = X[u + H][v];
+      const Vw<W>& x22 = X[u + H][v + H];
+      if constexpr (SIDE == 0) {
+        // S1 = A21 + A22; S2 = S1 - A11; S3 = A11 - A21; S4 = A12 - S2
+        S[0][u][v] = vadd(x21, x22);
+        S[1][u][v] = vsub(S[0][u][v], x11);
+        S[2][u][v] = vsub(x11, x21);
+        S[3][u][v] = vsub(x12, S[1][u][v]);
+      } else {
+        // T1 = B12 - B11; T2 = B22 - T1; T3 = B22 - B12; T4 = T2 - B21
+        S[0][u][v] = vsub(x12, x11);
+        S[1][u][v] = vsub(x22, S[0][u][v]);
+        S[2][u][v] = vsub(x22, x12);
+        S[3][u][v] = vsub(S[1][u][v], x21);
+      }
+    }
+  // Blocks of this level: (H br) x (H bc), dense.
+  const int64_t ldo = (int64_t)H * nd.bc;
+  const int64_t blk = (int64_t)H * nd.br * ldo;
+  float* base = nd.dst[REL] + node * 4 * blk + (int64_t)r * ldo + c;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+#pragma unroll
+      for (int v = 0; v < H; ++v)
+        stw(base + i * blk + (int64_t)u * nd.br * ldo + (int64_t)v * nd.bc, S[i][u][v]);
+  if constexpr (J > 1) {
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      Vw<W> Ch[H][H];
+#pragma unroll
+      for (int u = 0; u < H; ++u)
+#pragma unroll
+        for (int v = 0; v < H; ++v) {
+          if constexpr (SIDE == 0) {
+            Ch[u][v] = i == 0 ? X[u][v] : i == 1 ? X[u][v + H] : i == 2 ? S[3][u][v]
+                     : i == 3 ? X[u + H][v + H] : S[i - 4][u][v];
+          } else {
+            Ch[u][v] = i == 0 ? X[u][v] : i == 1 ? X[u + H][v] : i == 2 ? X[u + H][v + H]
+                     : i == 3 ? S[3][u][v] : S[i - 4][u][v];
+          }
+        }
+      tree_pre<SIDE, J - 1, REL + 1, W>(Ch, nd, node * 7 + i, r, c);
+    }
+  }
+}
+
+template <int SIDE, int L>
+__global__ void __launch_bounds__(kAddThreads)
+tree_preadd_kernel(const TreeNode* __restrict__ nodes, int nnodes) {
+  constexpr int W = tree_width(L);
+  const TreeNode nd = nodes[find_node(nodes, nnodes, blockIdx.x)];
+  const int cw = nd.bc / W;
+  const int64_t g = (int64_t)(blockIdx.x - nd.block_begin) * kAddThreads + threadIdx.x;
+  if (g >= (int64_t)nd.br * cw) return;
+  const int r = (int)(g / cw);
+  const int c = (int)(g - (int64_t)r * cw) * W;
+  Vw<W> X[1 << L][1 << L];
+#pragma unroll
+  for (int u = 0; u < (1 << L); ++u)
+#pragma unroll
+    for (int v = 0; v < (1 << L); ++v)
+      X[u][v] = ldw<W>(nd.src + ((int64_t)u * nd.br + r) * nd.ld + (int64_t)v * nd.bc + c);
+  tree_pre<SIDE, L, 0, W>(X, nd, nd.node, r, c);
+}
+
+__host__ __device__ constexpr int64_t pow7c(int j) { return j == 0 ? 1 : 7 * pow7c(j - 1); }
+
+// The product of a subtree of J levels as a 2^J x 2^J grid (this thread's
+// element of each cell), from its 7^J bottom products starting at block t.
+// Children are taken in the order that keeps the fewest grids alive; every
+// result is the single-level chain of the same operands.
+template <int J, int W>
+__device__ __forceinline__ void tree_post(Vw<W> (&G)[1 << J][1 << J], const float* __restrict__ P,
+                                          int64_t t, int64_t cell, int64_t off) {
+  if constexpr (J == 0) {
+    G[0][0] = ldw<W>(P + t * cell + off);
+  } else {
+    constexpr int H = 1 << (J - 1);
+    constexpr int64_t s7 = pow7c(J - 1);
+    Vw<W> p1[H][H], p2[H][H], u2[H][H], u3[H][H], q[H][H];
+    tree_post<J - 1, W>(p1, P, t + 0 * s7, cell, off);
+    tree_post<J - 1, W>(p2, P, t + 1 * s7, cell, off);
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+#pragma unroll
+      for (int v = 0; v < H; ++v) G[u][v] = vadd(p1[u][v], p2[u][v]);  // C11 = P1 + P2
+    tree_post<J - 1, W>(q, P, t + 5 * s7, cell, off);  // P6
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+#pragma unroll
+      for (int v = 0; v < H; ++v) u2[u][v] = vadd(p1[u][v], q[u][v]);  // U2 = P1 + P6
+    tree_post<J - 1, W>(q, P, t + 6 * s7, cell, off);  // P7
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+#pragma unroll
+      for (int v = 0; v < H; ++v) u3[u][v] = vadd(u2[u][v], q[u][v]);  // U3 = U2 + P7
+    tree_post<J - 1, W>(q, P, t + 4 * s7, cell, off);  // P5
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+#pragma unroll
+      for (int v = 0; v < H; ++v) {
+        u2[u][v] = vadd(u2[u][v], q[u][v]);            // U4 = U2 + P5
+        G[u + H][v + H] = vadd(u3[u][v], q[u][v]);     // C22 = U3 + P5
+      }
+    tree_post<J - 1, W>(q, P, t + 2 * s7, cell, off);  // P3
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+#pragma unroll
+      for (int v = 0; v < H; ++v) G[u][v + H] = vadd(u2[u][v], q[u][v]);  // C12 = U4 + P3
+    tree_post<J - 1, W>(q, P, t + 3 * s7, cell, off);  // P4
+#pragma unroll
+    for (int u = 0; u < H; ++u)
+#pragma unroll
+      for (int v = 0; v < H; ++v) G[u + H][v] = vsub(u3[u][v], q[u][v]);  // C21 = U3 - P4
+  }
+}
+
+template <int L>
+__global__ void __launch_bounds__(kAddThreads)
+tree_postadd_kernel(const TreeNode* __restrict__ nodes, int nnodes) {
+  constexpr int W = tree_width(L);
+  const TreeNode nd = nodes[find_node(nodes, nnodes, blockIdx.x)];
+  const int cw = nd.bc / W;
+  const int64_t g = (int64_t)(blockIdx.x - nd.block_begin) * kAddThreads + threadIdx.x;
+  if (g >= (int64_t)nd.br * cw) return;
+  const int r = (int)(g / cw);
+  const int c = (int)(g - (int64_t)r * cw) * W;
+  Vw<W> G[1 << L][1 << L];
+  tree_post<L, W>(G, nd.src, 0, (int64_t)nd.br * nd.bc, (int64_t)r * nd.bc + c);
+  float* out = nd.dst[0];
+#pragma unroll
+  for (int u = 0; u < (1 << L); ++u)
+#pragma unroll
+    for (int v = 0; v < (1 << L); ++v)
+      stw(out + ((int64_t)u * nd.br + r) * nd.ld + (int64_t)v * nd.bc + c, G[u][v]);
+}
+
+void launch_tree_add(int kind, int levels, const TreeNode* d_nodes, int nnodes, int total_blocks,
+                     hipStream_t stream) {
+  if (nnodes <= 0 || total_blocks <= 0) return;
+  dim3 grid(total_blocks), block(kAddThreads);
+  const int key = kind * 10 + levels;
+  switch (key) {
+    case 2: hipLaunchKernelGGL((tree_preadd_kernel<0, 2>), grid, block, 0, stream, d_nodes, nnodes); break;
+    case 3: hipLaunchKernelGGL((tree_preadd_kernel<0, 3>), grid, block, 0, stream, d_nodes, nnodes); break;
+    case 12: hipLaunchKernelGGL((tree_preadd_kernel<1, 2>), grid, block, 0, stream, d_nodes, nnodes); break;
+    case 13: hipLaunchKernelGGL((tree_preadd_kernel<1, 3>), grid, block, 0, stream, d_nodes, nnodes); break;
+    case 22: hipLaunchKernelGGL((tree_postadd_kernel<2>), grid, block, 0, stream, d_nodes, nnodes); break;
+    case 23: hipLaunchKernelGGL((tree_postadd_kernel<3>), grid, block, 0, stream, d_nodes, nnodes); break;
+    default: throw Error(kInvalidValue, "bad multi-level addition launch");
+  }
+  FASTMM_HIP(hipGetLastError());
+}
+
 void launch_preadd(int side, const PreAddNode* d_nodes, int nnodes, int total_blocks, bool vec,
                    hipStream_t stream) {
   if (nnodes <= 0 || total_blocks <= 0) return;

@@ -60,11 +60,12 @@ def test_winograd_all_ones_equals_k(fastmm):
     assert np.all(host(C) == k)
 
 
-def test_structure_counts_match_closed_forms(fastmm):
+def test_structure_counts_match_closed_forms(fastmm, monkeypatch):
     M, N, K = 1536, 1024, 1280
     A = uniform(81, M, K)
     B = uniform(82, K, N)
     C = empty_dev(M, N)
+    monkeypatch.setenv("FASTMM_TREE_ADDS", "1")  # one level per launch
     fastmm.gemm(M, N, K, dev(A), dev(B), C, depth=3, leaf=64)
     st = fastmm.get_stats()
     s = W.structure(M, N, K, 3, 64)
@@ -74,6 +75,16 @@ def test_structure_counts_match_closed_forms(fastmm):
     assert st["leaf_flops"] == s["leaf_flops"]
     assert st["add_bytes"] == s["add_bytes"]
     assert st["launches"] == 3 * 3 + 1
+    # Every split is exact: the three levels of each side take one pass
+    # (the operand read once, every S / T block written once: 4^3 + 4 * 4^2
+    # + 7 * 4 * 4 + 49 * 4 = 436 leaf-sized cells), and so do the
+    # post-additions (343 products read, the 64 cells of C written).
+    monkeypatch.setenv("FASTMM_TREE_ADDS", "3")
+    fastmm.gemm(M, N, K, dev(A), dev(B), C, depth=3, leaf=64)
+    st = fastmm.get_stats()
+    lm, lk, ln = s["leaf_dims"]
+    assert st["add_bytes"] == 4 * (436 * lm * lk + 436 * lk * ln + (343 + 64) * lm * ln)
+    assert st["launches"] == 4
 
 
 def test_host_pinned_and_pageable_match_device(fastmm):

@@ -1,0 +1,130 @@
+"""Multi-level additions: where every split of two or three consecutive
+levels is exact, their pre-additions (and post-additions) run as one pass
+that follows each element position through all of those levels.  The
+chains are the single-level ones, so the result must equal, bit for bit,
+the one-level-per-launch schedule (FASTMM_TREE_ADDS=1), on the level-wise
+path, the batched graph, the pipelined host path and the split-precision
+forms; and it must still meet the oracle's tolerance."""
+import numpy as np
+import pytest
+
+from oracle import checks, classic
+from tests.gpu_util import dev, empty_dev, host, say, uniform
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(fastmm, monkeypatch, levels, m, k, n, A, B, depth, leaf, tile=None):
+    monkeypatch.setenv("FASTMM_TREE_ADDS", str(levels))
+    C = empty_dev(m, n)
+    fastmm.gemm(m, n, k, A, B, C, depth=depth, leaf=leaf, tile=tile)
+    return host(C), fastmm.get_stats()
+
+
+# (m, k, n, depth, leaf, launches with one level per launch, launches grouped)
+CASES = [
+    (512, 512, 512, 2, 32, 7, 4),        # one group of 2 levels per side and for the post-additions
+    (512, 512, 512, 3, 32, 10, 4),       # one group of 3
+    (1536, 1024, 1280, 3, 64, 10, 4),    # rectangular
+    (1024, 1024, 1024, 4, 32, 13, 7),    # top level alone, then a group of 3
+    (768, 640, 896, 2, 32, 7, 4),
+    (2048, 256, 1024, 3, 16, 10, 4),
+]
+
+
+@pytest.mark.parametrize("m,k,n,depth,leaf,n_level,n_tree", CASES)
+def test_tree_adds_bitwise_equal_level_wise(fastmm, monkeypatch, m, k, n, depth, leaf, n_level, n_tree):
+    say(f"tree adds {m}x{k}x{n} depth {depth}")
+    A = uniform(5101 + m, m, k)
+    B = uniform(5102 + n, k, n)
+    Ad, Bd = dev(A), dev(B)
+    ref, st1 = _run(fastmm, monkeypatch, 1, m, k, n, Ad, Bd, depth, leaf)
+    got, st3 = _run(fastmm, monkeypatch, 3, m, k, n, Ad, Bd, depth, leaf)
+    say(f"  launches {st1['launches']} -> {st3['launches']}, add bytes "
+        f"{st1['add_bytes'] / 1e6:.1f} -> {st3['add_bytes'] / 1e6:.1f} MB")
+    assert st1["depth"] == st3["depth"] == depth
+    assert st1["launches"] == n_level and st3["launches"] == n_tree
+    assert st3["add_bytes"] < st1["add_bytes"]
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    assert checks.rel_frob(got, classic.gemm(A, B)) <= 1e-4
+
+
+def test_tree_adds_two_level_groups(fastmm, monkeypatch):
+    # FASTMM_TREE_ADDS=2 at depth 3: a lone top level, then a group of two
+    m = k = n = 512
+    A, B = uniform(5201, m, k), uniform(5202, k, n)
+    Ad, Bd = dev(A), dev(B)
+    ref, _ = _run(fastmm, monkeypatch, 1, m, k, n, Ad, Bd, 3, 32)
+    got, st = _run(fastmm, monkeypatch, 2, m, k, n, Ad, Bd, 3, 32)
+    assert st["launches"] == 7
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("m,k,n,depth", [(520, 512, 512, 2), (512, 516, 512, 3), (512, 512, 508, 3)])
+def test_tree_adds_skip_inexact_splits(fastmm, monkeypatch, m, k, n, depth):
+    # A split that is not exact (a clipped quadrant) keeps that operand's
+    # levels level-wise; the result is still the level-wise one.
+    A, B = uniform(5301 + m, m, k), uniform(5302 + n, k, n)
+    Ad, Bd = dev(A), dev(B)
+    ref, st1 = _run(fastmm, monkeypatch, 1, m, k, n, Ad, Bd, depth, 16)
+    got, st3 = _run(fastmm, monkeypatch, 3, m, k, n, Ad, Bd, depth, 16)
+    say(f"  {m}x{k}x{n} d{depth}: launches {st1['launches']} -> {st3['launches']}")
+    assert st3["launches"] <= st1["launches"]
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("tile", [8, 9])
+def test_tree_adds_split_forms(fastmm, monkeypatch, tile):
+    # depth 3 with split-precision leaves: the last level's pre-additions
+    # stay fused with the pack pass, the two above form one group.
+    m = k = n = 1024
+    A, B = uniform(5401, m, k), uniform(5402, k, n)
+    Ad, Bd = dev(A), dev(B)
+    ref, st1 = _run(fastmm, monkeypatch, 1, m, k, n, Ad, Bd, 3, 64, tile)
+    got, st3 = _run(fastmm, monkeypatch, 3, m, k, n, Ad, Bd, 3, 64, tile)
+    say(f"  tile {tile}: launches {st1['launches']} -> {st3['launches']}")
+    assert st3["launches"] < st1["launches"]
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def test_tree_adds_batched_graph(fastmm, monkeypatch):
+    import torch
+    shapes = [(384, 512, 448, 3), (256, 256, 256, 2), (320, 192, 128, 1), (513, 257, 129, 2),
+              (1024, 512, 768, 3)]
+    As = [dev(uniform(5500 + 2 * i, m, k)) for i, (m, k, n, d) in enumerate(shapes)]
+    Bs = [dev(uniform(5501 + 2 * i, k, n)) for i, (m, k, n, d) in enumerate(shapes)]
+    depths = [d for (_, _, _, d) in shapes]
+    out = {}
+    for levels in (1, 3):
+        monkeypatch.setenv("FASTMM_TREE_ADDS", str(levels))
+        for call in range(2):
+            Cs = [empty_dev(m, n) for (m, k, n, d) in shapes]
+            fastmm.gemm_batched(As, Bs, Cs, depth=depths, leaf=[1] * len(shapes))
+            assert fastmm.get_stats()["graph_replayed"] == call
+            junk = torch.randn(1 << 18, device="cuda")
+            junk.mul_(2.0)
+            torch.cuda.synchronize()
+            res = [host(C) for C in Cs]
+            if call == 0:
+                out[levels] = res
+            else:
+                for a, b in zip(res, out[levels]):
+                    assert np.array_equal(a, b)
+    for i, (a, b) in enumerate(zip(out[1], out[3])):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32)), f"problem {i}"
+
+
+def test_tree_adds_pinned_host(fastmm, monkeypatch):
+    import torch
+    n, depth = 1024, 3
+    A, B = uniform(5601, n, n), uniform(5602, n, n)
+    Ap = torch.from_numpy(A).pin_memory()
+    Bp = torch.from_numpy(B).pin_memory()
+    res = {}
+    for levels in (1, 3):
+        monkeypatch.setenv("FASTMM_TREE_ADDS", str(levels))
+        Cp = torch.empty((n, n), dtype=torch.float32).pin_memory()
+        fastmm.gemm(n, n, n, Ap, Bp, Cp, depth=depth, leaf=64)
+        res[levels] = Cp.numpy().copy()
+    assert np.array_equal(res[1].view(np.uint32), res[3].view(np.uint32))
+    assert checks.rel_frob(res[3], classic.gemm(A, B)) <= 1e-4
