@@ -370,8 +370,14 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
           const int L = g[l];
           const Dims& cell = dims[l + L];
           const int64_t br = kind == 0 ? cell.m : cell.k, bc = kind == 0 ? cell.k : cell.n;
-          double cells = (double)(1 << (2 * L));  // the top operand, read once
-          for (int j = 0; j < L; ++j) cells += (double)pow7(j) * 4.0 * (double)(1 << (2 * (L - 1 - j)));
+          // The top operand read once; of each S / T block of level l + j,
+          // the 3^(L-1-j) cells that the levels below read as views.
+          double cells = (double)(1 << (2 * L));
+          for (int j = 0; j < L; ++j) {
+            double seen = 1.0;
+            for (int i = 0; i < L - 1 - j; ++i) seen *= 3.0;
+            cells += (double)pow7(j) * 4.0 * seen;
+          }
           for (int64_t x = 0; x < (int64_t)lv[l].size(); ++x) {
             TreeNode tn{};
             tn.src = lv[l][x].src;

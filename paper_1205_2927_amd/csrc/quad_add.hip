@@ -186,7 +186,8 @@ postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
 // are the single-level ones, operand for operand, so results are bit for bit
 // those of the level-by-level launches; what disappears is the traffic of
 // the levels in between (each S or T block of an inner level read back, each
-// inner product written and read back).
+// inner product written and read back), and the writes of the S / T cells
+// that only the sums of the next level inside the subtree need.
 
 template <int W>
 struct Vw {
@@ -270,7 +271,14 @@ __device__ __forceinline__ void tree_pre(const Vw<W> (&X)[1 << J][1 << J], const
         S[3][u][v] = vsub(S[1][u][v], x21);
       }
     }
-  // Blocks of this level: (H br) x (H bc), dense.
+  // Blocks of this level: (H br) x (H bc), dense.  Below this level each
+  // block is read only through the children that are quadrant views (A11,
+  // A12, A22 / B11, B21, B22) -- the other quadrant enters the sums done
+  // here in registers -- and in full only at the bottom of the subtree (by
+  // the leaves, the pack pass or the next launch, all of which read views
+  // within their valid extents).  So cell (u, v) is written only if every
+  // level of its path is a view quadrant: no bit of u set where v's is
+  // clear (A side), or the reverse (B side).
   const int64_t ldo = (int64_t)H * nd.bc;
   const int64_t blk = (int64_t)H * nd.br * ldo;
   float* base = nd.dst[REL] + node * 4 * blk + (int64_t)r * ldo + c;
@@ -280,7 +288,8 @@ __device__ __forceinline__ void tree_pre(const Vw<W> (&X)[1 << J][1 << J], const
     for (int u = 0; u < H; ++u)
 #pragma unroll
       for (int v = 0; v < H; ++v)
-        stw(base + i * blk + (int64_t)u * nd.br * ldo + (int64_t)v * nd.bc, S[i][u][v]);
+        if ((SIDE == 0 ? (u & ~v) : (v & ~u)) == 0)
+          stw(base + i * blk + (int64_t)u * nd.br * ldo + (int64_t)v * nd.bc, S[i][u][v]);
   if constexpr (J > 1) {
 #pragma unroll
     for (int i = 0; i < 7; ++i) {

@@ -181,6 +181,9 @@ def test_split_fused_pack_matches_two_passes(fastmm, monkeypatch, m, k, n, depth
         B = _pow2_scaled(B, col_exp=synthgen.int_range(3604, 1, n, -30, 30)[0].astype(np.int64))
     dA, dB = dev(A), dev(B)
     C1, C2 = empty_dev(m, n), empty_dev(m, n)
+    # one level of additions per launch, so that the launch counts compare
+    # the pack passes alone
+    monkeypatch.setenv("FASTMM_TREE_ADDS", "1")
     monkeypatch.delenv("FASTMM_FUSED_PACK", raising=False)
     fastmm.gemm(m, n, k, dA, dB, C1, depth=depth, leaf=1, tile=tile)
     fused_launches = fastmm.get_stats()["launches"]
