@@ -37,7 +37,7 @@ PEAK_HBM_GBS = 8000.0
 # runs, each scaled by its reading for a 1 GiB calibration copy (fetch x2.000,
 # write x1.000); see profiles/leaf_gemm_n19456_d3_device_hbm_traffic.md.
 # Valid for leaf_gemm_kernel<128,128,16,2,2> in that configuration only.
-TRAFFIC_BYTES_PER_LAUNCH = 37010240.4 * 1024 * 2.000 + 7924672.0 * 1024 * 1.000
+TRAFFIC_BYTES_PER_LAUNCH = 37642619.6 * 1024 * 2.000 + 7924672.0 * 1024 * 1.000
 
 
 def log(msg):

@@ -128,3 +128,18 @@ def test_tree_adds_pinned_host(fastmm, monkeypatch):
         res[levels] = Cp.numpy().copy()
     assert np.array_equal(res[1].view(np.uint32), res[3].view(np.uint32))
     assert checks.rel_frob(res[3], classic.gemm(A, B)) <= 1e-4
+
+
+@pytest.mark.parametrize("m,k,n,depth,tile,levels", [(1024, 1024, 1024, 4, None, 3), (1536, 1024, 1280, 3, None, 2),
+                                                     (1024, 1024, 1024, 3, 8, 3), (1024, 1024, 1024, 3, 9, 3)])
+def test_tree_adds_poisoned_workspace(fastmm, monkeypatch, m, k, n, depth, tile, levels):
+    # The workspace is filled with NaN before the call: S / T cells that the
+    # grouped pass does not write must never be read.
+    monkeypatch.setenv("FASTMM_POISON", "1")
+    A, B = uniform(5701 + m, m, k), uniform(5702 + n, k, n)
+    Ad, Bd = dev(A), dev(B)
+    got, st = _run(fastmm, monkeypatch, levels, m, k, n, Ad, Bd, depth, 32, tile)
+    assert st["depth"] == depth
+    assert np.isfinite(got).all()
+    ref, _ = _run(fastmm, monkeypatch, 1, m, k, n, Ad, Bd, depth, 32, tile)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
