@@ -57,7 +57,8 @@ std::string signature(const Schedule& s) {
     o << "p" << (const void*)s.d_post[l] << ',' << s.post[l].size() << ',' << blocks_post(s.post[l])
       << ',' << (int)s.vec_post[l] << ';';
   for (const auto& t : s.trees)
-    o << "t" << t.kind << ',' << t.level << ',' << t.levels << ',' << (const void*)t.d_nodes << ','
+    o << "t" << t.kind << ',' << t.level << ',' << t.levels << ',' << t.width << ',' << t.clip << ','
+      << (const void*)t.d_nodes << ','
       << t.nodes.size() << ',' << t.blocks << ';';
   for (int fmt = 0; fmt < 2; ++fmt)
     for (int side = 0; side < 2; ++side)

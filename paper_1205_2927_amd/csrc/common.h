@@ -110,25 +110,28 @@ struct PostAddNode {
 };
 
 // One node of a multi-level addition launch: L consecutive levels of the
-// recursion (L = 2 or 3) in one pass, for subtrees whose quadrant splits are
-// exact at every one of those levels (no clipped quadrant anywhere).  The
-// top node's operand (or product) is then a 2^L x 2^L grid of equal cells of
-// br x bc elements, and every S, T and P of the levels in between is a grid
+// recursion (L = 2 or 3) in one pass, for subtrees in which every level is
+// exactly twice the next (the engine's split rule makes them so below the
+// top of the recursion).  The top node's operand (or product) is then a
+// 2^L x 2^L grid of equal cells of br x bc elements -- virtually: only its
+// first vrows x vcols elements exist, the rest read as zero and are not
+// written -- and every S, T and P of the levels in between is a dense grid
 // of the same cells, so one thread can follow one element position through
 // all L levels.
-//   pre-additions: src = the top node's operand (leading dimension ld);
-//     dst[j] = the S (T) blocks of level l0 + j, all nodes of that level,
-//     node-major, four dense blocks per node (the level-wise layout);
-//     node = index of the top node within level l0.
+//   pre-additions: src = the top node's operand (leading dimension ld,
+//     vrows x vcols valid); dst[j] = the S (T) blocks of level l0 + j, all
+//     nodes of that level, node-major, four dense blocks per node (the
+//     level-wise layout); node = index of the top node within level l0.
 //   post-additions: src = the 7^L products of level l0 + L under this node
 //     (consecutive dense br x bc blocks); dst[0] = the node's product
-//     (leading dimension ld).
+//     (leading dimension ld), never clipped: vrows x vcols is the whole grid.
 struct TreeNode {
   const float* src;
   float* dst[3];
   int64_t ld;
   int64_t node;
   int32_t br, bc;
+  int32_t vrows, vcols;
   int32_t block_begin;
   int32_t pad_;
 };
@@ -323,16 +326,19 @@ void launch_postadd(const PostAddNode* d_nodes, int nnodes, int total_blocks, bo
 
 // Multi-level additions over TreeNode descriptors.  kind 0: A-side
 // pre-additions, 1: B-side pre-additions, 2: post-additions; levels 2 or 3.
-// Each thread takes tree_width(levels) consecutive elements of a cell: four
-// (16-byte accesses) for two levels; one for three, whose 64 inputs (pre) or
-// 64 outputs (post) per element already fill the registers.
+// Each thread takes `width` consecutive elements of a cell: four (16-byte
+// accesses; two levels, aligned rows and cells only) or one (three levels,
+// whose 64 inputs (pre) or 64 outputs (post) per element already fill the
+// registers, and any misaligned case).
 constexpr int kMaxTreeLevels = 3;
-constexpr int tree_width(int levels) { return levels >= 3 ? 1 : 4; }
-inline int64_t tree_blocks_for(int levels, int64_t br, int64_t bc) {
-  const int64_t groups = br * (bc / tree_width(levels));
+inline int tree_width(int levels, bool aligned) { return levels == 2 && aligned ? 4 : 1; }
+inline int64_t tree_blocks_for(int width, int64_t br, int64_t bc) {
+  const int64_t groups = br * (bc / width);
   return (groups + kAddThreadsPerBlock - 1) / kAddThreadsPerBlock;
 }
-void launch_tree_add(int kind, int levels, const TreeNode* d_nodes, int nnodes, int total_blocks,
-                     hipStream_t stream);
+// clip: some top operand of a pre-addition launch is clipped (post-addition
+// launches never are).
+void launch_tree_add(int kind, int levels, int width, bool clip, const TreeNode* d_nodes, int nnodes,
+                     int total_blocks, hipStream_t stream);
 
 }  // namespace fastmm

@@ -171,7 +171,8 @@ std::vector<Dims> level_dims(const Problem& p) {
   std::vector<Dims> dims{{p.M, p.K, p.N}};
   for (int l = 0; l < p.depth; ++l) {
     const Dims& d = dims.back();
-    dims.push_back({split_half(d.m), split_half(d.k), split_half(d.n)});
+    const int left = p.depth - l;
+    dims.push_back({split_at(d.m, left), split_at(d.k, left), split_at(d.n, left)});
   }
   return dims;
 }
@@ -231,9 +232,9 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
   const char* te = std::getenv("FASTMM_TREE_ADDS");
   const int tree_max = (te && te[0] >= '0' && te[0] <= '9') ? std::min(kMaxTreeLevels, std::atoi(te))
                                                             : kMaxTreeLevels;
-  auto add_tree = [&](int kind, int level, int levels, const TreeNode& tn) {
+  auto add_tree = [&](int kind, int level, int levels, int width, const TreeNode& tn) {
     for (auto& t : s.trees)
-      if (t.kind == kind && t.level == level && t.levels == levels) {
+      if (t.kind == kind && t.level == level && t.levels == levels && t.width == width) {
         t.nodes.push_back(tn);
         return;
       }
@@ -241,6 +242,7 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     t.kind = kind;
     t.level = level;
     t.levels = levels;
+    t.width = width;
     t.nodes.push_back(tn);
     s.trees.push_back(std::move(t));
   };
@@ -328,22 +330,26 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     }
     // Group the levels from the bottom up: the deepest levels hold the most
     // nodes, so they gain most from sharing a pass.  g[l] = levels of the
-    // launch whose top level is l (1: level-wise), 0 inside a group.
-    auto full_pre = [](const PreAddNode& n) {
-      return n.top_rows == n.h_r && n.bot_rows == n.h_r && n.left_cols == n.h_c &&
-             n.right_cols == n.h_c && pre_vec_ok(n);
+    // launch whose top level is l (1: level-wise), 0 inside a group.  A
+    // group needs every level below its top exactly twice the next (the
+    // split rule gives that; the top node itself may be clipped).
+    // side 0: A's extents (m, k); 1: B's (k, n); 2: the products' (m, n).
+    auto exact = [&](int a, int b, int side) {
+      for (int j = a + 1; j < b; ++j) {
+        const Dims &x = dims[j], &y = dims[j + 1];
+        const bool ok = side == 0   ? (x.m == 2 * y.m && x.k == 2 * y.k)
+                        : side == 1 ? (x.k == 2 * y.k && x.n == 2 * y.n)
+                                    : (x.m == 2 * y.m && x.n == 2 * y.n);
+        if (!ok) return false;
+      }
+      return true;
     };
-    auto group_levels = [&](int top, const std::function<bool(int)>& level_ok) {
+    auto group_levels = [&](int top, const std::function<bool(int, int)>& group_ok) {
       std::vector<int> g(d, 1);
       int hi = top;
       while (hi > 0) {
         int L = std::min(tree_max, hi);
-        auto range_ok = [&](int a, int b) {
-          for (int l = a; l < b; ++l)
-            if (!level_ok(l)) return false;
-          return true;
-        };
-        while (L > 1 && !range_ok(hi - L, hi)) --L;
+        while (L > 1 && !group_ok(hi - L, L)) --L;
         L = std::max(L, 1);
         for (int j = hi - L; j < hi; ++j) g[j] = 0;
         g[hi - L] = L;
@@ -356,11 +362,8 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     auto pre_side = [&](int kind, std::vector<std::vector<PreAddNode>>& lv,
                         const std::vector<float*>& base, const std::vector<double>& by,
                         std::vector<std::vector<PreAddNode>>& out) {
-      const std::vector<int> g = group_levels(pre_top, [&](int l) {
-        if ((int64_t)lv[l].size() != pow7(l)) return false;
-        for (const auto& n : lv[l])
-          if (!full_pre(n)) return false;
-        return true;
+      const std::vector<int> g = group_levels(pre_top, [&](int l, int L) {
+        return (int64_t)lv[l].size() == pow7(l) && exact(l, l + L, kind);
       });
       for (int l = 0; l < d; ++l) {
         if (g[l] == 1) {
@@ -370,6 +373,9 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
           const int L = g[l];
           const Dims& cell = dims[l + L];
           const int64_t br = kind == 0 ? cell.m : cell.k, bc = kind == 0 ? cell.k : cell.n;
+          bool aligned = bc % 4 == 0;
+          for (const auto& n : lv[l]) aligned = aligned && aligned16(n.src) && n.ld % 4 == 0;
+          const int width = tree_width(L, aligned);
           // The top operand read once; of each S / T block of level l + j,
           // the 3^(L-1-j) cells that the levels below read as views.
           double cells = (double)(1 << (2 * L));
@@ -382,11 +388,13 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
             TreeNode tn{};
             tn.src = lv[l][x].src;
             tn.ld = lv[l][x].ld;
+            tn.vrows = lv[l][x].top_rows + lv[l][x].bot_rows;
+            tn.vcols = lv[l][x].left_cols + lv[l][x].right_cols;
             for (int j = 0; j < L; ++j) tn.dst[j] = base[l + j];
             tn.node = x;
             tn.br = (int32_t)br;
             tn.bc = (int32_t)bc;
-            add_tree(kind, l, L, tn);
+            add_tree(kind, l, L, width, tn);
           }
           s.add_bytes += (double)lv[l].size() * cells * 4.0 * (double)br * (double)bc;
         }
@@ -484,12 +492,11 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
                                         dims[l].n, dims[l].m, dims[l].n));
       }
     }
-    const std::vector<int> gp = group_levels(d, [&](int l) {
-      for (const auto& n : lvP[l])
-        if (!(n.top_rows == n.h_r && n.bot_rows == n.h_r && n.left_cols == n.h_c &&
-              n.right_cols == n.h_c && post_vec_ok(n)))
-          return false;
-      return true;
+    // A clipped C (the root's product) keeps the root's level to itself.
+    const bool c_clipped = d > 0 && (lvP[0][0].top_rows + lvP[0][0].bot_rows < 2 * lvP[0][0].h_r ||
+                                     lvP[0][0].left_cols + lvP[0][0].right_cols < 2 * lvP[0][0].h_c);
+    const std::vector<int> gp = group_levels(d, [&](int l, int L) {
+      return exact(l, l + L, 2) && !(l == 0 && c_clipped);
     });
     for (int l = d - 1; l >= 0; --l) {
       const Dims c = dims[l + 1];
@@ -501,15 +508,20 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
         const int L = gp[l];
         const Dims& cell = dims[l + L];
         const int64_t blocks = pow7(L);
+        bool aligned = cell.n % 4 == 0;
+        for (const auto& n : lvP[l]) aligned = aligned && aligned16(n.dst) && n.ld % 4 == 0;
+        const int width = tree_width(L, aligned);
         for (int64_t x = 0; x < (int64_t)lvP[l].size(); ++x) {
           TreeNode tn{};
           tn.src = P[l + L] + x * blocks * cell.m * cell.n;
           tn.dst[0] = lvP[l][x].dst;
           tn.ld = lvP[l][x].ld;
+          tn.vrows = lvP[l][x].top_rows + lvP[l][x].bot_rows;
+          tn.vcols = lvP[l][x].left_cols + lvP[l][x].right_cols;
           tn.node = x;
           tn.br = (int32_t)cell.m;
           tn.bc = (int32_t)cell.n;
-          add_tree(2, l, L, tn);
+          add_tree(2, l, L, width, tn);
         }
         s.add_bytes += (double)lvP[l].size() * (double)(blocks + (1 << (2 * L))) * 4.0 *
                        (double)cell.m * (double)cell.n;
@@ -556,8 +568,9 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
   for (auto& t : s.trees) {
     int64_t b = 0;
     for (auto& n : t.nodes) {
+      if (n.vrows < ((int64_t)n.br << t.levels) || n.vcols < ((int64_t)n.bc << t.levels)) t.clip = true;
       n.block_begin = (int32_t)b;
-      b += tree_blocks_for(t.levels, n.br, n.bc);
+      b += tree_blocks_for(t.width, n.br, n.bc);
     }
     if (b > INT32_MAX) throw Error(kNotSupported, "multi-level addition launch too large");
     t.blocks = (int)b;
@@ -657,7 +670,8 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
     if (bb) { launch_preadd(1, s.d_preB[l], (int)s.preB[l].size(), bb, s.vec_preB[l], L.stream); ++launches; }
     for (const auto& t : s.trees)
       if (t.kind < 2 && t.level == l && t.blocks > 0) {
-        launch_tree_add(t.kind, t.levels, t.d_nodes, (int)t.nodes.size(), t.blocks, L.stream);
+        launch_tree_add(t.kind, t.levels, t.width, t.clip, t.d_nodes, (int)t.nodes.size(), t.blocks,
+                        L.stream);
         ++launches;
       }
   }
@@ -716,7 +730,7 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
     if (bp) { launch_postadd(s.d_post[l], (int)s.post[l].size(), bp, s.vec_post[l], L.stream); ++launches; }
     for (const auto& t : s.trees)
       if (t.kind == 2 && t.level == l && t.blocks > 0) {
-        launch_tree_add(2, t.levels, t.d_nodes, (int)t.nodes.size(), t.blocks, L.stream);
+        launch_tree_add(2, t.levels, t.width, false, t.d_nodes, (int)t.nodes.size(), t.blocks, L.stream);
         ++launches;
       }
   }
@@ -836,14 +850,14 @@ size_t bfs_need(const Problem& p) {
 }
 
 size_t top_need(const Problem& p) {
-  const int64_t m2 = split_half(p.M), k2 = split_half(p.K), n2 = split_half(p.N);
+  const int64_t m2 = split_at(p.M, p.depth), k2 = split_at(p.K, p.depth), n2 = split_at(p.N, p.depth);
   return align_up((size_t)4 * m2 * k2 * 4, 256) + align_up((size_t)4 * k2 * n2 * 4, 256) +
          align_up((size_t)7 * m2 * n2 * 4, 256) + 3 * 256;
 }
 
 // Sub-product i (P1..P7 = 0..6) of p, with p's S, T and P blocks at S, T, P.
 Problem child_problem(const Problem& p, int i, float* S, float* T, float* P) {
-  const int64_t m2 = split_half(p.M), k2 = split_half(p.K), n2 = split_half(p.N);
+  const int64_t m2 = split_at(p.M, p.depth), k2 = split_at(p.K, p.depth), n2 = split_at(p.N, p.depth);
   const View a{p.A, p.lda, p.ar(), p.ac()}, b{p.B, p.ldb, p.br(), p.bc()};
   auto sv = [&](int j) { return View{S + j * m2 * k2, k2, m2, k2}; };
   auto tv = [&](int j) { return View{T + j * k2 * n2, n2, k2, n2}; };
@@ -905,7 +919,7 @@ void run_within(Library& L, const Problem& p, char* ws, size_t bytes, RunTotals&
   }
   if (p.depth == 0 || top_need(p) >= bytes)
     throw Error(kOutOfMemory, "workspace budget too small even for depth-first execution");
-  const int64_t m2 = split_half(p.M), k2 = split_half(p.K), n2 = split_half(p.N);
+  const int64_t m2 = split_at(p.M, p.depth), k2 = split_at(p.K, p.depth), n2 = split_at(p.N, p.depth);
   size_t off = 0;
   auto take = [&](size_t b) {
     char* q = ws + off;

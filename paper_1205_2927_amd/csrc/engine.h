@@ -31,6 +31,26 @@ inline int64_t split_half(int64_t m) {
   return h >= 64 ? (h + 3) / 4 * 4 : h;
 }
 
+// Leaf extent of a d-level split of m: ceil(m / 2^d), rounded up just
+// enough that every level's extent (2^j leaf extents) of 64 or more is a
+// multiple of 4: to a multiple of 4 from 64 on, to an even number from 32 on
+// when the level above it exists.  (The top level's bottom quadrant keeps
+// m - 2^(d-1) x leaf >= 1 rows.)
+inline int64_t leaf_extent(int64_t m, int d) {
+  const int64_t leaf = (m + (int64_t(1) << d) - 1) >> d;
+  const int64_t g = leaf >= 64 ? 4 : (d >= 2 && leaf >= 32) ? 2 : 1;
+  return (leaf + g - 1) / g * g;
+}
+
+// Quadrant extent at which the engine splits m when d levels remain
+// (d >= 1): 2^(d-1) leaf extents.  Every level below is then exactly twice
+// the next, so only the quadrants of the operands at the top of the
+// recursion can be clipped (their missing rows and columns are virtual
+// zeros), and several levels of additions can share one pass.  For d = 1
+// this is split_half(m); where repeated split_half is exact at every level
+// the two rules agree.
+inline int64_t split_at(int64_t m, int d) { return d <= 0 ? m : leaf_extent(m, d) << (d - 1); }
+
 // Stop rule: split iff levels remain and floor(min(m,k,n)/2) >= max(leaf,1).
 inline bool splits(int64_t m, int64_t k, int64_t n, int levels_left, int64_t leaf) {
   int64_t mn = m < k ? m : k;
@@ -94,7 +114,8 @@ struct Schedule {
   // number of levels; pre launches run with the level-wise ones of their
   // top level, post launches with the post-additions of their top level.
   struct TreeLaunch {
-    int kind = 0, level = 0, levels = 0, blocks = 0;
+    int kind = 0, level = 0, levels = 0, width = 1, blocks = 0;
+    bool clip = false;  // some top operand is clipped (pre-additions only)
     std::vector<TreeNode> nodes;
     const TreeNode* d_nodes = nullptr;
   };

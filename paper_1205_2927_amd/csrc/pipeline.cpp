@@ -114,10 +114,13 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   // operand keeps 16-byte aligned rows.  The split and all device-side
   // extents use K4 and N4; the copies move the K and N valid columns.
   const int64_t K4 = (K + 3) / 4 * 4, N4 = (N + 3) / 4 * 4;
-  const int64_t m2 = split_half(M), k2 = split_half(K4), n2 = split_half(N4);
+  // The top split: where the recursion continues below it, at the extent
+  // that keeps every lower level exactly halved (split_at).
+  const bool wino = depth >= 1;
+  auto top = [&](int64_t x) { return wino ? split_at(x, depth) : split_half(x); };
+  const int64_t m2 = top(M), k2 = top(K4), n2 = top(N4);
   const int64_t mb = M - m2, kb = K4 - k2, nb = N4 - n2;
   const int64_t kb_v = std::max<int64_t>(0, K - k2), nb_v = std::max<int64_t>(0, N - n2);
-  const bool wino = depth >= 1;
   const TileShape ts = tile_shape(tile);
 
   // ---- workspace layout (byte offsets into the arena)

@@ -4,11 +4,14 @@
 // thresholds found by experiment (Table 2 and the K0 / K1 operating points of
 // Section 3.2) and stops the recursion at a fixed size (Section 3.1).  Three
 // modes here:
-//   DEFAULT     the fixed rule: split while the leaf stays >= 1536, tile
+//   DEFAULT     the fixed rule: split while the leaf stays >= 1280, tile
 //               128x128 (the analogue of the paper's size thresholds and
 //               recursion point, set from measured Winograd-vs-classic
-//               crossovers on MI355X: the fastest depth leaves 1536..2432
-//               in every dimension for square n from 3072 to 19456); a
+//               crossovers on MI355X: with additions grouped over levels
+//               the fastest depth leaves 1024..2432 in every dimension for
+//               square n from 3072 to 22528, and 1280 is the cutoff that
+//               is never more than 3% off the fastest depth there while
+//               keeping n = 19456 at depth 3 (1216-wide leaves lose 6%)); a
 //               launch that would have fewer than 512 tiles of 128x128
 //               (under half the device's 1024 workgroup slots) takes 64x64
 //               tiles instead (n = 1024: 0.081 against 0.129 ms, 1536:
@@ -54,7 +57,7 @@ namespace {
 constexpr int kNParams = FASTMM_MLP_PARAMS;
 constexpr int64_t kMinLeaf = 128;   // smallest leaf extent a candidate may reach
 constexpr int kMaxDepth = 4;
-constexpr int64_t kDefaultLeaf = 1536;
+constexpr int64_t kDefaultLeaf = 1280;
 // Tiles the planner considers: one per macro-tile area (the area is the
 // model's tile feature), the best-measured variant of each.
 constexpr int kPlannerTiles[] = {kTile128x128, kTile128x64, kTile64x64, kTile256x128w8,
@@ -197,6 +200,31 @@ void upload_model(Library& L) {
   FASTMM_HIP(hipStreamSynchronize(L.stream));
 }
 
+// The fixed rule's tile for a depth-d product: 64x64 when the leaf launch
+// would have fewer than 512 tiles of 128x128 (under half the device's
+// workgroup slots), else 128x128.
+int rule_tile(int64_t M, int64_t N, int d) {
+  int64_t leaves = 1;
+  for (int l = 0; l < d; ++l) leaves *= 7;
+  const int64_t m = d ? leaf_extent(M, d) : M, n = d ? leaf_extent(N, d) : N;
+  const int64_t tiles = leaves * ((m + 127) / 128) * ((n + 127) / 128);
+  return tiles < 512 ? kTile64x64 : kTile128x128;
+}
+
+// The fixed rule: the deepest split whose leaves stay >= kDefaultLeaf, with
+// rule_tile's tile.
+std::pair<int, int> default_choice(int64_t M, int64_t N, int64_t K) {
+  const int d = effective_depth(M, N, K, 16, kDefaultLeaf);
+  return {d, rule_tile(M, N, d)};
+}
+
+// The model chooses the depth (each depth with rule_tile's tile: the rule's
+// tile choice is the measured one, while the network, trained on a few
+// dozen shapes, mispredicts tiles whose times differ by wave quantisation),
+// and departs from the fixed rule's depth only where it predicts at least
+// this gain.
+constexpr double kModelMargin = 1.05;
+
 fastmm_plan_t plan_model(Library& L, int64_t M, int64_t N, int64_t K) {
   ModelDev& D = model_dev();
   const auto cand = candidates(M, N, K);
@@ -209,9 +237,15 @@ fastmm_plan_t plan_model(Library& L, int64_t M, int64_t N, int64_t K) {
   mlp_forward(n, D.params, dX, dy, nullptr, L.stream);
   FASTMM_HIP(hipMemcpyAsync(y.data(), dy, n * 4, hipMemcpyDeviceToHost, L.stream));
   FASTMM_HIP(hipStreamSynchronize(L.stream));
-  int bi = 0;
-  for (int i = 1; i < n; ++i)
-    if (y[i] < y[bi]) bi = i;
+  const auto def = default_choice(M, N, K);
+  int bi = -1, di = -1;
+  for (int i = 0; i < n; ++i) {
+    if (cand[i].second != rule_tile(M, N, cand[i].first)) continue;
+    if (bi < 0 || y[i] < y[bi]) bi = i;
+    if (cand[i] == def) di = i;
+  }
+  if (bi < 0) bi = 0;
+  if (di >= 0 && (double)y[di] <= (double)y[bi] + std::log2(kModelMargin)) bi = di;
   return make_plan(cand[bi].first, cand[bi].second, std::exp2((double)y[bi]), FASTMM_PLAN_MODEL);
 }
 
@@ -227,15 +261,8 @@ int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_pl
     return kSuccess;
   }
   if (mode == FASTMM_PLAN_DEFAULT) {
-    const int d = effective_depth(M, N, K, 16, kDefaultLeaf);
-    int64_t m = M, n = N, leaves = 1;
-    for (int l = 0; l < d; ++l) {
-      m = split_half(m);
-      n = split_half(n);
-      leaves *= 7;
-    }
-    const int64_t tiles = leaves * ((m + 127) / 128) * ((n + 127) / 128);
-    *out = make_plan(d, tiles < 512 ? kTile64x64 : kTile128x128, -1.0, FASTMM_PLAN_DEFAULT);
+    const auto def = default_choice(M, N, K);
+    *out = make_plan(def.first, def.second, -1.0, FASTMM_PLAN_DEFAULT);
     out->leaf = kDefaultLeaf;
     return kSuccess;
   }

@@ -223,6 +223,17 @@ __device__ __forceinline__ void stw(float* p, const Vw<W>& x) {
   }
 }
 
+// Loads of a clipped top operand: elements outside the valid rows / columns
+// read as zero.
+template <int W>
+__device__ __forceinline__ Vw<W> ldw_valid(const float* p, bool rv, int64_t col, int64_t vcols) {
+  if (rv && col + W <= vcols) return ldw<W>(p);
+  Vw<W> r;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r.v[i] = (rv && col + i < vcols) ? p[i] : 0.f;
+  return r;
+}
+
 template <int W>
 __device__ __forceinline__ Vw<W> vadd(const Vw<W>& a, const Vw<W>& b) {
   Vw<W> r;
@@ -311,10 +322,11 @@ __device__ __forceinline__ void tree_pre(const Vw<W> (&X)[1 << J][1 << J], const
   }
 }
 
-template <int SIDE, int L>
+// CLIP: some top node of the launch is clipped (reads outside its valid
+// extent give zero); without it every read is a plain one.
+template <int SIDE, int L, int W, bool CLIP>
 __global__ void __launch_bounds__(kAddThreads)
 tree_preadd_kernel(const TreeNode* __restrict__ nodes, int nnodes) {
-  constexpr int W = tree_width(L);
   const TreeNode nd = nodes[find_node(nodes, nnodes, blockIdx.x)];
   const int cw = nd.bc / W;
   const int64_t g = (int64_t)(blockIdx.x - nd.block_begin) * kAddThreads + threadIdx.x;
@@ -326,7 +338,9 @@ tree_preadd_kernel(const TreeNode* __restrict__ nodes, int nnodes) {
   for (int u = 0; u < (1 << L); ++u)
 #pragma unroll
     for (int v = 0; v < (1 << L); ++v)
-      X[u][v] = ldw<W>(nd.src + ((int64_t)u * nd.br + r) * nd.ld + (int64_t)v * nd.bc + c);
+      X[u][v] = CLIP ? ldw_valid<W>(nd.src + ((int64_t)u * nd.br + r) * nd.ld + (int64_t)v * nd.bc + c,
+                                    (int64_t)u * nd.br + r < nd.vrows, (int64_t)v * nd.bc + c, nd.vcols)
+                     : ldw<W>(nd.src + ((int64_t)u * nd.br + r) * nd.ld + (int64_t)v * nd.bc + c);
   tree_pre<SIDE, L, 0, W>(X, nd, nd.node, r, c);
 }
 
@@ -382,10 +396,13 @@ __device__ __forceinline__ void tree_post(Vw<W> (&G)[1 << J][1 << J], const floa
   }
 }
 
-template <int L>
+// Every product below the root is a dense block, so a grouped launch never
+// writes a clipped product: the root's post-additions, when C is clipped,
+// stay with the single-level kernel.  (Masked stores here made the compiler
+// hoist all 7^L loads: 256 registers and spills for L = 3.)
+template <int L, int W>
 __global__ void __launch_bounds__(kAddThreads)
 tree_postadd_kernel(const TreeNode* __restrict__ nodes, int nnodes) {
-  constexpr int W = tree_width(L);
   const TreeNode nd = nodes[find_node(nodes, nnodes, blockIdx.x)];
   const int cw = nd.bc / W;
   const int64_t g = (int64_t)(blockIdx.x - nd.block_begin) * kAddThreads + threadIdx.x;
@@ -399,21 +416,36 @@ tree_postadd_kernel(const TreeNode* __restrict__ nodes, int nnodes) {
   for (int u = 0; u < (1 << L); ++u)
 #pragma unroll
     for (int v = 0; v < (1 << L); ++v)
-      stw(out + ((int64_t)u * nd.br + r) * nd.ld + (int64_t)v * nd.bc + c, G[u][v]);
+      stw<W>(out + ((int64_t)u * nd.br + r) * nd.ld + (int64_t)v * nd.bc + c, G[u][v]);
 }
 
-void launch_tree_add(int kind, int levels, const TreeNode* d_nodes, int nnodes, int total_blocks,
-                     hipStream_t stream) {
+template <int L, int W, bool CLIP>
+static void launch_tree_kind(int kind, dim3 grid, dim3 block, hipStream_t stream, const TreeNode* d,
+                             int n) {
+  if (kind == 0) hipLaunchKernelGGL((tree_preadd_kernel<0, L, W, CLIP>), grid, block, 0, stream, d, n);
+  else if (kind == 1) hipLaunchKernelGGL((tree_preadd_kernel<1, L, W, CLIP>), grid, block, 0, stream, d, n);
+  else hipLaunchKernelGGL((tree_postadd_kernel<L, W>), grid, block, 0, stream, d, n);
+}
+
+void launch_tree_add(int kind, int levels, int width, bool clip, const TreeNode* d_nodes, int nnodes,
+                     int total_blocks, hipStream_t stream) {
   if (nnodes <= 0 || total_blocks <= 0) return;
+  if (kind < 0 || kind > 2 || (kind == 2 && clip)) throw Error(kInvalidValue, "bad multi-level addition launch");
   dim3 grid(total_blocks), block(kAddThreads);
-  const int key = kind * 10 + levels;
+  const int key = levels * 10 + width;
   switch (key) {
-    case 2: hipLaunchKernelGGL((tree_preadd_kernel<0, 2>), grid, block, 0, stream, d_nodes, nnodes); break;
-    case 3: hipLaunchKernelGGL((tree_preadd_kernel<0, 3>), grid, block, 0, stream, d_nodes, nnodes); break;
-    case 12: hipLaunchKernelGGL((tree_preadd_kernel<1, 2>), grid, block, 0, stream, d_nodes, nnodes); break;
-    case 13: hipLaunchKernelGGL((tree_preadd_kernel<1, 3>), grid, block, 0, stream, d_nodes, nnodes); break;
-    case 22: hipLaunchKernelGGL((tree_postadd_kernel<2>), grid, block, 0, stream, d_nodes, nnodes); break;
-    case 23: hipLaunchKernelGGL((tree_postadd_kernel<3>), grid, block, 0, stream, d_nodes, nnodes); break;
+    case 24:
+      clip ? launch_tree_kind<2, 4, true>(kind, grid, block, stream, d_nodes, nnodes)
+           : launch_tree_kind<2, 4, false>(kind, grid, block, stream, d_nodes, nnodes);
+      break;
+    case 21:
+      clip ? launch_tree_kind<2, 1, true>(kind, grid, block, stream, d_nodes, nnodes)
+           : launch_tree_kind<2, 1, false>(kind, grid, block, stream, d_nodes, nnodes);
+      break;
+    case 31:
+      clip ? launch_tree_kind<3, 1, true>(kind, grid, block, stream, d_nodes, nnodes)
+           : launch_tree_kind<3, 1, false>(kind, grid, block, stream, d_nodes, nnodes);
+      break;
     default: throw Error(kInvalidValue, "bad multi-level addition launch");
   }
   FASTMM_HIP(hipGetLastError());

@@ -152,7 +152,7 @@ def _ld(x, ld):
     return max(1, int(x.stride(0)))
 
 
-def gemm(M, N, K, A, B, C, depth=0, leaf=1536, tile=None, lda=None, ldb=None, ldc=None):
+def gemm(M, N, K, A, B, C, depth=0, leaf=1280, tile=None, lda=None, ldb=None, ldc=None):
     """fastmm_gemm / fastmm_gemm_ex: C = A B.  Returns the status (raises on error)."""
     lib = load()
     if tile is None:
@@ -179,7 +179,7 @@ def gemm_raw(M, N, K, A, lda, B, ldb, C, ldc, depth, leaf, tile=None) -> int:
     return lib.fastmm_gemm_ex(M, N, K, A, lda, B, ldb, C, ldc, depth, leaf, tile)
 
 
-def matmul(A, B, depth=0, leaf=1536, tile=None, out=None):
+def matmul(A, B, depth=0, leaf=1280, tile=None, out=None):
     """Convenience: C = A @ B for 2-D FP32 tensors (same residency)."""
     import torch
     M, K = A.shape

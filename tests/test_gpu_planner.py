@@ -64,12 +64,12 @@ def test_mlp_adam_matches_oracle(fastmm):
 
 
 def test_default_rule(fastmm):
-    # deepest split whose leaf stays >= 1536 in every dimension; 64x64 tiles
+    # deepest split whose leaf stays >= 1280 in every dimension; 64x64 tiles
     # when the leaf launch would have fewer than 512 tiles of 128x128
-    for n, d, t in [(19456, 3, 0), (16384, 3, 0), (8192, 2, 0), (4096, 1, 0), (3072, 1, 0),
-                    (2560, 0, 3), (2048, 0, 3), (512, 0, 3)]:
+    for n, d, t in [(19456, 3, 0), (16384, 3, 0), (10240, 3, 0), (8192, 2, 0), (5632, 2, 0),
+                    (4096, 1, 0), (3072, 1, 0), (2560, 1, 0), (2048, 0, 3), (512, 0, 3)]:
         p = fastmm.plan(n, n, n, fastmm.PLAN_DEFAULT)
-        assert (p.depth, p.leaf, p.tile, p.source) == (d, 1536, t, fastmm.PLAN_DEFAULT), n
+        assert (p.depth, p.leaf, p.tile, p.source) == (d, 1280, t, fastmm.PLAN_DEFAULT), n
     p = fastmm.plan(19456, 12288, 16384, fastmm.PLAN_DEFAULT)  # leaves 2432 x 1536 x 2048
     assert p.depth == 3
 
@@ -123,7 +123,7 @@ def test_auto_depth_product_is_correct(fastmm):
     C = torch.empty((n, n), device="cuda")
     fastmm.set_plan_mode(fastmm.PLAN_DEFAULT)
     fastmm.gemm(n, n, n, dev(A), dev(B), C, depth=fastmm.AUTO)
-    assert fastmm.get_stats()["depth"] == 0  # 1536 / 2 = 768 < 1024
+    assert fastmm.get_stats()["depth"] == 0  # 1536 / 2 = 768 < 1280
     assert checks.rel_frob(host(C), classic.gemm(A, B)) < 1e-4
 
 

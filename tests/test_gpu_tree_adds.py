@@ -60,17 +60,23 @@ def test_tree_adds_two_level_groups(fastmm, monkeypatch):
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
 
 
-@pytest.mark.parametrize("m,k,n,depth", [(520, 512, 512, 2), (512, 516, 512, 3), (512, 512, 508, 3)])
-def test_tree_adds_skip_inexact_splits(fastmm, monkeypatch, m, k, n, depth):
-    # A split that is not exact (a clipped quadrant) keeps that operand's
-    # levels level-wise; the result is still the level-wise one.
+@pytest.mark.parametrize("m,k,n,depth", [(520, 512, 512, 2), (512, 516, 512, 3), (512, 512, 508, 3),
+                                         (1000, 1000, 1000, 3), (1001, 999, 1003, 2), (6015, 517, 1234, 3)])
+def test_tree_adds_clipped_top(fastmm, monkeypatch, m, k, n, depth):
+    # Extents that do not halve exactly: the split rule places the leaf
+    # first, so only the top node's quadrants are clipped; the grouped
+    # pre-addition pass reads the missing rows and columns as zero (one
+    # launch per side).  A clipped C keeps the root's post-additions in the
+    # single-level kernel, the levels below it grouped: 4 or 5 launches.
     A, B = uniform(5301 + m, m, k), uniform(5302 + n, k, n)
     Ad, Bd = dev(A), dev(B)
     ref, st1 = _run(fastmm, monkeypatch, 1, m, k, n, Ad, Bd, depth, 16)
     got, st3 = _run(fastmm, monkeypatch, 3, m, k, n, Ad, Bd, depth, 16)
     say(f"  {m}x{k}x{n} d{depth}: launches {st1['launches']} -> {st3['launches']}")
-    assert st3["launches"] <= st1["launches"]
+    assert st1["depth"] == st3["depth"] == depth
+    assert st1["launches"] == 3 * depth + 1 and st3["launches"] in (4, 5)
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    assert checks.rel_frob(got, classic.gemm(A, B)) <= 1e-4
 
 
 @pytest.mark.parametrize("tile", [8, 9])

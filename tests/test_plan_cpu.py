@@ -1,6 +1,6 @@
 """The planner's fixed rule and the workspace it reports, on the host (the
 DEFAULT mode needs no device): depth from the stop rule with leaf cutoff
-1536, 64x64 tiles for launches of fewer than 512 tiles of 128x128, and the
+1280, 64x64 tiles for launches of fewer than 512 tiles of 128x128, and the
 level-wise schedule's temporaries against their closed form."""
 import pytest
 
@@ -12,11 +12,12 @@ def lib():
     fastmm.load()
 
 
-@pytest.mark.parametrize("n,depth,tile", [(19456, 3, 0), (16384, 3, 0), (8192, 2, 0), (4096, 1, 0),
-                                          (3072, 1, 0), (2560, 0, 3), (2048, 0, 3), (512, 0, 3)])
+@pytest.mark.parametrize("n,depth,tile", [(19456, 3, 0), (16384, 3, 0), (10240, 3, 0), (8192, 2, 0),
+                                          (5632, 2, 0), (4096, 1, 0), (3072, 1, 0), (2560, 1, 0),
+                                          (2048, 0, 3), (512, 0, 3)])
 def test_default_rule_on_host(n, depth, tile):
     p = fastmm.plan(n, n, n, fastmm.PLAN_DEFAULT)
-    assert (p.depth, p.leaf, p.tile, p.source) == (depth, 1536, tile, fastmm.PLAN_DEFAULT)
+    assert (p.depth, p.leaf, p.tile, p.source) == (depth, 1280, tile, fastmm.PLAN_DEFAULT)
 
 
 def _closed_form_temp_bytes(n, d):
@@ -44,5 +45,6 @@ def test_plan_workspace_grows_with_padding():
     # aligned size's own temporaries
     a = fastmm.plan(6016, 6016, 6016, fastmm.PLAN_DEFAULT)
     b = fastmm.plan(6015, 6015, 6015, fastmm.PLAN_DEFAULT)
-    assert a.depth == b.depth == 1
-    assert b.workspace_bytes >= _closed_form_temp_bytes(6016, 1) * 6015 // 6016
+    assert a.depth == b.depth == 2
+    assert a.workspace_bytes == _closed_form_temp_bytes(6016, 2)
+    assert b.workspace_bytes >= _closed_form_temp_bytes(6016, 2) * 6015 // 6016
