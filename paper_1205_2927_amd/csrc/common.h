@@ -4,7 +4,8 @@
 // "valid" extent: elements outside it read as zero.  That is how odd extents
 // follow the paper's quadrant split (equation (1), Section 3.1: quadrant 0 is
 // ceil(m/2) x ceil(n/2), quadrant 3 floor(m/2) x floor(n/2)) while every
-// quadrant of one level keeps the same ceil-sized virtual shape.
+// quadrant of one level keeps the same virtual shape (the engine places the
+// split at or a little above ceil(m/2): split_at in engine.h).
 #pragma once
 
 #include <hip/hip_runtime.h>

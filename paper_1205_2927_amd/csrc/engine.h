@@ -21,11 +21,11 @@ struct Dims {
 // Half extent of equation (1): quadrant 0 takes ceil(m/2).
 inline int64_t half_up(int64_t m) { return (m + 1) / 2; }
 
-// Quadrant extent the engine splits at: ceil(m/2), rounded up to a multiple
-// of 4 once it reaches 64.  Every temporary's rows and every quadrant offset
-// then stay 16-byte aligned, so the leaves keep their 16-byte load path; the
-// few extra rows or columns are virtual zeros, like quadrant 1's padding
-// for an odd extent (quadrant 1 keeps m minus this, at least 61).
+// One step of the ceil(m/2) chain, rounded up to a multiple of 4 once it
+// reaches 64 (16-byte aligned rows and quadrant offsets; the extra rows or
+// columns are virtual zeros, quadrant 1 keeps m minus this, at least 61).
+// The stop rule's depth is decided on this chain, and the classic recursion
+// splits at it; the Winograd engine splits at split_at below.
 inline int64_t split_half(int64_t m) {
   const int64_t h = (m + 1) / 2;
   return h >= 64 ? (h + 3) / 4 * 4 : h;
