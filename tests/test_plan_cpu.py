@@ -48,3 +48,51 @@ def test_plan_workspace_grows_with_padding():
     assert a.depth == b.depth == 2
     assert a.workspace_bytes == _closed_form_temp_bytes(6016, 2)
     assert b.workspace_bytes >= _closed_form_temp_bytes(6016, 2) * 6015 // 6016
+
+
+def _leaf_first_extents(m, d):
+    # The engine's split rule for a d-level recursion: the leaf extent is
+    # ceil(m / 2^d), rounded up to a multiple of 4 when it is 64 or more and
+    # to an even number when it is 32 or more (d >= 2), so that every level's
+    # extent of 64 or more is a multiple of 4; level l >= 1 is 2^(d-l) leaves.
+    leaf = -(-m // 2 ** d)
+    g = 4 if leaf >= 64 else (2 if d >= 2 and leaf >= 32 else 1)
+    leaf = -(-leaf // g) * g
+    return [m] + [leaf << (d - l) for l in range(1, d + 1)]
+
+
+def _leaf_first_temp_bytes(M, N, K, d):
+    # S and T blocks of levels 0..d-1 and products of levels 1..d, each
+    # level's array 256-byte aligned (64 floats).
+    al = lambda f: -(-f // 64) * 64
+    m, k, n = (_leaf_first_extents(x, d) for x in (M, K, N))
+    floats = 0
+    for l in range(d):
+        floats += al(7 ** l * 4 * m[l + 1] * k[l + 1]) + al(7 ** l * 4 * k[l + 1] * n[l + 1])
+    for l in range(1, d + 1):
+        floats += al(7 ** l * m[l] * n[l])
+    return 4 * floats
+
+
+@pytest.mark.parametrize("M,N,K", [(10004, 10004, 10004), (14004, 14004, 14004), (6015, 6015, 6015),
+                                   (12031, 9000, 7777), (19456, 19456, 19456)])
+def test_plan_workspace_follows_leaf_first_split(M, N, K):
+    # Extents that do not halve exactly: every level below the top is exactly
+    # twice the next (K and N first rounded up to 4, as staged operands are).
+    p = fastmm.plan(M, N, K, fastmm.PLAN_DEFAULT)
+    assert p.depth >= 1
+    K4, N4 = -(-K // 4) * 4, -(-N // 4) * 4
+    assert p.workspace_bytes == _leaf_first_temp_bytes(M, N4, K4, p.depth)
+
+
+def test_leaf_first_extents_keep_the_bottom_quadrant():
+    # the top split leaves a non-empty bottom quadrant, covers ceil(m/2), and
+    # every extent of 64 or more is a multiple of 4
+    for m in range(2, 5000, 7):
+        for d in range(1, 6):
+            if (m >> (d - 1)) < 2:
+                continue
+            e = _leaf_first_extents(m, d)
+            assert (m + 1) // 2 <= e[1] < m
+            assert all(x % 4 == 0 for x in e[1:] if x >= 64)
+            assert all(e[l] == 2 * e[l + 1] for l in range(1, d))
