@@ -149,3 +149,23 @@ def test_tree_adds_poisoned_workspace(fastmm, monkeypatch, m, k, n, depth, tile,
     assert np.isfinite(got).all()
     ref, _ = _run(fastmm, monkeypatch, 1, m, k, n, Ad, Bd, depth, 32, tile)
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def test_tree_adds_batched_mixed_widths_and_clipping(fastmm, monkeypatch):
+    # One batch whose level-0 launches mix 16-byte and 4-byte cells (C with a
+    # leading dimension that is not a multiple of 4 takes the narrow form),
+    # clipped and unclipped top operands: every problem must equal, bit for
+    # bit, the same product computed alone one level per launch.
+    shapes = [(1024, 1024, 1024, 2), (1001, 999, 1003, 2), (768, 640, 896, 2), (1000, 1000, 1000, 3),
+              (1024, 512, 768, 3)]
+    As = [dev(uniform(5800 + 2 * i, m, k)) for i, (m, k, n, d) in enumerate(shapes)]
+    Bs = [dev(uniform(5801 + 2 * i, k, n)) for i, (m, k, n, d) in enumerate(shapes)]
+    Cs = [empty_dev(m, n) for (m, k, n, d) in shapes]
+    monkeypatch.setenv("FASTMM_TREE_ADDS", "3")
+    fastmm.gemm_batched(As, Bs, Cs, depth=[d for (_, _, _, d) in shapes], leaf=[1] * len(shapes))
+    got = [host(C) for C in Cs]
+    monkeypatch.setenv("FASTMM_TREE_ADDS", "1")
+    for i, ((m, k, n, d), A, B) in enumerate(zip(shapes, As, Bs)):
+        C = empty_dev(m, n)
+        fastmm.gemm(m, n, k, A, B, C, depth=d, leaf=1)
+        assert np.array_equal(got[i].view(np.uint32), host(C).view(np.uint32)), f"problem {i}"
