@@ -178,6 +178,8 @@ def main():
                     help="skip the addition-kernel and classic-recursion context")
     ap.add_argument("--no-shards", action="store_true",
                     help="skip one GPU's share of the sharded product")
+    ap.add_argument("--no-rect", action="store_true",
+                    help="skip the rectangular 19456 x 16384 x 12288 context block")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-problem batched context (uneven shapes)")
     ap.add_argument("--pinned-headline", action="store_true",
@@ -394,6 +396,30 @@ def main():
                             "effective_GFLOPS": 2.0 * sm * sn * K / min(ts) / 1e9}
         log(f"bench: shard shapes {shards}")
 
+    # The paper-scale rectangular product, M = 19456, K = 16384, N = 12288,
+    # with operands in pinned host memory (transfers timed) at depths 2-4 and
+    # plain, and the same shape with operands in HBM; strided views of the
+    # square operands.
+    rect = None
+    if (n == 19456 and not args.no_rect and not args.pinned_headline and not args.no_pinned
+            and not args.no_device_context):
+        rm, rk, rn = 19456, 16384, 12288
+        rect = {"M": rm, "N": rn, "K": rk, "pinned_ms": {}, "device_ms": {}}
+        rf = 2.0 * rm * rn * rk
+        for where, (a, b, c) in (("pinned_ms", (hA[:, :rk], hB[:rk, :rn], hC[:, :rn])),
+                                 ("device_ms", (A[:, :rk], B[:rk, :rn], C[:, :rn]))):
+            for d in (0, 2, 3, 4):
+                fn = lambda: fastmm.gemm(rm, rn, rk, a, b, c, depth=d, leaf=1)
+                tot, ts = time_calls(fn, 2, 1)
+                assert fastmm.get_stats()["depth"] == d
+                rect[where][str(d)] = 1e3 * min(ts)
+        for where in ("pinned", "device"):
+            t = rect[where + "_ms"]
+            bd = min(("2", "3", "4"), key=lambda k: t[k])
+            rect[where + "_best"] = {"depth": int(bd), "effective_GFLOPS": rf / (t[bd] * 1e-3) / 1e9,
+                                     "speedup_vs_plain": t["0"] / t[bd]}
+        log(f"bench: rectangular {rect}")
+
     batched = None
     if not args.no_batched and not args.pinned_headline:
         batched = batched_context(fastmm, torch)
@@ -436,7 +462,7 @@ def main():
         "depth_probe_ms": {str(k): 1e3 * v for k, v in probe.items()},
         "phases": phases, "classic_recursion": classic, "precision_forms": precision,
         "pinned_host": pinned,
-        "batched": batched, "shards": shards, "parity": parity,
+        "batched": batched, "shards": shards, "rectangular": rect, "parity": parity,
     }
     print(json.dumps(out), flush=True)
 
