@@ -169,3 +169,25 @@ def test_tree_adds_batched_mixed_widths_and_clipping(fastmm, monkeypatch):
         C = empty_dev(m, n)
         fastmm.gemm(m, n, k, A, B, C, depth=d, leaf=1)
         assert np.array_equal(got[i].view(np.uint32), host(C).view(np.uint32)), f"problem {i}"
+
+
+def test_tree_adds_random_shapes(fastmm, monkeypatch):
+    # Seeded random extents in [1, 700] and depths 1-4 (as deep as the stop
+    # rule allows with leaf 1): clipped tops, narrow and wide cells, staged
+    # operands.  Integer operands in [-2, 2]: the oracle's certificate shows
+    # every intermediate of these seeds to be an exact FP32 integer (far
+    # below 2^24), so both schedules must equal the int64 product.
+    import synthgen
+    ext = synthgen.int_range(5901, 40, 3, 1, 700).astype(np.int64)
+    dep = synthgen.int_range(5902, 40, 1, 1, 4)[:, 0].astype(np.int64)
+    for i in range(40):
+        m, k, n = (int(x) for x in ext[i])
+        depth = int(dep[i])
+        A = synthgen.int_range(5903 + i, m, k, -2, 2)
+        B = synthgen.int_range(6003 + i, k, n, -2, 2)
+        Ad, Bd = dev(A), dev(B)
+        ref, st1 = _run(fastmm, monkeypatch, 1, m, k, n, Ad, Bd, depth, 1)
+        got, st3 = _run(fastmm, monkeypatch, 3, m, k, n, Ad, Bd, depth, 1)
+        say(f"  {m}x{k}x{n} depth {st3['depth']}: launches {st1['launches']} -> {st3['launches']}")
+        assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (m, k, n, depth)
+        assert np.array_equal(got.astype(np.int64), classic.gemm(A.astype(np.int64), B.astype(np.int64)))
