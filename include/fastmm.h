@@ -57,7 +57,9 @@ enum { FASTMM_AUTO = -1 }; /* depth < 0 (or tile < 0): let the planner choose */
 enum {
   FASTMM_PLAN_DEFAULT = 0,   /* fixed rule: deepest split with leaf >= 1280; 64x64
                                 tiles when 128x128 ones would number under 512 */
-  FASTMM_PLAN_MODEL = 1,     /* learned cost model; falls back to EXHAUSTIVE */
+  FASTMM_PLAN_MODEL = 1,     /* learned cost model chooses the depth (each with the
+                                fixed rule's tile), keeping DEFAULT's unless it
+                                predicts a 5% gain; untrained: EXHAUSTIVE */
   FASTMM_PLAN_EXHAUSTIVE = 2 /* time every candidate on the device, cache it */
 };
 
@@ -160,7 +162,8 @@ int fastmm_rmul(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, co
  * leading dimensions (same rules as fastmm_gemm, per problem).  depth == NULL:
  * each problem's depth/tile from the planner (mode set by
  * fastmm_set_plan_mode); leaf == NULL: default cutoff 1280.  Every level of
- * every problem is one grouped launch; the launch sequence is captured once
+ * every problem is one grouped launch (or one per group of up to three levels,
+ * the additions of levels that halve exactly); the launch sequence is captured once
  * per set of shapes and plans into a HIP graph and replayed.  All problems are
  * validated first: on error nothing is written. */
 int fastmm_gemm_batched(int count, const int64_t* M, const int64_t* N, const int64_t* K,
