@@ -8,8 +8,10 @@
 // (breadth first): every level is one pre-addition launch per operand, all
 // 7^d leaves are one grouped MFMA launch, and every level is one
 // post-addition launch, so a depth-d product costs 2d + d + 1 launches
-// instead of thousands.  Quadrants that are plain sub-blocks (A11, A12, A22,
-// B11, B21, B22) are strided views, never copies.
+// instead of thousands; levels that halve exactly share their additions'
+// launches, up to three levels each (4 launches at depth 3).  Quadrants that
+// are plain sub-blocks (A11, A12, A22, B11, B21, B22) are strided views,
+// never copies.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
