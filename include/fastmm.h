@@ -159,7 +159,10 @@ int fastmm_rmul(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, co
                 int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf, int tile);
 
 /* count independent products C[i] = A[i]*B[i], each with its own extents and
- * leading dimensions (same rules as fastmm_gemm, per problem).  depth == NULL:
+ * leading dimensions (same rules as fastmm_gemm, per problem).  The paper
+ * runs two independent products at once, one per GPU, to fill its devices
+ * (Section 4.2, the two-GPU measurement); here many uneven products share
+ * each launch of one device.  depth == NULL:
  * each problem's depth/tile from the planner (mode set by
  * fastmm_set_plan_mode); leaf == NULL: default cutoff 1280.  Every level of
  * every problem is one grouped launch (or one per group of up to three levels,
@@ -194,8 +197,18 @@ int fastmm_planner_train(int epochs, int batch, float lr, uint64_t seed, float* 
 /* Number of timing records in the planner's database. */
 int64_t fastmm_planner_records(void);
 
-/* Run all kernels on this HIP stream (a hipStream_t; NULL: the library's own
- * stream, created at default priority). */
+/* The paper keeps, per device, an "MM queue": the device's memory context,
+ * its buffers, its compiled kernels and the command queue every product is
+ * issued on, created once and reused by every call (Section 3.3).  Here the
+ * library's state plays that role: one workspace, pinned staging, cached
+ * graphs and a command stream.
+ *
+ * Run all kernels on this HIP stream (a hipStream_t; NULL: the library's own
+ * stream, created at default priority).  The call first drains the stream in
+ * use; later calls are ordered after any work the caller queued on the new
+ * stream before them, and still return only when their own work on it is
+ * done.  The caller keeps ownership of the stream and must not destroy it
+ * while it is set. */
 int fastmm_set_stream(void* hip_stream);
 
 /* Record HIP events per phase in every later call (fastmm_get_stats). */
@@ -204,11 +217,16 @@ int fastmm_set_profiling(int on);
 /* Structure counts and phase times of the last successful product call. */
 int fastmm_get_stats(fastmm_stats_t* out);
 
-/* Message of the calling thread's last error ("" if none).  Valid until the
- * thread's next fastmm call. */
+/* Message of the calling thread's last error ("" if none): what failed in
+ * the MM queue's last command (Section 3.3), e.g. the HIP error string of a
+ * failed copy or launch.  Valid until the thread's next fastmm call. */
 const char* fastmm_get_last_error(void);
 
-/* Release workspace, staging buffers, graphs and the library stream. */
+/* Tear the MM queue down (Section 3.3 builds it once before any product):
+ * drain the stream, release the workspace, the pinned staging, the cached
+ * graphs, the events and the library's own streams, and forget a stream set
+ * by fastmm_set_stream.  The next call builds everything again; calling it
+ * twice, or before any other call, does nothing. */
 void fastmm_finalize(void);
 
 /* ---- Kernel-level entry points (device pointers only), for verification of

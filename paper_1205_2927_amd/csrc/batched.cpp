@@ -27,7 +27,11 @@ namespace {
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct GraphCache {
-  std::map<std::string, hipGraphExec_t> execs;
+  struct Entry {
+    hipGraphExec_t exec;
+    int launches;  // kernel launches the captured schedule holds
+  };
+  std::map<std::string, Entry> execs;
   int64_t captures = 0, replays = 0;
 };
 
@@ -90,16 +94,16 @@ int launch_graphed(Library& L, Schedule& s, bool& replayed) {
     (void)hipGraphDestroy(graph);
     FASTMM_HIP(e);
     if (G.execs.size() >= 32) {  // bound the cache
-      (void)hipGraphExecDestroy(G.execs.begin()->second);
+      (void)hipGraphExecDestroy(G.execs.begin()->second.exec);
       G.execs.erase(G.execs.begin());
     }
-    it = G.execs.emplace(key, exec).first;
+    it = G.execs.emplace(key, GraphCache::Entry{exec, s.launches}).first;
     ++G.captures;
   } else {
     ++G.replays;
   }
-  FASTMM_HIP(hipGraphLaunch(it->second, L.stream));
-  return s.launches;
+  FASTMM_HIP(hipGraphLaunch(it->second.exec, L.stream));
+  return it->second.launches;
 }
 
 void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const int64_t* K,
@@ -264,7 +268,7 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
 }  // namespace
 
 void destroy_graphs() {
-  for (auto& kv : graphs().execs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : graphs().execs) (void)hipGraphExecDestroy(kv.second.exec);
   graphs().execs.clear();
 }
 

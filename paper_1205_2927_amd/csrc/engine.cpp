@@ -947,6 +947,9 @@ void run_within(Library& L, const Problem& p, char* ws, size_t bytes, RunTotals&
   FASTMM_HIP(hipStreamSynchronize(L.stream));  // the pinned block is reused below
   rt.launches += 2;
   for (int i = 0; i < 7; ++i) run_within(L, child_problem(p, i, S, T, P), ws + off, bytes - off, rt);
+  // A child may have grown (reallocated) the pinned block for its own
+  // descriptors: take its current address again.
+  host = ensure_pinned(L, 3 * 256);
   std::memcpy(host + 512, &np, sizeof(np));
   FASTMM_HIP(hipMemcpyAsync(dnodes + 512, host + 512, sizeof(np), hipMemcpyHostToDevice, L.stream));
   launch_postadd(reinterpret_cast<const PostAddNode*>(dnodes + 512), 1,

@@ -177,6 +177,15 @@ def shapes_loguniform(seed: int, count: int, lo: int = 256, hi: int = 6144,
     return r.reshape(count, 3)
 
 
+def batch_seeds(config: int, i: int) -> tuple[int, int]:
+    """Seeds of the A and B operands of problem ``i`` of a batched workload
+    of configuration ``config``: (1001 + config) * 1000 + i and
+    (2001 + config) * 1000 + i (disjoint for i < 1000)."""
+    if not 0 <= i < 1000:
+        raise ValueError("problem index out of range")
+    return (1001 + config) * 1000 + i, (2001 + config) * 1000 + i
+
+
 def signs_pm1(seed: int, count: int) -> np.ndarray:
     """``count`` values in {-1.0, +1.0} (float64), from bit 63 of the stream."""
     z = stream(seed, 0, count)

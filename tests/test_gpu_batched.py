@@ -1,12 +1,17 @@
 """fastmm_gemm_batched: uneven problems in one level-wise schedule, captured
-into a HIP graph and replayed.  Each problem must equal, bit for bit, the
-same product computed alone by fastmm_gemm with the same plan."""
+into a HIP graph and replayed.  Every problem is checked against the oracle
+(the FP64-accumulated classic product: relative Frobenius error <= 1e-4 on
+uniform inputs, bit for bit on certified integers), and must also equal, bit
+for bit, the same product computed alone by fastmm_gemm with the same plan."""
 import numpy as np
 import pytest
 
 import synthgen
 from oracle import checks, classic
-from tests.gpu_util import dev, empty_dev, host, say, uniform
+from oracle import winograd as W
+from tests.gpu_util import dev, empty_dev, host, ints, say, uniform
+
+TOL = 1e-4
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +51,30 @@ def test_batched_equals_single_calls_and_replays(fastmm):
         torch.cuda.synchronize()
         refs = _singles(fastmm, SHAPES, As, Bs)
         for i, (C, ref) in enumerate(zip(Cs, refs)):
-            assert np.array_equal(host(C), ref), f"call {call} problem {i}"
+            got = host(C)
+            assert np.array_equal(got, ref), f"call {call} problem {i}"
+            err = checks.rel_frob(got, classic.gemm(host(As[i]), host(Bs[i])))
+            assert err <= TOL, f"call {call} problem {i}: {err}"
+
+
+def test_batched_certified_integers_exact(fastmm):
+    # Entries in {-1, 0, 1}: the oracle's integer certificate shows every
+    # intermediate of the recursion is an integer below 2^24, so every FP32
+    # step is exact and each batched result must equal the exact product.
+    shapes = SHAPES + [(1030, 770, 514, 3), (300, 900, 260, 2)]
+    As = [dev(ints(3400 + 3 * i, m, k)) for i, (m, k, n, d) in enumerate(shapes)]
+    Bs = [dev(ints(3401 + 3 * i, k, n)) for i, (m, k, n, d) in enumerate(shapes)]
+    Cs = [empty_dev(m, n) for (m, k, n, d) in shapes]
+    fastmm.gemm_batched(As, Bs, Cs, depth=[d for (_, _, _, d) in shapes], leaf=[1] * len(shapes))
+    assert fastmm.get_stats()["depth"] == 3
+    for i, (m, k, n, d) in enumerate(shapes):
+        A = host(As[i]).astype(np.int64)
+        B = host(Bs[i]).astype(np.int64)
+        cert = W.Certificate()
+        exact = W.winograd(A, B, d, 1, cert)
+        assert cert.exact_in_fp32, i
+        assert np.array_equal(exact, classic.gemm(A, B))
+        assert np.array_equal(host(Cs[i]).astype(np.int64), exact), f"problem {i} {m}x{k}x{n} d{d}"
 
 
 def test_batched_new_buffers_same_shapes(fastmm):
@@ -57,8 +85,9 @@ def test_batched_new_buffers_same_shapes(fastmm):
         Cs = [empty_dev(m, n) for (m, k, n, d) in SHAPES]
         fastmm.gemm_batched(As, Bs, Cs, depth=depths, leaf=[1] * len(SHAPES))
         refs = _singles(fastmm, SHAPES, As, Bs)
-        for C, ref in zip(Cs, refs):
+        for i, (C, ref) in enumerate(zip(Cs, refs)):
             assert np.array_equal(host(C), ref)
+            assert checks.rel_frob(host(C), classic.gemm(host(As[i]), host(Bs[i]))) <= TOL
 
 
 def test_batched_graph_off_matches(fastmm, monkeypatch):
@@ -103,8 +132,9 @@ def test_batched_host_operands(fastmm):
     Bh = [b.cpu().pin_memory() for b in Bs]
     Ch = [torch.full((m, n), float("nan")).pin_memory() for (m, k, n, d) in shapes]
     fastmm.gemm_batched(Ah, Bh, Ch, depth=depths, leaf=[1] * len(shapes))
-    for C, ref in zip(Ch, refs):
+    for i, (C, ref) in enumerate(zip(Ch, refs)):
         assert np.array_equal(C.numpy(), ref)
+        assert checks.rel_frob(C.numpy(), classic.gemm(host(As[i]), host(Bs[i]))) <= TOL
 
 
 def test_batched_validation_is_atomic(fastmm):

@@ -336,3 +336,52 @@ def test_misaligned_device_operands_staged(fastmm, m, k, n, depth):
     assert np.all(np.isnan(got[:, n:]))
     assert torch.equal(Abig, A0) and torch.equal(Bbig, B0)
 
+
+
+_FRESH_DEPTH_FIRST = r"""
+import sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import synthgen
+from paper_1205_2927_amd import fastmm
+fastmm.load()
+n, depth, leaf = 1024, 3, 32
+A = torch.from_numpy(synthgen.uniform_pm1(133, n, n)).to("cuda")
+B = torch.from_numpy(synthgen.uniform_pm1(134, n, n)).to("cuda")
+C = torch.full((n, n), float("nan"), device="cuda")
+print("fresh process: first call depth-first", flush=True)
+fastmm.gemm(n, n, n, A, B, C, depth=depth, leaf=leaf)
+st = fastmm.get_stats()
+np.save(sys.argv[2], C.cpu().numpy())
+print(f"launches {st['launches']} leaves {st['leaves']} depth {st['depth']}", flush=True)
+"""
+
+
+def test_depth_first_fallback_first_call_in_fresh_process(fastmm, tmp_path):
+    # The first call of a process runs depth first at the top and level-wise
+    # below it: the children's descriptor blocks (49 leaves each) outgrow the
+    # 4 KB pinned block the top level took first, so the pinned buffer is
+    # reallocated while the top level still has its post-addition node to
+    # upload.  The result must match the oracle and equal the level-wise one.
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = str(tmp_path / "c.npy")
+    env = dict(os.environ, FASTMM_WORKSPACE_LIMIT="35000000")
+    say("fresh subprocess: depth-first fallback as its first call")
+    r = subprocess.run([sys.executable, "-c", _FRESH_DEPTH_FIRST, root, out], env=env,
+                       capture_output=True, text=True, timeout=300)
+    say(r.stdout + r.stderr[-2000:])
+    assert r.returncode == 0
+    launches = int(r.stdout.split("launches ")[1].split()[0])
+    n = 1024
+    A = uniform(133, n, n)
+    B = uniform(134, n, n)
+    got = np.load(out)
+    C0 = empty_dev(n, n)
+    fastmm.gemm(n, n, n, dev(A), dev(B), C0, depth=3, leaf=32)
+    assert launches > fastmm.get_stats()["launches"]  # it did run depth first
+    assert np.array_equal(got, host(C0))
+    assert checks.rel_frob(got, classic.gemm(A, B)) <= TOL_WINOGRAD
