@@ -147,6 +147,32 @@ int fastmm_gemm_ex(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
                    const float* B, int64_t ldb, float* C, int64_t ldc, int depth, int64_t leaf,
                    int tile);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * product as fastmm_gemm (same schedule, same kernels, bit for bit the same
+ * result), run in a fixed workspace of FASTMM_NOALLOC_WORKSPACE_BYTES that
+ * the library holds in a statically allocated device array: reserved on
+ * every GPU the library is loaded on, held until the process ends, shared by
+ * every call on that GPU (calls of one process are serialised and return
+ * when done; nothing else may use it concurrently).  No device or pinned
+ * allocation happens in the call (the schedule itself is built in host heap
+ * memory).
+ *   - A, B, C must be device memory with 16-byte aligned rows of A and B,
+ *     lda and ldb multiples of 4 and K, N multiples of 4 (what fastmm_gemm
+ *     would otherwise copy into staging buffers); else
+ *     FASTMM_ERROR_NOT_SUPPORTED.  The current device must be the one the
+ *     library was initialised on.
+ *   - depth < 0 takes the planner's fixed rule (FASTMM_PLAN_DEFAULT), which
+ *     needs no device; depth >= 0 and leaf as in fastmm_gemm.
+ *   - A product whose temporaries and descriptors need more than the fixed
+ *     workspace gives FASTMM_ERROR_OUT_OF_MEMORY (the message states both
+ *     sizes) before anything is written; a smaller depth needs less.
+ *   - Other arguments and errors as fastmm_gemm. */
+enum { FASTMM_NOALLOC_WORKSPACE_BYTES = 256 << 20 };
+int fastmm_gemm_noalloc(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda,
+                        const float* B, int64_t ldb, float* C, int64_t ldc, int depth,
+                        int64_t leaf);
+
 /* C = A*B by the paper's classic recursion (Table 1): eight sub-products per
  * level over the quadrant split of equation (1), the second product of each
  * result quadrant accumulated (C += AB), down to the same stop rule as

@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfastmm.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["leaf_gemm.hip", "leaf_split.hip", "quad_add.hip", "mlp.hip", "engine.cpp", "pipeline.cpp", "batched.cpp", "planner.cpp", "rmul.cpp"]
+SOURCES = ["leaf_gemm.hip", "leaf_split.hip", "quad_add.hip", "mlp.hip", "engine.cpp", "pipeline.cpp", "batched.cpp", "planner.cpp", "rmul.cpp", "noalloc.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -92,8 +92,11 @@ void ensure_init(Library& L) {
   for (auto& e : L.sync_ev) FASTMM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (auto& e : L.leaf_ev) FASTMM_HIP(hipEventCreate(&e));
   for (auto& e : L.tune_ev) FASTMM_HIP(hipEventCreate(&e));
-  FASTMM_HIP(hipMalloc(&L.leaf_queue, 256));
-  FASTMM_HIP(hipMemset(L.leaf_queue, 0, 256));
+  // The persistent leaf launches' two counters: the head of the statically
+  // allocated device workspace (noalloc.cpp), so that initialisation itself
+  // allocates no device memory.
+  L.leaf_queue = reinterpret_cast<int*>(bind_static_scratch(L.device));
+  FASTMM_HIP(hipMemset(L.leaf_queue, 0, static_queue_bytes()));
   L.initialised = true;
 }
 
@@ -1333,8 +1336,7 @@ void fastmm_finalize(void) {
   for (auto& e : L.leaf_ev) e = nullptr;
   for (auto& e : L.tune_ev) e = nullptr;
   if (L.own_stream) (void)hipStreamDestroy(L.own_stream);
-  if (L.leaf_queue) (void)hipFree(L.leaf_queue);
-  L.leaf_queue = nullptr;
+  L.leaf_queue = nullptr;  // static device memory: nothing to free
   L.arena = nullptr;
   L.arena_bytes = 0;
   L.pinned = nullptr;

@@ -172,6 +172,11 @@ struct Library {
 
 Library& lib();
 void ensure_init(Library& L);
+// Device address of the statically allocated workspace on `device` (looked
+// up once per device with that device current; noalloc.cpp), and the bytes
+// at its head that hold the persistent leaf launches' counters.
+char* bind_static_scratch(int device);
+size_t static_queue_bytes();
 char* ensure_arena(Library& L, size_t bytes);
 char* ensure_pinned(Library& L, size_t bytes);
 

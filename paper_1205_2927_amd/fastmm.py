@@ -40,8 +40,9 @@ EXPORTS = [
     "fastmm_planner_train", "fastmm_planner_records", "fastmm_set_stream",
     "fastmm_set_profiling", "fastmm_get_stats", "fastmm_get_last_error", "fastmm_finalize",
     "fastmm_preadd", "fastmm_postadd", "fastmm_mlp_forward", "fastmm_mlp_backward",
-    "fastmm_mlp_adam",
+    "fastmm_mlp_adam", "fastmm_gemm_noalloc",
 ]
+NOALLOC_WORKSPACE_BYTES = 256 << 20
 
 
 class FastmmError(RuntimeError):
@@ -95,6 +96,7 @@ def load(path: str | None = None):
     sig = {
         "fastmm_gemm": [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, i64],
         "fastmm_gemm_ex": [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, i64, i32],
+        "fastmm_gemm_noalloc": [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, i64],
         "fastmm_rmul": [i64, i64, i64, vp, i64, vp, i64, vp, i64, i32, i64, i32],
         "fastmm_gemm_batched": [i32, P64, P64, P64, vp, P64, vp, P64, vp, P64, vp, vp],
         "fastmm_plan": [i64, i64, i64, i32, ctypes.POINTER(Plan)],
@@ -163,6 +165,17 @@ def gemm(M, N, K, A, B, C, depth=0, leaf=1280, tile=None, lda=None, ldb=None, ld
                                 _ld(C, ldc), int(depth), int(leaf), int(tile))
     _check(rc)
     return rc
+
+
+def gemm_noalloc(M, N, K, A, B, C, depth=0, leaf=1280, lda=None, ldb=None, ldc=None):
+    """fastmm_gemm_noalloc: C = A B in the library's static device workspace."""
+    _check(load().fastmm_gemm_noalloc(M, N, K, _ptr(A), _ld(A, lda), _ptr(B), _ld(B, ldb),
+                                      _ptr(C), _ld(C, ldc), int(depth), int(leaf)))
+
+
+def gemm_noalloc_raw(M, N, K, A, lda, B, ldb, C, ldc, depth, leaf) -> int:
+    """Status code of fastmm_gemm_noalloc without raising."""
+    return load().fastmm_gemm_noalloc(M, N, K, A, lda, B, ldb, C, ldc, depth, leaf)
 
 
 def rmul(M, N, K, A, B, C, depth=0, leaf=3008, tile=TILE_128x128, lda=None, ldb=None, ldc=None):
