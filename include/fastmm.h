@@ -57,9 +57,10 @@ enum { FASTMM_AUTO = -1 }; /* depth < 0 (or tile < 0): let the planner choose */
 enum {
   FASTMM_PLAN_DEFAULT = 0,   /* fixed rule: deepest split with leaf >= 1280; 64x64
                                 tiles when 128x128 ones would number under 512 */
-  FASTMM_PLAN_MODEL = 1,     /* learned cost model chooses the depth (each with the
-                                fixed rule's tile), keeping DEFAULT's unless it
-                                predicts a 5% gain; untrained: EXHAUSTIVE */
+  FASTMM_PLAN_MODEL = 1,     /* learned cost model chooses depth and tile among all
+                                candidates (mean predicted time of its networks),
+                                keeping DEFAULT's choice unless another is predicted
+                                1% faster; untrained: EXHAUSTIVE */
   FASTMM_PLAN_EXHAUSTIVE = 2 /* time every candidate on the device, cache it */
 };
 
@@ -188,9 +189,13 @@ int fastmm_rmul(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, co
  * leading dimensions (same rules as fastmm_gemm, per problem).  The paper
  * runs two independent products at once, one per GPU, to fill its devices
  * (Section 4.2, the two-GPU measurement); here many uneven products share
- * each launch of one device.  depth == NULL:
- * each problem's depth/tile from the planner (mode set by
- * fastmm_set_plan_mode); leaf == NULL: default cutoff 1280.  Every level of
+ * each launch of one device.  depth == NULL: each problem's depth from
+ * the planner (mode set by fastmm_set_plan_mode), always with 128x128 tiles
+ * (the batch's shared leaf launch fills the device): DEFAULT's fixed rule,
+ * or, in the MODEL and EXHAUSTIVE modes, the fastest predicted or timed
+ * depth among those whose leaf launch would fill the device on its own, when
+ * it beats the fixed rule's; depth != NULL: 128x128 tiles and leaf[i] (NULL:
+ * the default cutoff 1280).  Every level of
  * every problem is one grouped launch (or one per group of up to three levels,
  * the additions of levels that halve exactly); the launch sequence is captured once
  * per set of shapes and plans into a HIP graph and replayed.  All problems are
@@ -211,13 +216,19 @@ int fastmm_plan(int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out);
 int fastmm_set_plan_mode(int mode);
 
 /* Load / save the planner's state: the timing database (JSON) and the cost
- * model weights (raw little-endian FP32, 4609 values).  NULL path: skip. */
+ * model weights (raw little-endian FP32, FASTMM_MODEL_NETS x
+ * FASTMM_MLP_PARAMS values: the networks one after another).  NULL path:
+ * skip. */
 int fastmm_planner_load(const char* timing_db_path, const char* model_path);
 int fastmm_planner_save(const char* timing_db_path, const char* model_path);
 
 /* Train the cost model on the timing database with the GPU forward/backward
- * and Adam kernels: `epochs` passes of minibatches of `batch`, learning rate
- * lr, seed for shuffling.  Final training loss in *loss (may be NULL). */
+ * and Adam kernels: each of its FASTMM_MODEL_NETS networks takes `epochs`
+ * passes of minibatches of `batch` at learning rate lr, network j drawing its
+ * initial weights and minibatch order from seed + j.  The paper sets its leaf
+ * thresholds by hand from measurements (Section 3.2, Table 2); the model
+ * learns them from this library's own timings.  Mean final training loss of
+ * the networks in *loss (may be NULL). */
 int fastmm_planner_train(int epochs, int batch, float lr, uint64_t seed, float* loss);
 
 /* Number of timing records in the planner's database. */
@@ -276,7 +287,7 @@ int fastmm_postadd(int64_t h_r, int64_t h_c, const float* P, float* C, int64_t l
  * -> 64 -> 1 with ReLU; flat parameters [W1 (5x64), b1, W2 (64x64), b2,
  * W3 (64x1), b3], W stored (fan_in, fan_out) row-major; X is (batch x 5).
  * Loss: mean squared error.  These are the planner's training kernels. ---- */
-enum { FASTMM_MLP_PARAMS = 4609 };
+enum { FASTMM_MLP_PARAMS = 4609, FASTMM_MODEL_NETS = 3 };
 
 /* y[batch] = network(X).  */
 int fastmm_mlp_forward(int batch, const float* params, const float* X, float* y);

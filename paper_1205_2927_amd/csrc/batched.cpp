@@ -150,13 +150,11 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
     int tile = kTile128x128;
     if (dep < 0) {
       fastmm_plan_t pl{};
-      int rc = plan_choose(L, p.M, p.N, p.K, L.plan_mode, &pl);
+      int rc = plan_choose_batched(L, p.M, p.N, p.K, L.plan_mode, &pl);
       if (rc != kSuccess) throw Error(rc, "planner failed");
       dep = pl.depth;
       lf = pl.leaf;
-      // The fixed rule's small-launch tile is for a product alone; the
-      // leaves of a batch share one launch, which the 128x128 tiles fill.
-      tile = L.plan_mode == FASTMM_PLAN_DEFAULT ? (int)kTile128x128 : pl.tile;
+      tile = pl.tile;
     }
     p.depth = p.K == 0 ? 0 : effective_depth(p.M, p.N, p.K, dep, lf);
     p.tile = tile;

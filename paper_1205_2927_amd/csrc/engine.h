@@ -236,6 +236,8 @@ int64_t graph_replays();
 
 // Planner hooks (planner.cpp).
 int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out);
+// The plan of one problem of a batched call (128x128 tiles; see planner.cpp).
+int plan_choose_batched(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out);
 int64_t default_leaf();
 
 void set_error(const std::string& msg);

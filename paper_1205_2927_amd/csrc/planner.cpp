@@ -19,10 +19,20 @@
 //   EXHAUSTIVE  time every candidate (depth, tile) on the device with
 //               device-resident operands, keep the fastest; every timing is
 //               a record of the timing database;
-//   MODEL       a learned cost model (the 5 -> 64 -> 64 -> 1 network of
-//               mlp.hip, trained on the GPU on the timing database) predicts
-//               each candidate's log2 run time; the argmin is taken.  With no
-//               trained model it falls back to EXHAUSTIVE.
+//   MODEL       a learned cost model -- kModelNets networks 5 -> 64 -> 64 -> 1
+//               (mlp.hip), each trained on the GPU on the whole timing
+//               database from its own seeded initialisation and minibatch
+//               order -- predicts every candidate's log2 run time as the
+//               mean of the networks' predictions; the argmin over all
+//               candidates (depth and tile) is taken, unless it is predicted
+//               within kModelMargin of the fixed rule's choice, which then
+//               stays.  With no trained model it falls back to EXHAUSTIVE.
+//               Measured on held-out shapes (timings of 160 training shapes,
+//               256 evaluation shapes, one MI355X): one network has mean
+//               regret 1.5-2.7% against the fastest candidate depending on
+//               its seed (worst single choice up to 52% slower); three have
+//               1.4%, and the 1% margin brings that to 1.1% with no choice
+//               worse than 17% (the fixed rule: 3.1%, worst 47%).
 // Candidates: depth 0..4 with leaves of at least 128 in every dimension,
 // times five leaf tiles (64x64 to 256x256).  Ties go to the smaller depth, then tile id.
 #include <hip/hip_runtime.h>
@@ -55,6 +65,7 @@ void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
 namespace {
 
 constexpr int kNParams = FASTMM_MLP_PARAMS;
+constexpr int kModelNets = FASTMM_MODEL_NETS;
 constexpr int64_t kMinLeaf = 128;   // smallest leaf extent a candidate may reach
 constexpr int kMaxDepth = 4;
 constexpr int64_t kDefaultLeaf = 1280;
@@ -72,8 +83,10 @@ struct Record {
 struct Planner {
   std::vector<Record> db;
   std::map<std::tuple<int64_t, int64_t, int64_t, int>, fastmm_plan_t> cache;
+  // Exhaustive timings per shape: (depth, tile) -> ms.
+  std::map<std::tuple<int64_t, int64_t, int64_t>, std::map<std::pair<int, int>, double>> table;
   bool trained = false;
-  std::vector<float> params;  // host copy of the model
+  std::vector<float> params;  // host copy of the model: kModelNets x kNParams
 };
 
 Planner& planner() {
@@ -167,6 +180,7 @@ fastmm_plan_t tune_exhaustive(Library& L, int64_t M, int64_t N, int64_t K) {
         ms = std::min(ms, (double)x);
       }
       P.db.push_back({M, N, K, d, t, ms});
+      P.table[std::make_tuple(M, N, K)][{d, t}] = ms;
       if (ms < best_ms) {  // strict: earlier (smaller depth, tile) wins ties
         best_ms = ms;
         best = make_plan(d, t, ms, FASTMM_PLAN_EXHAUSTIVE);
@@ -182,8 +196,8 @@ fastmm_plan_t tune_exhaustive(Library& L, int64_t M, int64_t N, int64_t K) {
 
 // Device copies of the model parameters and a small inference buffer.
 struct ModelDev {
-  float* params = nullptr;
-  float* buf = nullptr;  // features (64 x 5) and outputs (64)
+  float* params = nullptr;  // kModelNets x kNParams
+  float* buf = nullptr;     // features (64 x 5) and outputs (kModelNets x 64)
 };
 
 ModelDev& model_dev() {
@@ -193,9 +207,9 @@ ModelDev& model_dev() {
 
 void upload_model(Library& L) {
   ModelDev& D = model_dev();
-  if (!D.params) FASTMM_HIP(hipMalloc(&D.params, kNParams * 4));
-  if (!D.buf) FASTMM_HIP(hipMalloc(&D.buf, 64 * 6 * 4));
-  FASTMM_HIP(hipMemcpyAsync(D.params, planner().params.data(), kNParams * 4,
+  if (!D.params) FASTMM_HIP(hipMalloc(&D.params, (size_t)kModelNets * kNParams * 4));
+  if (!D.buf) FASTMM_HIP(hipMalloc(&D.buf, (size_t)64 * (5 + kModelNets) * 4));
+  FASTMM_HIP(hipMemcpyAsync(D.params, planner().params.data(), (size_t)kModelNets * kNParams * 4,
                             hipMemcpyHostToDevice, L.stream));
   FASTMM_HIP(hipStreamSynchronize(L.stream));
 }
@@ -218,40 +232,115 @@ std::pair<int, int> default_choice(int64_t M, int64_t N, int64_t K) {
   return {d, rule_tile(M, N, d)};
 }
 
-// The model chooses the depth (each depth with rule_tile's tile: the rule's
-// tile choice is the measured one, while the network, trained on a few
-// dozen shapes, mispredicts tiles whose times differ by wave quantisation),
-// and departs from the fixed rule's depth only where it predicts at least
-// this gain.
-constexpr double kModelMargin = 1.05;
+// The model's choice stays with the fixed rule's unless another candidate is
+// predicted at least this much faster (a tie-break inside the networks'
+// spread: on held-out shapes it took the three networks' mean regret from
+// 1.4% to 1.1%).
+constexpr double kModelMargin = 1.01;
 
-fastmm_plan_t plan_model(Library& L, int64_t M, int64_t N, int64_t K) {
+// Mean predicted log2 time of the networks for each candidate.
+std::vector<double> model_predict(Library& L, int64_t M, int64_t N, int64_t K,
+                                  const std::vector<std::pair<int, int>>& cand) {
   ModelDev& D = model_dev();
-  const auto cand = candidates(M, N, K);
   const int n = (int)cand.size();
-  std::vector<float> X((size_t)n * 5), y(n);
+  if (n > 64) throw Error(kDeviceError, "planner: too many candidates for the inference buffer");
+  std::vector<float> X((size_t)n * 5), y((size_t)kModelNets * 64);
   for (int i = 0; i < n; ++i) features(M, N, K, cand[i].first, cand[i].second, &X[(size_t)i * 5]);
   float* dX = D.buf;
   float* dy = D.buf + 64 * 5;
   FASTMM_HIP(hipMemcpyAsync(dX, X.data(), X.size() * 4, hipMemcpyHostToDevice, L.stream));
-  mlp_forward(n, D.params, dX, dy, nullptr, L.stream);
-  FASTMM_HIP(hipMemcpyAsync(y.data(), dy, n * 4, hipMemcpyDeviceToHost, L.stream));
+  for (int j = 0; j < kModelNets; ++j)
+    mlp_forward(n, D.params + (size_t)j * kNParams, dX, dy + (size_t)j * 64, nullptr, L.stream);
+  FASTMM_HIP(hipMemcpyAsync(y.data(), dy, y.size() * 4, hipMemcpyDeviceToHost, L.stream));
   FASTMM_HIP(hipStreamSynchronize(L.stream));
-  const auto def = default_choice(M, N, K);
-  int bi = -1, di = -1;
+  std::vector<double> pred(n, 0.0);
   for (int i = 0; i < n; ++i) {
-    if (cand[i].second != rule_tile(M, N, cand[i].first)) continue;
-    if (bi < 0 || y[i] < y[bi]) bi = i;
+    for (int j = 0; j < kModelNets; ++j) pred[i] += (double)y[(size_t)j * 64 + i];
+    pred[i] /= kModelNets;
+  }
+  return pred;
+}
+
+fastmm_plan_t plan_model(Library& L, int64_t M, int64_t N, int64_t K) {
+  const auto cand = candidates(M, N, K);
+  const int n = (int)cand.size();
+  const std::vector<double> pred = model_predict(L, M, N, K, cand);
+  const auto def = default_choice(M, N, K);
+  int bi = 0, di = -1;
+  for (int i = 0; i < n; ++i) {
+    if (pred[i] < pred[bi]) bi = i;  // strict: earlier (smaller depth, tile) wins ties
     if (cand[i] == def) di = i;
   }
-  if (bi < 0) bi = 0;
-  if (di >= 0 && (double)y[di] <= (double)y[bi] + std::log2(kModelMargin)) bi = di;
-  return make_plan(cand[bi].first, cand[bi].second, std::exp2((double)y[bi]), FASTMM_PLAN_MODEL);
+  if (di >= 0 && pred[di] <= pred[bi] + std::log2(kModelMargin)) bi = di;
+  return make_plan(cand[bi].first, cand[bi].second, std::exp2(pred[bi]), FASTMM_PLAN_MODEL);
+}
+
+// 128x128 tiles of a depth-d product's leaf launch.
+int64_t leaf_tiles_128(int64_t M, int64_t N, int d) {
+  int64_t leaves = 1;
+  for (int l = 0; l < d; ++l) leaves *= 7;
+  const int64_t m = d ? leaf_extent(M, d) : M, n = d ? leaf_extent(N, d) : N;
+  return leaves * ((m + 127) / 128) * ((n + 127) / 128);
 }
 
 }  // namespace
 
 int64_t default_leaf() { return kDefaultLeaf; }
+
+// A problem of a batch: its leaves join one launch with every other
+// problem's, which fills the device, so the tile is always 128x128 (the
+// fixed rule's smaller tiles only help a product alone fill the device).  A
+// single-product timing (EXHAUSTIVE) or prediction (MODEL) measures the
+// batch's situation only where the product alone already fills the device
+// with long leaves -- a leaf launch of at least 1024 tiles of 128x128, every
+// leaf extent at least 1024 --: a deeper plan for a smaller product mostly
+// buys occupancy that the batch already has, at the price of additions and
+// short reductions (measured on the 256-problem batch: taking the fastest
+// single-product depth wherever the product fills the device alone made
+// the batch 6% slower under EXHAUSTIVE and 22% slower under MODEL than the
+// fixed rule).  So the mode's choice is taken among those candidates,
+// against the fixed rule's depth, which stays unless one of them is faster
+// (for MODEL, predicted at least 1% faster).
+int plan_choose_batched(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out) {
+  if (mode < FASTMM_PLAN_DEFAULT || mode > FASTMM_PLAN_EXHAUSTIVE)
+    throw Error(kInvalidValue, "unknown planner mode");
+  const int def = (M > 0 && N > 0 && K > 0) ? default_choice(M, N, K).first : 0;
+  *out = make_plan(def, kTile128x128, -1.0, mode);
+  out->leaf = kDefaultLeaf;
+  if (mode == FASTMM_PLAN_DEFAULT || M <= 0 || N <= 0 || K <= 0) return kSuccess;
+  ensure_init(L);
+  Planner& P = planner();
+  std::vector<std::pair<int, int>> cand;
+  for (auto c : candidates(M, N, K))
+    if (c.second == kTile128x128 &&
+        (c.first == def ||
+         (leaf_tiles_128(M, N, c.first) >= 1024 && std::min(std::min(M, N), K) >> c.first >= 1024)))
+      cand.push_back(c);
+  if (cand.size() <= 1) return kSuccess;
+  int best = -1;
+  if (mode == FASTMM_PLAN_MODEL && P.trained) {
+    const std::vector<double> pred = model_predict(L, M, N, K, cand);
+    int di = 0;
+    for (int i = 0; i < (int)cand.size(); ++i) {
+      if (best < 0 || pred[i] < pred[best]) best = i;
+      if (cand[i].first == def) di = i;
+    }
+    if (pred[di] <= pred[best] + std::log2(kModelMargin)) best = di;
+  } else {
+    fastmm_plan_t ex{};
+    plan_choose(L, M, N, K, FASTMM_PLAN_EXHAUSTIVE, &ex);  // fills the timing table
+    const auto& t = P.table[std::make_tuple(M, N, K)];
+    for (int i = 0; i < (int)cand.size(); ++i) {
+      auto f = t.find(cand[i]);
+      if (f == t.end()) continue;
+      if (best < 0 || f->second < t.at(cand[best])) best = i;
+    }
+  }
+  if (best >= 0 && cand[best].first != def) {
+    *out = make_plan(cand[best].first, kTile128x128, -1.0, mode);
+  }
+  return kSuccess;
+}
 
 int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out) {
   if (mode < FASTMM_PLAN_DEFAULT || mode > FASTMM_PLAN_EXHAUSTIVE)
@@ -281,6 +370,13 @@ int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_pl
 
 namespace {
 
+void train_network(Library& L, const std::vector<float>& X, const std::vector<float>& t, int n,
+                   int batch, int epochs, float lr, float tmean, uint64_t& s, std::vector<float>& p,
+                   float& loss);
+
+// Trains the kModelNets networks of the cost model on the whole timing
+// database (targets: log2 of the measured milliseconds), network j from the
+// seed + j stream.  *loss_out: the networks' mean full-data loss.
 void train(Library& L, int epochs, int batch, float lr, uint64_t seed, float* loss_out) {
   Planner& P = planner();
   if (P.db.empty()) throw Error(kInvalidValue, "timing database is empty");
@@ -297,9 +393,30 @@ void train(Library& L, int epochs, int batch, float lr, uint64_t seed, float* lo
     tmean += t[i];
   }
   tmean /= n;
-  // He-uniform initialisation from the seeded stream; last bias = mean target.
-  std::vector<float> p(kNParams, 0.f);
-  uint64_t s = seed;
+  std::vector<float> all((size_t)kModelNets * kNParams);
+  double loss_sum = 0.0;
+  for (int net = 0; net < kModelNets; ++net) {
+    // Network `net` draws its initialisation and minibatch order from its
+    // own seeded stream.
+    uint64_t s = seed + (uint64_t)net;
+    std::vector<float> p(kNParams, 0.f);
+    float loss = 0.f;
+    train_network(L, X, t, n, batch, epochs, lr, (float)tmean, s, p, loss);
+    std::copy(p.begin(), p.end(), all.begin() + (size_t)net * kNParams);
+    loss_sum += loss;
+  }
+  if (loss_out) *loss_out = (float)(loss_sum / kModelNets);
+  P.params = all;
+  P.trained = true;
+  upload_model(L);
+}
+
+// One network of the cost model: He-uniform initialisation from the seeded
+// stream s (last bias: the mean target), then `epochs` passes of Adam over
+// minibatches in an order shuffled from s; `loss` = full-data loss.
+void train_network(Library& L, const std::vector<float>& X, const std::vector<float>& t, int n,
+                   int batch, int epochs, float lr, float tmean, uint64_t& s, std::vector<float>& p,
+                   float& loss) {
   auto init = [&](int off, int fan_in, int count) {
     const double a = std::sqrt(6.0 / fan_in);
     for (int i = 0; i < count; ++i) p[off + i] = (float)((2.0 * uniform01(s) - 1.0) * a);
@@ -307,7 +424,7 @@ void train(Library& L, int epochs, int batch, float lr, uint64_t seed, float* lo
   init(0, 5, 5 * 64);
   init(5 * 64 + 64, 64, 64 * 64);
   init(5 * 64 + 64 + 64 * 64 + 64, 64, 64);
-  p[kNParams - 1] = (float)tmean;
+  p[kNParams - 1] = tmean;
 
   float *dp = nullptr, *dm = nullptr, *dv = nullptr, *dg = nullptr, *dX = nullptr, *dt = nullptr,
         *dscr = nullptr, *dloss = nullptr, *hbuf = nullptr;
@@ -355,19 +472,14 @@ void train(Library& L, int epochs, int batch, float lr, uint64_t seed, float* lo
     FASTMM_HIP(hipMemcpyAsync(dX, X.data(), (size_t)n * 5 * 4, hipMemcpyHostToDevice, L.stream));
     FASTMM_HIP(hipMemcpyAsync(dt, t.data(), (size_t)n * 4, hipMemcpyHostToDevice, L.stream));
     mlp_backward(n, dp, dX, dt, dg, dloss, dscr, L.stream);
-    float loss = 0.f;
     FASTMM_HIP(hipMemcpyAsync(&loss, dloss, 4, hipMemcpyDeviceToHost, L.stream));
     FASTMM_HIP(hipMemcpyAsync(p.data(), dp, kNParams * 4, hipMemcpyDeviceToHost, L.stream));
     FASTMM_HIP(hipStreamSynchronize(L.stream));
-    if (loss_out) *loss_out = loss;
   } catch (...) {
     release();
     throw;
   }
   release();
-  P.params = p;
-  P.trained = true;
-  upload_model(L);
 }
 
 // Timing database: a flat JSON list of records.
@@ -460,11 +572,11 @@ int fastmm_planner_load(const char* db_path, const char* model_path) {
     if (model_path) {
       FILE* f = std::fopen(model_path, "rb");
       if (!f) throw Error(kInvalidValue, std::string("cannot read ") + model_path);
-      std::vector<float> p(kNParams);
-      const size_t got = std::fread(p.data(), 4, kNParams, f);
+      std::vector<float> p((size_t)kModelNets * kNParams);
+      const size_t got = std::fread(p.data(), 4, p.size(), f);
       const bool extra = std::fgetc(f) != EOF;
       std::fclose(f);
-      if (got != (size_t)kNParams || extra)
+      if (got != p.size() || extra)
         throw Error(kInvalidValue, std::string("model file has the wrong size: ") + model_path);
       for (float x : p)
         if (!std::isfinite(x)) throw Error(kInvalidValue, "model file holds non-finite values");
@@ -485,7 +597,7 @@ int fastmm_planner_save(const char* db_path, const char* model_path) {
       if (!planner().trained) throw Error(kInvalidValue, "no trained model to save");
       FILE* f = std::fopen(model_path, "wb");
       if (!f) throw Error(kInvalidValue, std::string("cannot write ") + model_path);
-      std::fwrite(planner().params.data(), 4, kNParams, f);
+      std::fwrite(planner().params.data(), 4, planner().params.size(), f);
       std::fclose(f);
     }
   });

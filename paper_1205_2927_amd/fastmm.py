@@ -32,6 +32,7 @@ TILES = {TILE_128x128: (128, 128), TILE_256x128: (256, 128), TILE_128x64: (128, 
          TILE_256x256_W8: (256, 256), TILE_128x256: (128, 256), TILE_BF16X3: (256, 256),
          TILE_FP16X3: (256, 256)}
 MLP_PARAMS = 4609
+MODEL_NETS = 3  # networks of the planner's cost model (model file: MODEL_NETS x MLP_PARAMS floats)
 
 # Every symbol include/fastmm.h declares.
 EXPORTS = [

@@ -74,32 +74,30 @@ def test_default_rule(fastmm):
     assert p.depth == 3
 
 
-def test_exhaustive_model_regret_and_gain(fastmm, tmp_path):
-    train_shapes = synthgen.shapes_loguniform(4001, 40)
-    eval_shapes = synthgen.shapes_loguniform(3001, 12)
-    for (M, N, K) in train_shapes:
-        fastmm.plan(int(M), int(N), int(K), fastmm.PLAN_EXHAUSTIVE)
-    n_train = fastmm.planner_records()
-    say(f"training records: {n_train}")
-    assert n_train >= 40 * 5
-    loss = fastmm.planner_train(epochs=400, batch=64, lr=3e-3, seed=4001)
-    say(f"trained, loss={loss:.4f}")
+def test_exhaustive_model_regret_and_gain(fastmm, trained_planner, tmp_path):
+    # The cost model is trained (conftest) on the exhaustive timings of 160
+    # shapes of seed 4001; it is judged on 48 held-out shapes of seed 3001
+    # against exhaustive timing of every candidate: its mean regret must not
+    # exceed the fixed rule's, and its choices must be at least as fast as
+    # the fixed rule's (geometric mean over the shapes).
+    import json
+    loss = trained_planner
     assert np.isfinite(loss) and loss < 0.5
+    eval_shapes = synthgen.shapes_loguniform(3001, 48)
     db = tmp_path / "db.json"
     model = tmp_path / "model.bin"
-    fastmm.planner_save(str(db), str(model))
-    # Evaluate on held-out shapes: exhaustive timing gives the table.
+    fastmm.planner_save(None, str(model))
+    assert model.stat().st_size == 4 * fastmm.MODEL_NETS * fastmm.MLP_PARAMS
     regrets_model, regrets_default, gains = [], [], []
-    import json
     for (M, N, K) in eval_shapes:
         M, N, K = int(M), int(N), int(K)
         best = fastmm.plan(M, N, K, fastmm.PLAN_EXHAUSTIVE)
-        fastmm.planner_save(str(db), None)
-        recs = [r for r in json.load(open(db))["records"] if (r["M"], r["N"], r["K"]) == (M, N, K)]
-        table = {(r["depth"], r["tile"]): r["ms"] for r in recs}
         pm = fastmm.plan(M, N, K, fastmm.PLAN_MODEL)
         pd = fastmm.plan(M, N, K, fastmm.PLAN_DEFAULT)
         assert pm.source == fastmm.PLAN_MODEL
+        fastmm.planner_save(str(db), None)
+        recs = [r for r in json.load(open(db))["records"] if (r["M"], r["N"], r["K"]) == (M, N, K)]
+        table = {(r["depth"], r["tile"]): r["ms"] for r in recs}
         t_best = table[(best.depth, best.tile)]
         t_model = table[(pm.depth, pm.tile)]
         t_default = table[(pd.depth, pd.tile)]
@@ -110,9 +108,16 @@ def test_exhaustive_model_regret_and_gain(fastmm, tmp_path):
             f"{t_model:.3f}, default d{pd.depth}t{pd.tile} {t_default:.3f}")
     rm, rd = float(np.mean(regrets_model)), float(np.mean(regrets_default))
     gain = float(np.exp(np.mean(np.log(gains))))
-    say(f"mean regret model={rm:.3f} default={rd:.3f}; geo-mean gain over default={gain:.3f}")
-    assert rm <= 0.15
-    assert gain >= 0.97
+    say(f"mean regret model={rm:.4f} default={rd:.4f}; geo-mean gain over default={gain:.4f}")
+    assert rm <= rd
+    assert gain >= 1.0
+    # the saved model reproduces the same choices after a reload
+    choices = [(fastmm.plan(int(M), int(N), int(K), fastmm.PLAN_MODEL).depth,
+                fastmm.plan(int(M), int(N), int(K), fastmm.PLAN_MODEL).tile) for (M, N, K) in eval_shapes[:8]]
+    fastmm.planner_load(None, str(model))
+    again = [(fastmm.plan(int(M), int(N), int(K), fastmm.PLAN_MODEL).depth,
+              fastmm.plan(int(M), int(N), int(K), fastmm.PLAN_MODEL).tile) for (M, N, K) in eval_shapes[:8]]
+    assert choices == again
 
 
 def test_auto_depth_product_is_correct(fastmm):
@@ -134,6 +139,6 @@ def test_model_file_errors(fastmm, tmp_path):
         fastmm.planner_load(None, str(bad))
     assert e.value.code == fastmm.ERROR_INVALID_VALUE
     nan = tmp_path / "nan.bin"
-    nan.write_bytes(np.full(mlp.N_PARAMS, np.nan, np.float32).tobytes())
+    nan.write_bytes(np.full(fastmm.MODEL_NETS * mlp.N_PARAMS, np.nan, np.float32).tobytes())
     with pytest.raises(fastmm.FastmmError):
         fastmm.planner_load(None, str(nan))
