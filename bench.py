@@ -1,13 +1,15 @@
 """Headline benchmark: effective GFLOPS (2MNK / wall-clock) of FP32 Winograd
 on MFMA leaves vs the plain MFMA SGEMM, square n = 19456.
 
-One step = one synchronous fastmm_gemm call over operands already resident in
-HBM when the timed region starts: pre-additions, grouped leaf products,
-post-additions.  The same product with operands in pinned host memory, where
-the wall-clock includes the host<->device transfers (the paper measures
-GFLOPS as 2N^3 over wall-clock with transfers included, Section 4), is
-reported beside it as context (`pinned_host`).  Inputs are seeded synthetic
-(uniform on the 2^-23 grid of [-1, 1)).  Prints one JSON line.
+One step = one synchronous fastmm_gemm call with A, B and C in pinned host
+memory: the wall-clock includes the host->device transfers of A and B, the
+recursion (pre-additions, grouped leaf products, post-additions) and the
+device->host transfer of C, as the paper measures GFLOPS (2N^3 over
+wall-clock with transfers included, Section 4).  The plain SGEMM (depth 0)
+runs on the same path as the comparator.  The same product with the operands
+already resident in HBM is reported beside it (`hbm_resident`).  Inputs are
+seeded synthetic (uniform on the 2^-23 grid of [-1, 1)).  Prints one JSON
+line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--depth D]
 """
@@ -18,6 +20,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -32,12 +36,28 @@ PEAK_16BIT_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 matrix peak
 SPLIT_FORMS = {8: ("bf16x3", "leaf_pack_kernel<0> + leaf_packed_kernel<0,256,256,4,4>"),
                9: ("fp16x3", "leaf_scale_kernel + leaf_pack_kernel<1> + leaf_packed_kernel<1,256,256,4,4>")}
 PEAK_HBM_GBS = 8000.0
-# HBM bytes per leaf launch (HBM-resident depth-3 call: one grouped launch of
-# 343 leaves of 2432 x 2432 x 2432) from the FETCH_SIZE and WRITE_SIZE counter
-# runs, each scaled by its reading for a 1 GiB calibration copy (fetch x2.000,
-# write x1.000); see profiles/leaf_gemm_n19456_d3_device_hbm_traffic.md.
-# Valid for leaf_gemm_kernel<128,128,16,2,2> in that configuration only.
-TRAFFIC_BYTES_PER_LAUNCH = 37642619.6 * 1024 * 2.000 + 7924672.0 * 1024 * 1.000
+# HBM bytes per leaf launch from the FETCH_SIZE and WRITE_SIZE counter runs,
+# each scaled by its reading for a 1 GiB calibration copy (fetch x2.000,
+# write x1.000).  HBM-resident depth-3 call: one grouped launch of 343 leaves
+# of 2432 x 2432 x 2432 (profiles/leaf_gemm_n19456_d3_device_hbm_traffic.md).
+# Pinned-host depth-3 call: None until the counters are taken for the
+# current pipelined schedule.  Valid for leaf_gemm_kernel<128,128,16,2,2> in
+# those configurations only.
+TRAFFIC_DEVICE_BYTES_PER_LAUNCH = 37642619.6 * 1024 * 2.000 + 7924672.0 * 1024 * 1.000
+TRAFFIC_PINNED_BYTES_PER_LAUNCH = None
+
+
+def cpu_model():
+    """The host CPU's model name (the oracle's cores are reported with it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def log(msg):
@@ -59,24 +79,29 @@ def time_calls(fn, steps, warmup):
     return time.perf_counter() - t0, times
 
 
-def batched_context(fastmm, torch):
-    """256 independent products with M, N, K log-uniform in [256, 6144]
-    (multiples of 64), device-resident, uniform[-1, 1) inputs: one
-    fastmm_gemm_batched call (each problem's plan from the default rule;
-    replayed from its HIP graph after the first call) against the same
-    products issued one fastmm_gemm call at a time, and against the batched
-    plain product (depth 0)."""
+def batched_context(fastmm, torch, with_planner=True):
+    """The 256-problem batched workload: M, N, K log-uniform in [256, 6144]
+    (multiples of 64, shape seed 3001), seeded uniform[-1, 1) operands,
+    device-resident, one fastmm_gemm_batched call (replayed from its HIP
+    graph after the first).  Timed with the plans of each planner mode --
+    DEFAULT (fixed rule), MODEL (the cost model, trained first on the
+    exhaustive timings of 160 shapes of seed 4001) and EXHAUSTIVE (every
+    candidate of every shape timed) -- against the batched plain product
+    (depth 0) and the same products as 256 single fastmm_gemm calls.  The
+    last result of each mode is checked against the oracle (2 sampled rows
+    and Freivalds' check per problem)."""
     import synthgen
-    shapes = synthgen.shapes_loguniform(3001, 256, lo=256, hi=6144)
-    g = torch.Generator(device="cuda")
-    g.manual_seed(5001)
-    As, Bs, Cs = [], [], []
-    for m, n, k in shapes.tolist():
-        As.append(torch.rand((m, k), device="cuda", generator=g) * 2 - 1)
-        Bs.append(torch.rand((k, n), device="cuda", generator=g) * 2 - 1)
+    from oracle import checks
+    shapes = [tuple(int(v) for v in x) for x in synthgen.shapes_loguniform(3001, 256, lo=256, hi=6144)]
+    hA, hB, As, Bs, Cs = [], [], [], [], []
+    for i, (m, n, k) in enumerate(shapes):
+        sa, sb = synthgen.batch_seeds(5, i)
+        hA.append(synthgen.uniform_pm1(sa, m, k))
+        hB.append(synthgen.uniform_pm1(sb, k, n))
+        As.append(torch.from_numpy(hA[-1]).to("cuda"))
+        Bs.append(torch.from_numpy(hB[-1]).to("cuda"))
         Cs.append(torch.empty((m, n), device="cuda"))
-    flops = float(sum(2.0 * m * n * k for m, n, k in shapes.tolist()))
-    fastmm.set_plan_mode(fastmm.PLAN_DEFAULT)
+    flops = float(sum(2.0 * m * n * k for m, n, k in shapes))
     # No per-phase timing events here: they cost about 4 us each per call,
     # which the 256 single calls would otherwise pay.
     fastmm.set_profiling(False)
@@ -84,27 +109,60 @@ def batched_context(fastmm, torch):
     def timed(fn, reps):
         fn()
         torch.cuda.synchronize()
-        best = 1e30
+        ts = []
         for _ in range(reps):
             t = time.perf_counter()
             fn()
             torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t)
-        return best
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts)), min(ts)
 
-    t_b = timed(lambda: fastmm.gemm_batched(As, Bs, Cs), 3)
-    st = fastmm.get_stats()
-    t_plain = timed(lambda: fastmm.gemm_batched(As, Bs, Cs, depth=[0] * len(As)), 3)
+    def parity():
+        worst = 0.0
+        for i, (m, n, k) in enumerate(shapes):
+            C = Cs[i].cpu().numpy()
+            rows = synthgen.row_sample(7100 + i, m, 2)
+            worst = max(worst, checks.sampled_rows_rel(C, hA[i], hB[i], rows),
+                        checks.freivalds_rel(C, hA[i], hB[i], synthgen.signs_pm1(7400 + i, n)))
+        return worst
+
+    out = {"problems": len(shapes), "flops": flops, "modes": {}}
+    modes = [("default", fastmm.PLAN_DEFAULT)]
+    if with_planner:
+        log("bench: batched: timing the planner's training shapes, training the cost model")
+        t = time.perf_counter()
+        for (M, N, K) in synthgen.shapes_loguniform(4001, 160):
+            fastmm.plan(int(M), int(N), int(K), fastmm.PLAN_EXHAUSTIVE)
+        loss = fastmm.planner_train(epochs=400, batch=64, lr=3e-3, seed=4001)
+        out["model_training"] = {"shapes": 160, "records": fastmm.planner_records(),
+                                 "loss": loss, "seconds": time.perf_counter() - t}
+        modes += [("model", fastmm.PLAN_MODEL), ("exhaustive", fastmm.PLAN_EXHAUSTIVE)]
+    for name, code in modes:
+        fastmm.set_plan_mode(code)
+        t = time.perf_counter()
+        fastmm.gemm_batched(As, Bs, Cs)  # first call: plans (EXHAUSTIVE times every candidate), capture
+        first = time.perf_counter() - t
+        med, best = timed(lambda: fastmm.gemm_batched(As, Bs, Cs), 5)
+        st = fastmm.get_stats()
+        out["modes"][name] = {"ms": 1e3 * med, "ms_min": 1e3 * best, "TFLOPS": flops / med / 1e12,
+                              "first_call_s": first, "max_depth": st["depth"], "leaves": st["leaves"],
+                              "leaf_launches": st["leaf_launches"], "launches": st["launches"],
+                              "graph_replayed": st["graph_replayed"], "parity_worst_rel": parity()}
+    fastmm.set_plan_mode(fastmm.PLAN_DEFAULT)
+    if with_planner:
+        out["model_regret_vs_exhaustive"] = out["modes"]["model"]["ms"] / out["modes"]["exhaustive"]["ms"] - 1
+        out["model_gain_vs_default"] = out["modes"]["default"]["ms"] / out["modes"]["model"]["ms"]
+    med, best = timed(lambda: fastmm.gemm_batched(As, Bs, Cs, depth=[0] * len(As)), 5)
+    out["plain_batched"] = {"ms": 1e3 * med, "TFLOPS": flops / med / 1e12, "parity_worst_rel": parity()}
 
     def singles():
-        for (m, n, k), A, B, C in zip(shapes.tolist(), As, Bs, Cs):
+        for (m, n, k), A, B, C in zip(shapes, As, Bs, Cs):
             fastmm.gemm(m, n, k, A, B, C, depth=-1)
-    t_s = timed(singles, 1)
+    med, best = timed(singles, 1)
+    out["single_calls"] = {"ms": 1e3 * med, "TFLOPS": flops / med / 1e12}
+    out["tolerance"] = 1e-4
     fastmm.set_profiling(True)
-    return {"problems": len(As), "flops": flops, "ms": 1e3 * t_b, "TFLOPS": flops / t_b / 1e12,
-            "graph_replayed": st["graph_replayed"], "launches": st["launches"],
-            "plain_batched_ms": 1e3 * t_plain, "plain_batched_TFLOPS": flops / t_plain / 1e12,
-            "single_calls_ms": 1e3 * t_s, "single_calls_TFLOPS": flops / t_s / 1e12}
+    return out
 
 
 def sweep(fastmm, torch, sizes):
@@ -176,18 +234,19 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-pinned", action="store_true",
-                    help="skip the pinned-host (transfer-inclusive) context")
+    ap.add_argument("--operands", choices=["pinned", "device"], default="pinned",
+                    help="where A, B, C live in the timed loop: pinned host memory (transfers "
+                         "timed, the headline) or HBM")
     ap.add_argument("--no-device-context", action="store_true",
-                    help="skip the addition-kernel and classic-recursion context")
+                    help="skip the HBM-resident, classic-recursion and precision-form context")
     ap.add_argument("--no-shards", action="store_true",
                     help="skip one GPU's share of the sharded product")
     ap.add_argument("--no-rect", action="store_true",
                     help="skip the rectangular 19456 x 16384 x 12288 context block")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-problem batched context (uneven shapes)")
-    ap.add_argument("--pinned-headline", action="store_true",
-                    help="time the pinned-host path in the main loop (profiling that path)")
+    ap.add_argument("--no-planner", action="store_true",
+                    help="batched context with the fixed rule only (no cost-model training)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="first run one plain 1 GiB device copy (calibrates HBM counters)")
     ap.add_argument("--precision-config", action="store_true",
@@ -225,7 +284,8 @@ def main():
         torch.cuda.empty_cache()
     n = args.n
     M = N = K = n
-    log(f"bench: n={n} generating operands (pinned host), copying to HBM")
+    on_device = args.operands == "device"
+    log(f"bench: n={n} generating operands (pinned host)")
     hA = torch.empty((M, K), dtype=torch.float32, pin_memory=True)
     hB = torch.empty((K, N), dtype=torch.float32, pin_memory=True)
     hC = torch.empty((M, N), dtype=torch.float32, pin_memory=True)
@@ -233,11 +293,11 @@ def main():
     synthgen.fill_uniform_pm1(1001 + 3, M, K, hA.data_ptr())
     synthgen.fill_uniform_pm1(2001 + 3, K, N, hB.data_ptr())
     flops = 2.0 * M * N * K
-    if args.pinned_headline:
-        A, B, C = hA, hB, hC
-    else:
-        A, B = hA.to("cuda"), hB.to("cuda")
-        C = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    dA = dB = dC = None
+    if on_device or not args.no_device_context:
+        dA, dB = hA.to("cuda"), hB.to("cuda")
+        dC = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    A, B, C = (dA, dB, dC) if on_device else (hA, hB, hC)
     torch.cuda.synchronize()
 
     fastmm.set_profiling(True)
@@ -245,14 +305,18 @@ def main():
     def run(depth, a=A, b=B, c=C):
         return lambda: fastmm.gemm(M, N, K, a, b, c, depth=depth, leaf=args.leaf, tile=args.tile)
 
-    # Plain MFMA SGEMM (depth 0) on the same operands.
+    def stats_ms(ts):
+        q = np.percentile(np.asarray(ts) * 1e3, [25, 50, 75])
+        return {"median": float(q[1]), "min": 1e3 * min(ts), "iqr": float(q[2] - q[0])}
+
+    # Plain MFMA SGEMM (depth 0) on the same operands and path.
     plain = None
     if not args.no_plain:
         log("bench: plain SGEMM (depth 0)")
         tot, ts = time_calls(run(0), args.steps, args.warmup)
         st = fastmm.get_stats()
         plain = {"ms_per_step": 1e3 * tot / args.steps, "value": flops / (tot / args.steps) / 1e9,
-                 "leaf_ms": st["leaf_ms"],
+                 "ms": stats_ms(ts), "leaf_ms": st["leaf_ms"],
                  "leaf_tflops": st["leaf_flops"] / (st["leaf_ms"] * 1e-3) / 1e12}
         log(f"  plain: {plain}")
 
@@ -267,15 +331,21 @@ def main():
     else:
         best = depths[0]
     log(f"bench: Winograd depth {best}, {args.steps} timed steps")
-    leaf_ms = []
+    leaf_ms, leaf_launches, step_s = [], [], []
 
     def step():
+        t = time.perf_counter()
         fastmm.gemm(M, N, K, A, B, C, depth=best, leaf=args.leaf, tile=args.tile)
-        leaf_ms.append(fastmm.get_stats()["leaf_ms"])
+        step_s.append(time.perf_counter() - t)
+        s_ = fastmm.get_stats()
+        leaf_ms.append(s_["leaf_ms"])
+        leaf_launches.append(s_["leaf_launches"])
 
     for _ in range(args.warmup):
         step()
     leaf_ms.clear()
+    leaf_launches.clear()
+    step_s.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -291,7 +361,7 @@ def main():
     from oracle import checks
     An = hA.numpy()
     Bn = hB.numpy()
-    Cn = C.cpu().numpy()
+    Cn = C.cpu().numpy() if on_device else hC.numpy()
     rows = synthgen.row_sample(7004, M, 8)
     parity = {"sampled_rows_rel": checks.sampled_rows_rel(Cn, An, Bn, rows),
               "freivalds_rel": checks.freivalds_rel(Cn, An, Bn, synthgen.signs_pm1(7005, N)),
@@ -300,61 +370,100 @@ def main():
 
     # Dominant kernel: the grouped leaf GEMM.  Its launches are timed with
     # HIP events recorded by the library on the stream it launches them on.
-    n_launch = max(1, st["leaf_launches"])
-    leaf_sum = float(np.mean(leaf_ms))          # ms per step, all leaf launches
-    avg_launch = leaf_sum / n_launch
-    flops_launch = st["leaf_flops"] / n_launch
-    leaf_tflops = flops_launch / (avg_launch * 1e-3) / 1e12
-    traffic_ok = (TRAFFIC_BYTES_PER_LAUNCH is not None and not args.pinned_headline and best == 3
-                  and n == 19456 and args.tile == 0 and args.leaf == 1024)
+    def leaf_roofline(leaf_list, launch_list, stats, traffic, kernel):
+        n_launch = max(1, int(np.mean(launch_list)))
+        leaf_sum = float(np.mean(leaf_list))          # ms per step, all leaf launches
+        avg_launch = leaf_sum / n_launch
+        flops_launch = stats["leaf_flops"] / n_launch
+        tf = flops_launch / (avg_launch * 1e-3) / 1e12
+        peak = PEAK_16BIT_TFLOPS / 3 if split else PEAK_FP32_TFLOPS
+        return {"bound": "mfma", "kernel": kernel, "achieved": tf, "peak": peak, "unit": "TFLOP/s",
+                "frac": tf / peak, "traffic": traffic, "flops_per_launch": flops_launch,
+                "avg_launch_ms": avg_launch, "launches_per_step": n_launch}, leaf_sum
+
     split = SPLIT_FORMS.get(args.tile)
-    peak = PEAK_16BIT_TFLOPS / 3 if split else PEAK_FP32_TFLOPS
     if split and st["depth"] >= 1:  # the scale and pack passes run fused with the last pre-additions
         kernel = f"leaf_packed_kernel<{args.tile - 8},256,256,4,4>"
     else:
         kernel = split[1] if split else "leaf_gemm_kernel<128,128,16,2,2> (grouped leaves)"
-    roofline = {"bound": "mfma", "kernel": kernel,
-                "achieved": leaf_tflops, "peak": peak, "unit": "TFLOP/s", "frac": leaf_tflops / peak,
-                "traffic": TRAFFIC_BYTES_PER_LAUNCH if traffic_ok else None,
-                "flops_per_launch": flops_launch, "avg_launch_ms": avg_launch,
-                "launches_per_step": n_launch}
+    std_cfg = best == 3 and n == 19456 and args.tile == 0 and args.leaf == 1024
+    traffic = (TRAFFIC_DEVICE_BYTES_PER_LAUNCH if on_device else TRAFFIC_PINNED_BYTES_PER_LAUNCH) \
+        if std_cfg else None
+    roofline, leaf_sum = leaf_roofline(leaf_ms, leaf_launches, st, traffic, kernel)
     phases = {"leaf_ms": leaf_sum, "preadd_ms": st["preadd_ms"], "postadd_ms": st["postadd_ms"],
+              "h2d_span_ms": st["h2d_ms"], "call_span_ms": st["total_ms"],
               "add_bytes": st["add_bytes"], "transfer_bytes": st["transfer_bytes"]}
     add_ms = st["preadd_ms"] + st["postadd_ms"]
     if add_ms > 0:
         phases["add_GBps"] = st["add_bytes"] / (add_ms * 1e-3) / 1e9
         phases["add_frac_of_hbm_peak"] = phases["add_GBps"] / PEAK_HBM_GBS
 
+    # Context: the same product with A, B, C already resident in HBM (no
+    # transfers in the wall-clock), best depth of 2-4, and the plain SGEMM.
+    hbm = None
+    if not on_device and not args.no_device_context:
+        log("bench: HBM-resident context")
+        hp = {}
+        for d in (2, 3, 4):
+            tot, ts = time_calls(run(d, dA, dB, dC), 2, 1)
+            hp[d] = min(ts)
+        hb = min(hp, key=hp.get)
+        lm, ll, hs = [], [], []
+        fn = run(hb, dA, dB, dC)
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        for _ in range(max(5, min(args.steps, 10))):
+            t = time.perf_counter()
+            fn()
+            hs.append(time.perf_counter() - t)
+            s_ = fastmm.get_stats()
+            lm.append(s_["leaf_ms"])
+            ll.append(s_["leaf_launches"])
+        sh = fastmm.get_stats()
+        hroof, hleaf = leaf_roofline(lm, ll, sh, TRAFFIC_DEVICE_BYTES_PER_LAUNCH
+                                     if hb == 3 and n == 19456 and args.tile == 0 and args.leaf == 1024
+                                     else None, kernel)
+        hbm = {"depth": hb, "ms": stats_ms(hs), "effective_GFLOPS": flops / float(np.median(hs)) / 1e9,
+               "depth_probe_ms": {str(k): 1e3 * v for k, v in hp.items()}, "roofline": hroof,
+               "preadd_ms": sh["preadd_ms"], "postadd_ms": sh["postadd_ms"], "add_bytes": sh["add_bytes"]}
+        if sh["preadd_ms"] + sh["postadd_ms"] > 0:
+            hbm["add_GBps"] = sh["add_bytes"] / ((sh["preadd_ms"] + sh["postadd_ms"]) * 1e-3) / 1e9
+        if not args.no_plain:
+            tot, ts = time_calls(run(0, dA, dB, dC), max(3, min(args.steps, 5)), 1)
+            hbm["plain_ms"] = stats_ms(ts)
+            hbm["speedup_vs_plain"] = hbm["plain_ms"]["median"] / hbm["ms"]["median"]
+        log(f"bench: HBM-resident {hbm}")
+
     # Context: the paper's own algorithm, the classic eight-product recursion
     # of Table 1 at its recursion point (leaves below 6016, i.e. leaf cutoff
-    # 3008), MFMA leaves, same operands.
+    # 3008), MFMA leaves, operands in HBM.
     classic = None
-    if not args.no_device_context and not args.pinned_headline:
-        fastmm.rmul(M, N, K, A, B, C, depth=8, leaf=3008)
+    if dA is not None and not args.no_device_context:
+        fastmm.rmul(M, N, K, dA, dB, dC, depth=8, leaf=3008)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        fastmm.rmul(M, N, K, A, B, C, depth=8, leaf=3008)
+        fastmm.rmul(M, N, K, dA, dB, dC, depth=8, leaf=3008)
         torch.cuda.synchronize()
         t = time.perf_counter() - t
         classic = {"ms": 1e3 * t, "effective_GFLOPS": flops / t / 1e9,
-                   "depth": fastmm.get_stats()["depth"], "leaf": 3008}
+                   "depth": fastmm.get_stats()["depth"], "leaf": 3008, "operands": "HBM"}
         log(f"bench: classic recursion {classic}")
 
     # Context: the split-precision leaf forms (never the FP32 headline): split
     # BF16 (tile 8) and scaled split FP16 (tile 9) leaves, plain and at depth
-    # 2 (their workload's depth), same operands in HBM; sampled-row error
-    # against the oracle.  Leaf times include the forms' pack (and FP16
-    # scale) passes.
+    # 2 (their workload's depth), operands in HBM; sampled-row error against
+    # the oracle.  Leaf times include the forms' pack (and FP16 scale) passes.
     precision = None
-    if not args.no_device_context and not args.pinned_headline:
+    if dA is not None and not args.no_device_context:
         precision = {}
         rows_p = synthgen.row_sample(7008, M, 4)
         for name, tile in (("bf16x3", 8), ("fp16x3", 9)):
             for d in (0, 2):
-                fn = lambda: fastmm.gemm(M, N, K, A, B, C, depth=d, leaf=args.leaf, tile=tile)
+                fn = lambda: fastmm.gemm(M, N, K, dA, dB, dC, depth=d, leaf=args.leaf, tile=tile)
                 tot, ts = time_calls(fn, 3, 1)
                 sp = fastmm.get_stats()
-                Cp = C.cpu().numpy()
+                Cp = dC.cpu().numpy()
                 precision[f"{name}_depth{sp['depth']}"] = {
                     "ms": 1e3 * min(ts), "effective_GFLOPS": flops / min(ts) / 1e9,
                     "leaf_ms": sp["leaf_ms"],
@@ -365,31 +474,12 @@ def main():
                 del Cp
         log(f"bench: precision forms {precision}")
 
-    # Context: the same products with operands in pinned host memory, the
-    # transfers inside the wall-clock (pipelined host path).
-    pinned = None
-    if not args.no_pinned and not args.pinned_headline:
-        ps = max(2, min(args.steps, 3))
-        tot, ts = time_calls(run(best, hA, hB, hC), ps, 1)
-        sp = fastmm.get_stats()
-        pinned = {"ms_per_step": 1e3 * tot / ps, "effective_GFLOPS": flops / (tot / ps) / 1e9,
-                  "depth": sp["depth"], "leaf_ms": sp["leaf_ms"],
-                  "leaf_TFLOPs_per_launch": sp["leaf_flops"] / (sp["leaf_ms"] * 1e-3) / 1e12,
-                  "leaf_launches": sp["leaf_launches"], "h2d_span_ms": sp["h2d_ms"],
-                  "transfer_bytes": sp["transfer_bytes"]}
-        if not args.no_plain:
-            tot, ts = time_calls(run(0, hA, hB, hC), ps, 1)
-            pinned["plain_ms_per_step"] = 1e3 * tot / ps
-            pinned["plain_effective_GFLOPS"] = flops / (tot / ps) / 1e9
-            pinned["speedup_vs_plain"] = pinned["plain_ms_per_step"] / pinned["ms_per_step"]
-        log(f"bench: pinned host {pinned}")
-
     # One GPU's share of the column-panel sharding (the paper's two-device
     # split, eqs. (3)-(4), generalised): 1 x 8 panels (19456 x 19456 x 2432)
     # and a 2 x 4 grid (9728 x 19456 x 4864), staged from the pinned host
     # operands (strided views), as many levels as the leaf cutoff allows.
     shards = None
-    if n == 19456 and not args.no_shards and not args.pinned_headline:
+    if n == 19456 and not args.no_shards and not on_device:
         shards = {}
         for name, (sm, sn) in {"panel_1x8": (M, N // 8), "grid_2x4": (M // 2, N // 4)}.items():
             fn = lambda: fastmm.gemm(sm, sn, K, hA[:sm], hB[:, :sn], hC[:sm, :sn], depth=16,
@@ -405,13 +495,12 @@ def main():
     # plain, and the same shape with operands in HBM; strided views of the
     # square operands.
     rect = None
-    if (n == 19456 and not args.no_rect and not args.pinned_headline and not args.no_pinned
-            and not args.no_device_context):
+    if n == 19456 and not args.no_rect and dA is not None and not on_device:
         rm, rk, rn = 19456, 16384, 12288
         rect = {"M": rm, "N": rn, "K": rk, "pinned_ms": {}, "device_ms": {}}
         rf = 2.0 * rm * rn * rk
         for where, (a, b, c) in (("pinned_ms", (hA[:, :rk], hB[:rk, :rn], hC[:, :rn])),
-                                 ("device_ms", (A[:, :rk], B[:rk, :rn], C[:, :rn]))):
+                                 ("device_ms", (dA[:, :rk], dB[:rk, :rn], dC[:, :rn]))):
             for d in (0, 2, 3, 4):
                 fn = lambda: fastmm.gemm(rm, rn, rk, a, b, c, depth=d, leaf=1)
                 tot, ts = time_calls(fn, 2, 1)
@@ -425,8 +514,11 @@ def main():
         log(f"bench: rectangular {rect}")
 
     batched = None
-    if not args.no_batched and not args.pinned_headline:
-        batched = batched_context(fastmm, torch)
+    if not args.no_batched and not on_device:
+        del dA, dB, dC
+        dA = dB = dC = None
+        torch.cuda.empty_cache()
+        batched = batched_context(fastmm, torch, with_planner=not args.no_planner)
         log(f"bench: batched context {batched}")
 
     cpu = None
@@ -443,30 +535,31 @@ def main():
         oracle_classic.gemm_rows(An, Bn, rows_c)
         dt = time.perf_counter() - t
         cpu = {"value": 2.0 * rows_c.size * N * K / dt / 1e9, "unit": "GFLOPS", "cores": threads,
-               "kind": "oracle",
+               "cpu_model": cpu_model(), "kind": "oracle",
                "sample": f"{rows_c.size} seeded rows of C (FP64-accumulated triple loop, "
                          f"OpenMP over rows), {dt:.1f} s"}
         log(f"bench: cpu {cpu}")
 
-    where = ("pinned host in/out (transfers timed)" if args.pinned_headline
-             else "operands resident in HBM")
+    where = ("operands resident in HBM" if on_device
+             else "pinned host in/out (H2D and D2H transfers inside the wall-clock)")
     out = {
         "metric": METRIC, "value": value, "unit": "GFLOPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "ms": stats_ms(step_s),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": split[0] if split else "f32",
         "data": "synthetic",
         "config": {"workload": f"FP32 Winograd-Strassen C=A*B, square n={n}, {where}, "
                                + (f"{split[0]} leaves, " if split else "") +
                                f"depth {st['depth']}, leaf {args.leaf}",
                    "M": M, "N": N, "K": K, "depth": st["depth"], "leaf": args.leaf,
-                   "tile": args.tile, "parallelism": "single GPU"},
+                   "tile": args.tile, "operands": args.operands, "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu,
         "plain_sgemm": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms_per_step) if plain else None,
         "depth_probe_ms": {str(k): 1e3 * v for k, v in probe.items()},
-        "phases": phases, "classic_recursion": classic, "precision_forms": precision,
-        "pinned_host": pinned,
-        "batched": batched, "shards": shards, "rectangular": rect, "parity": parity,
+        "phases": phases, "hbm_resident": hbm, "classic_recursion": classic,
+        "precision_forms": precision, "batched": batched, "shards": shards, "rectangular": rect,
+        "parity": parity,
     }
     print(json.dumps(out), flush=True)
 
