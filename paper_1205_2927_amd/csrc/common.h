@@ -43,10 +43,11 @@ struct GemmDesc {
 };
 
 // One node of a pre-addition launch: reads the four quadrants of a parent
-// operand (or a band of rows of each) and writes four h_r x h_c results.
-// Quadrant X11 starts at src, X12 at src + h_c, X21 at src + bot_off and
-// X22 at src + bot_off + h_c, all with leading dimension ld; rows / columns
-// beyond the valid counts read as zero.  Output q (0..3) starts at
+// operand (or a band of rows or of columns of each) and writes four h_r x h_c
+// results.  Quadrant X11 starts at src, X12 at src + right_off, X21 at
+// src + bot_off and X22 at src + bot_off + right_off, all with leading
+// dimension ld (right_off = h_c for whole quadrants); rows / columns beyond
+// the valid counts read as zero.  Output q (0..3) starts at
 // dst + q * out_stride with leading dimension h_c.
 struct PreAddNode {
   const float* src;
@@ -59,6 +60,8 @@ struct PreAddNode {
   int32_t h_r, h_c;               // rows of this node, quadrant width
   int32_t block_begin;            // first workgroup of this node within the launch
   int32_t mask;                   // outputs to write (bit q-1 for S_q / T_q); 0 = all
+  int32_t right_off;              // offset of the right quadrants from the left ones
+  int32_t pad_;
 };
 
 // One node of a fused pre-addition and pack launch (split-BF16 leaves, last
@@ -93,10 +96,11 @@ inline unsigned preadd_inputs(int side, unsigned outputs) {
 }
 
 // One node of a post-addition launch: reads seven h_r x h_c products (P_i at
-// P + i * p_stride, leading dimension h_c) and writes the result quadrants:
-// C11 at dst, C12 at dst + h_c, C21 at dst + bot_off, C22 at
-// dst + bot_off + h_c (leading dimension ld), each clipped to its valid
-// rows / columns.
+// P + i * p_stride, leading dimension h_c) and writes the result quadrants
+// (or a band of rows or of columns of each): C11 at dst, C12 at
+// dst + right_off, C21 at dst + bot_off, C22 at dst + bot_off + right_off
+// (leading dimension ld; right_off = h_c for whole quadrants), each clipped
+// to its valid rows / columns.
 struct PostAddNode {
   const float* P;
   float* dst;
@@ -107,7 +111,7 @@ struct PostAddNode {
   int32_t left_cols, right_cols;
   int32_t h_r, h_c;
   int32_t block_begin;
-  int32_t pad_;
+  int32_t right_off;  // offset of C12 / C22 from C11 / C21
 };
 
 // One node of a multi-level addition launch: L consecutive levels of the
@@ -157,6 +161,7 @@ inline PreAddNode preadd_node(const float* src, int64_t ld, int64_t vrows, int64
   n.right_cols = clamp_extent(vcols - h_c, h_c);
   n.h_r = (int32_t)h_r;
   n.h_c = (int32_t)h_c;
+  n.right_off = (int32_t)h_c;
   return n;
 }
 
@@ -176,6 +181,7 @@ inline PostAddNode postadd_node(const float* P, int64_t h_r, int64_t h_c, float*
   n.right_cols = clamp_extent(cols - h_c, h_c);
   n.h_r = (int32_t)h_r;
   n.h_c = (int32_t)h_c;
+  n.right_off = (int32_t)h_c;
   return n;
 }
 

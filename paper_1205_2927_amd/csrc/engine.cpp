@@ -56,12 +56,12 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 // 16-byte accesses need every quadrant and output row start 16-byte aligned.
 bool pre_vec_ok(const PreAddNode& n) {
   return aligned16(n.src) && aligned16(n.dst) && n.ld % 4 == 0 && n.h_c % 4 == 0 &&
-         n.bot_off % 4 == 0 && n.out_stride % 4 == 0;
+         n.bot_off % 4 == 0 && n.out_stride % 4 == 0 && n.right_off % 4 == 0;
 }
 
 bool post_vec_ok(const PostAddNode& n) {
   return aligned16(n.P) && aligned16(n.dst) && n.ld % 4 == 0 && n.h_c % 4 == 0 &&
-         n.bot_off % 4 == 0 && n.p_stride % 4 == 0;
+         n.bot_off % 4 == 0 && n.p_stride % 4 == 0 && n.right_off % 4 == 0;
 }
 
 void set_error(const std::string& msg) { t_last_error = msg; }
@@ -203,12 +203,25 @@ size_t b_tree_bytes(int64_t M, int64_t K, int64_t N, int depth) {
   return floats * sizeof(float);
 }
 
+size_t a_tree_bytes(int64_t M, int64_t K, int64_t N, int depth) {
+  Problem p;
+  p.M = M;
+  p.K = K;
+  p.N = N;
+  p.depth = depth;
+  const auto dims = level_dims(p);
+  size_t floats = 0;
+  for (int l = 0; l < depth; ++l)
+    floats += align_up((size_t)pow7(l) * 4 * dims[l + 1].m * dims[l + 1].k, kAlignFloats);
+  return floats * sizeof(float);
+}
+
 size_t problem_temp_bytes(const Problem& p) {
   const auto dims = level_dims(p);
   size_t floats = 0;
   for (int l = 0; l < p.depth; ++l) {
     const Dims& c = dims[l + 1];
-    floats += align_up((size_t)pow7(l) * 4 * c.m * c.k, kAlignFloats);
+    if (!p.a_tree) floats += align_up((size_t)pow7(l) * 4 * c.m * c.k, kAlignFloats);
     if (!p.b_tree) floats += align_up((size_t)pow7(l) * 4 * c.k * c.n, kAlignFloats);
   }
   for (int l = 1; l <= p.depth; ++l)
@@ -270,10 +283,11 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     const int d = p.depth;
     std::vector<View> Av{{p.A, p.lda, p.ar(), p.ac()}}, Bv{{p.B, p.ldb, p.br(), p.bc()}};
     size_t t_off = 0;  // floats into p.b_tree
+    size_t s_off = 0;  // floats into p.a_tree
     // Fused pre-addition and pack (split-BF16 leaves, depth >= 1, no shared
     // B tree): nodes of the last level whose quadrants allow 16-byte access.
     const bool fuse = fuse_allowed && (p.tile == kTileBf16x3 || p.tile == kTileFp16x3) && d >= 1 &&
-                      !p.b_tree;
+                      !p.b_tree && !p.a_tree;
     const int fmt = p.tile == kTileFp16x3 ? 1 : 0;
     struct Fused {
       int64_t x;
@@ -290,7 +304,13 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     for (int l = 0; l < d; ++l) {
       const Dims c = dims[l + 1];
       const int64_t nodes = pow7(l);
-      float* S = carve((size_t)nodes * 4 * c.m * c.k);
+      float* S;
+      if (p.a_tree) {
+        S = p.a_tree + s_off;
+        s_off += align_up((size_t)nodes * 4 * c.m * c.k, kAlignFloats);
+      } else {
+        S = carve((size_t)nodes * 4 * c.m * c.k);
+      }
       float* T;
       if (p.b_tree) {
         T = p.b_tree + t_off;
@@ -308,7 +328,7 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
         if (fuse && l == d - 1 && pre_vec_ok(na) && pre_vec_ok(nb)) {
           fused.push_back({x, na, nb});
         } else {
-          lvA[l].push_back(na);
+          if (!p.a_tree_ready) lvA[l].push_back(na);
           if (!p.b_tree_ready) lvB[l].push_back(nb);
         }
         const View a11 = quadrant(a, 0, 0, c.m, c.k), a12 = quadrant(a, 0, 1, c.m, c.k),
@@ -330,7 +350,7 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
       Bv.swap(nB);
       Sb[l] = S;
       Tb[l] = T;
-      byA[l] = (double)nodes * 32.0 * c.m * c.k;
+      byA[l] = p.a_tree_ready ? 0.0 : (double)nodes * 32.0 * c.m * c.k;
       byB[l] = p.b_tree_ready ? 0.0 : (double)nodes * 32.0 * c.k * c.n;
     }
     // Group the levels from the bottom up: the deepest levels hold the most
@@ -405,7 +425,7 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
         }
       }
     };
-    pre_side(0, lvA, Sb, byA, s.preA);
+    if (!p.a_tree_ready) pre_side(0, lvA, Sb, byA, s.preA);
     if (!p.b_tree_ready) pre_side(1, lvB, Tb, byB, s.preB);
     // Product buffers P[l] (l = 1..d), 7^l blocks of m_l x n_l.
     std::vector<float*> P(d + 1, nullptr);

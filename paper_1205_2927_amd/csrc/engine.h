@@ -84,6 +84,10 @@ struct Problem {
   // pre-additions are issued.
   float* b_tree = nullptr;
   bool b_tree_ready = false;
+  // The same for the A-side temporaries (the S blocks of every level,
+  // a_tree_bytes of them), for products that share their left operand.
+  float* a_tree = nullptr;
+  bool a_tree_ready = false;
   int64_t ar() const { return a_rows < 0 ? M : a_rows; }
   int64_t ac() const { return a_cols < 0 ? K : a_cols; }
   int64_t br() const { return b_rows < 0 ? K : b_rows; }
@@ -134,10 +138,13 @@ struct Schedule {
 };
 
 // Bytes of temporaries a problem needs in the schedule's workspace (no
-// allocation; without the B-side blocks when p.b_tree is set).
+// allocation; without the B-side blocks when p.b_tree is set, nor the A-side
+// ones when p.a_tree is).
 size_t problem_temp_bytes(const Problem& p);
-// Bytes of the B-side temporaries of a product with these extents and depth.
+// Bytes of the B-side (A-side) temporaries of a product with these extents
+// and depth.
 size_t b_tree_bytes(int64_t M, int64_t K, int64_t N, int depth);
+size_t a_tree_bytes(int64_t M, int64_t K, int64_t N, int depth);
 
 // Builds the schedule; temporaries are carved from `ws` (device), which must
 // hold at least the sum of problem_temp_bytes.
@@ -158,9 +165,9 @@ struct Library {
   hipEvent_t ev[8] = {};
   hipStream_t h2d_stream = nullptr;  // host->device staging copies
   hipStream_t d2h_stream = nullptr;  // device->host result copies
-  static constexpr int kSyncEvents = 48;
+  static constexpr int kSyncEvents = 64;
   hipEvent_t sync_ev[kSyncEvents] = {};  // ordering between the streams
-  static constexpr int kLeafEvents = 48;
+  static constexpr int kLeafEvents = 128;
   hipEvent_t leaf_ev[kLeafEvents] = {};  // timing of leaf launches
   hipEvent_t tune_ev[2] = {};            // planner's candidate timing
   int* leaf_queue = nullptr;             // two counters for persistent leaf launches

@@ -8,24 +8,28 @@
 //
 // Here the top level of the recursion runs as a sequence of steps on a
 // compute stream while one copy stream brings operand blocks in and a second
-// copy stream sends result blocks back as soon as they are final.  The
-// A-side quadrants are moved and multiplied in two row bands: band b of a
-// top-level product, P_i[b] = L_i[b] R_i, needs only band b of its left
-// operand, and is itself a Winograd product of depth d - 1.
+// copy stream sends result blocks back as soon as they are final.  The top
+// quadrants are cut into two row bands (A side) and two column bands (B
+// side): piece (i, r, c) of top-level product i, P_i[r, c] = L_i[r] R_i[:, c],
+// needs only row band r of its left operand and column band c of its right
+// operand, and is itself a Winograd product of depth d - 1.  The pieces of
+// one product and row band (column band) share the inner recursion's
+// A-side (B-side) temporaries, computed by the first of them.
 //
 // Input order.  Every product needs a different subset of the eight
 // quadrants (P1: A11 B11; P7: A11 A21 B12 B22; P5: A21 A22 B11 B12; P6: A11
 // A21 A22 B11 B12 B22; P2: A12 B21; P4: A22 and all of B; P3: all of A and
-// B22).  Sending A12 and B21 last leaves only P2, P3 and P4 waiting for the
-// end of the transfer; the fixed order below (found by simulating the
-// copies and products at n = 19456) also interleaves bands so that products
-// can start early:
-//   A11[0] B11 A22[0] A11[1] A21[0] B12 B22 B21 A22[1] A21[1] A12[0] A12[1]
-// Products run greedily in order of estimated readiness.  Pre-additions
-// compute only the S / T outputs whose inputs have arrived (a later pass
-// adds the rest), and each result block C_q[b] is formed and sent out as
-// soon as its four products (C11: P1 P2; C12: P1 P6 P5 P3; C21: P1 P6 P7 P4;
-// C22: P1 P6 P7 P5) are done.
+// B22).  The fixed order of the 16 band blocks (found by simulating the
+// copies and the pieces at n = 19456 and searching over orders) starts
+// with the first bands of B11 and A11 and ends with A12, so that the first
+// piece waits for about a quarter of the data the first whole-band product
+// needed and only P2 and P3 wait for the end of the transfer.  Pieces run
+// greedily in order of estimated readiness.  Pre-additions compute only the
+// S / T outputs of a band whose inputs have arrived (a later pass adds the
+// rest), and each result block C_q[r, c] is formed and sent out as soon as
+// its four products (C11: P1 P2; C12: P1 P6 P5 P3; C21: P1 P6 P7 P4; C22: P1
+// P6 P7 P5) are done, so one block of one quadrant (about 1.5 ms of copy at
+// n = 19456) remains after the last piece.
 //
 #include <hip/hip_runtime.h>
 
@@ -79,11 +83,16 @@ struct Band {
   int64_t r0, rows, bot;
 };
 
+// Also column bands of the left quadrants' n2 columns (r0, rows: first
+// column and width; bot: valid columns of the right quadrants' band).  The
+// split is a multiple of `align` near the middle, else of 4 (16-byte aligned
+// band starts), else the middle.
 std::vector<Band> make_bands(int64_t m2, int64_t mb, int nb, int64_t align) {
   std::vector<Band> v;
   int64_t split = m2;
   if (nb >= 2 && m2 >= 2) {
     split = (m2 / 2 + align / 2) / align * align;
+    if (split <= 0 || split >= m2) split = (m2 / 2 + 3) / 4 * 4;
     if (split <= 0 || split >= m2) split = (m2 + 1) / 2;
   }
   v.push_back({0, split, std::min(split, mb)});
@@ -132,46 +141,85 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   };
   const size_t oA = take((size_t)M * K4 * 4), oB = take((size_t)K4 * N4 * 4),
                oC = take((size_t)M * N4 * 4);
-  size_t oS = 0, oT = 0, oP = 0;
-  if (wino) {
-    oS = take((size_t)4 * m2 * k2 * 4);
-    oT = take((size_t)4 * k2 * n2 * 4);
-    oP = take((size_t)7 * m2 * n2 * 4);
-  }
 
-  // ---- the steps, as groups of sub-problems (device pointers filled below)
-  // Bands of A's rows: for Winograd, of the top quadrants (m2 rows); for the
-  // plain product, of A itself (M rows) in quarters.
-  const int64_t align = (int64_t)ts.bm << (wino ? depth - 1 : 0);
-  std::vector<Band> bands;
+  // ---- bands.  Winograd: row bands of the top quadrants' rows (m2) and
+  // column bands of their columns (n2); a band of the bottom (right)
+  // quadrants keeps only its valid rows (columns).  Plain product: A's rows
+  // in quarters.
+  std::vector<Band> bands, cbands;
   if (wino) {
-    bands = make_bands(m2, mb, 2, align);
+    bands = make_bands(m2, mb, 2, (int64_t)ts.bm << (depth - 1));
+    cbands = make_bands(n2, nb, 2, (int64_t)ts.bn << (depth - 1));
   } else {
     // Quarters of M, rounded to whole tiles when M allows (at most 6 bands).
     int64_t q = (M + 3) / 4;
     if (q >= ts.bm) q = (q + ts.bm / 2) / ts.bm * ts.bm;
     for (int64_t r0 = 0; r0 < M; r0 += q) bands.push_back({r0, std::min(q, M - r0), 0});
   }
-  const int nband = (int)bands.size();
-  // Both row bands of a top-level product share its right operand, so the
-  // B-side temporaries of the inner recursion are computed by the first band
-  // and reused by the second: one region per product, outside the
-  // temporaries the bands take in turn.
-  const size_t bt_each =
-      (wino && nband > 1) ? align_up(b_tree_bytes(1, k2, n2, depth - 1), 256) : 0;
-  const size_t oBT = bt_each ? take(7 * bt_each) : 0;
-  char* bt_base = reinterpret_cast<char*>(256);  // placeholder until allocation
+  const int nband = (int)bands.size(), ncband = (int)cbands.size();
+  // Valid host columns of column band c of the right quadrants.
+  auto right_valid = [&](const Band& c) {
+    return std::max<int64_t>(0, std::min(c.rows, nb_v - c.r0));
+  };
+
+  // Winograd temporaries: S (four m2 x k2 blocks; a row band is a row range
+  // of each), T per column band (four dense k2 x cols blocks), and the seven
+  // products of each (row band, column band) block, dense rows x cols each.
+  size_t oS = 0, oT = 0, oP = 0;
+  std::vector<size_t> t_off(ncband), p_off((size_t)nband * ncband);
+  if (wino) {
+    oS = take((size_t)4 * m2 * k2 * 4);
+    size_t t = 0;
+    for (int c = 0; c < ncband; ++c) {
+      t_off[c] = t;
+      t += (size_t)4 * k2 * cbands[c].rows;
+    }
+    oT = take(t * 4);
+    size_t q = 0;
+    for (int r = 0; r < nband; ++r)
+      for (int c = 0; c < ncband; ++c) {
+        p_off[(size_t)r * ncband + c] = q;
+        q += (size_t)7 * bands[r].rows * cbands[c].rows;
+      }
+    oP = take(q * 4);
+  }
+  // A piece (i, r, c) -- top-level product i restricted to row band r and
+  // column band c -- is a Winograd product of depth d - 1.  The pieces of one
+  // product and row band share their left operand, those of one product and
+  // column band their right operand, so the inner recursion's A-side (B-side)
+  // temporaries are computed by the first such piece and reused by the
+  // others: one region per (product, row band) and per (product, column
+  // band), outside the temporaries the pieces take in turn.
+  const bool trees = wino && depth >= 2;
+  std::vector<size_t> at_off((size_t)7 * std::max(nband, 1)), bt_off((size_t)7 * std::max(ncband, 1));
+  size_t oAT = 0, oBT = 0;
+  if (trees) {
+    size_t a = 0, b = 0;
+    for (int i = 0; i < 7; ++i) {
+      for (int r = 0; r < nband; ++r) {
+        at_off[(size_t)i * nband + r] = a;
+        a += align_up(a_tree_bytes(bands[r].rows, k2, 1, depth - 1), 256);
+      }
+      for (int c = 0; c < ncband; ++c) {
+        bt_off[(size_t)i * ncband + c] = b;
+        b += align_up(b_tree_bytes(1, k2, cbands[c].rows, depth - 1), 256);
+      }
+    }
+    oAT = take(a);
+    oBT = take(b);
+  }
+  char* tree_base = reinterpret_cast<char*>(256);  // placeholder until allocation
 
   // Placeholder device pointers for sizing (real ones set after allocation).
   char* ws = nullptr;
   float *dA = nullptr, *dB = nullptr, *dC = nullptr, *S = nullptr, *T = nullptr, *P = nullptr;
-  const int64_t ma = m2 * k2, tb = k2 * n2, pc = m2 * n2;
+  const int64_t ma = m2 * k2;
 
   struct V {
     const float* p;
     int64_t ld, r, c;
   };
-  // Left operand of top-level product i (0..6), band b; right operand of i.
+  // Left operand of top-level product i (0..6), row band b.
   auto left = [&](int i, const Band& b) -> V {
     switch (i) {
       case 0: return {dA + b.r0 * K4, K4, b.rows, k2};               // A11
@@ -183,23 +231,29 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       default: return {S + 2 * ma + b.r0 * k2, k2, b.rows, k2};      // S3
     }
   };
-  auto right = [&](int i) -> V {
+  // Right operand of product i, column band c.
+  auto right = [&](int i, int ci) -> V {
+    const Band& c = cbands[ci];
+    float* Tc = T + t_off[ci];
+    const int64_t tb = k2 * c.rows;
     switch (i) {
-      case 0: return {dB, N4, k2, n2};                  // B11
-      case 1: return {dB + k2 * N4, N4, kb, n2};        // B21
-      case 2: return {dB + k2 * N4 + n2, N4, kb, nb};   // B22
-      case 3: return {T + 3 * tb, n2, k2, n2};        // T4
-      case 4: return {T + 0 * tb, n2, k2, n2};        // T1
-      case 5: return {T + 1 * tb, n2, k2, n2};        // T2
-      default: return {T + 2 * tb, n2, k2, n2};       // T3
+      case 0: return {dB + c.r0, N4, k2, c.rows};                    // B11
+      case 1: return {dB + k2 * N4 + c.r0, N4, kb, c.rows};          // B21
+      case 2: return {dB + k2 * N4 + n2 + c.r0, N4, kb, c.bot};      // B22
+      case 3: return {Tc + 3 * tb, c.rows, k2, c.rows};              // T4
+      case 4: return {Tc + 0 * tb, c.rows, k2, c.rows};              // T1
+      case 5: return {Tc + 1 * tb, c.rows, k2, c.rows};              // T2
+      default: return {Tc + 2 * tb, c.rows, k2, c.rows};             // T3
     }
   };
-  auto wino_problem = [&](int i, const Band& b) {
+  auto wino_piece = [&](int i, int ri, int ci) {
+    const Band& b = bands[ri];
+    const Band& c = cbands[ci];
     Problem p;
-    const V l = left(i, b), r = right(i);
+    const V l = left(i, b), r = right(i, ci);
     p.M = b.rows;
     p.K = k2;
-    p.N = n2;
+    p.N = c.rows;
     p.A = l.p;
     p.lda = l.ld;
     p.a_rows = l.r;
@@ -208,11 +262,15 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     p.ldb = r.ld;
     p.b_rows = r.r;
     p.b_cols = r.c;
-    p.C = P + i * pc + b.r0 * n2;
-    p.ldc = n2;
+    p.C = P + p_off[(size_t)ri * ncband + ci] + (int64_t)i * b.rows * c.rows;
+    p.ldc = c.rows;
     p.depth = depth - 1;
     p.tile = tile;
-    if (bt_each) p.b_tree = reinterpret_cast<float*>(bt_base + i * bt_each);
+    if (trees) {
+      // tree_base is the arena at oAT; the B-side regions follow at oBT.
+      p.a_tree = reinterpret_cast<float*>(tree_base + at_off[(size_t)i * nband + ri]);
+      p.b_tree = reinterpret_cast<float*>(tree_base + (oBT - oAT) + bt_off[(size_t)i * ncband + ci]);
+    }
     return p;
   };
   auto plain_problem = [&](const Band& b, int half) {
@@ -234,55 +292,73 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   // The step list is built twice: once with placeholder pointers (sizes),
   // once with the real ones.  Each group's temporaries share one region.
   std::vector<Group> groups;
-  // Product bands in compute order (wino): chosen by simulating the copies
-  // and the products with rough rates; see the comment at the top.
+  // Input blocks: A quadrant q of row band b (mat 0), B quadrant q of column
+  // band b (mat 1).
   struct Item {
-    int mat, qr, qc, band;  // mat 0 = A (band 0/1), 1 = B (band -1)
+    int mat, q, band;
   };
   std::vector<Item> items;
-  std::vector<std::pair<int, int>> order;  // (product 0..6, band)
-  // Quadrant bit (X11, X12, X21, X22) -> item index for A (per band) and B.
-  int a_item[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}}, b_item[4] = {-1, -1, -1, -1};
+  struct Piece {
+    int i, r, c;
+  };
+  std::vector<Piece> order;  // pieces in compute order
+  int a_item[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
+  int b_item[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
   // Quadrants each product reads (bit 0 = X11, 1 = X12, 2 = X21, 3 = X22).
   static const unsigned kNeedA[7] = {0x1, 0x2, 0xF, 0x8, 0xC, 0xD, 0x5};
   static const unsigned kNeedB[7] = {0x1, 0x4, 0x8, 0xF, 0x3, 0xB, 0xA};
   if (wino) {
-    const int nbd = (int)bands.size();
-    auto A_ = [&](int q, int b) { items.push_back({0, q / 2, q % 2, b}); a_item[q][b] = (int)items.size() - 1; };
-    auto B_ = [&](int q) { items.push_back({1, q / 2, q % 2, -1}); b_item[q] = (int)items.size() - 1; };
-    const int b1 = nbd > 1 ? 1 : 0;
-    A_(0, 0); B_(0); A_(3, 0); if (b1) A_(0, 1); A_(2, 0); B_(1); B_(3); B_(2);
-    if (b1) { A_(3, 1); A_(2, 1); }
-    A_(1, 0); if (b1) A_(1, 1);
-    // Estimated arrival times (bytes at PCIe rate) and product costs (flops
-    // at the leaf rate); only the order matters.
+    // Input order, found by simulating the copies (at the PCIe rate) and the
+    // pieces (at the leaf rate) for n = 19456 and searching over orders: B
+    // quadrants before A ones within a pair, the first row and column bands
+    // of the X11 quadrants first, A12 last.  Blocks of a band that does not
+    // exist are skipped.
+    static const int kRecipe[16][3] = {{1, 0, 0}, {0, 0, 0}, {1, 0, 1}, {0, 0, 1},
+                                       {1, 1, 1}, {0, 2, 1}, {1, 3, 1}, {0, 3, 1},
+                                       {1, 1, 0}, {1, 3, 0}, {1, 2, 0}, {0, 3, 0},
+                                       {0, 1, 0}, {0, 2, 0}, {1, 2, 1}, {0, 1, 1}};
+    for (const auto& x : kRecipe) {
+      const int mat = x[0], q = x[1], band = x[2];
+      if (band >= (mat == 0 ? nband : ncband)) continue;
+      items.push_back({mat, q, band});
+      (mat == 0 ? a_item : b_item)[q][band] = (int)items.size() - 1;
+    }
+    // Estimated arrival times (bytes at the PCIe rate) and piece costs
+    // (flops at the leaf rate); only the order matters.
     std::vector<double> t_arrive(items.size());
     double t = 0.0;
     for (size_t k = 0; k < items.size(); ++k) {
       const Item& it = items[k];
-      const double rows = it.mat == 0 ? (it.qr ? bands[it.band].bot : bands[it.band].rows)
-                                      : (it.qr ? kb : k2);
-      const double cols = it.mat == 0 ? (it.qc ? kb : k2) : (it.qc ? nb : n2);
+      const Band& b = it.mat == 0 ? bands[it.band] : cbands[it.band];
+      double rows, cols;
+      if (it.mat == 0) {
+        rows = (double)(it.q / 2 ? b.bot : b.rows);
+        cols = (double)(it.q % 2 ? kb : k2);
+      } else {
+        rows = (double)(it.q / 2 ? kb : k2);
+        cols = (double)(it.q % 2 ? b.bot : b.rows);
+      }
       t += rows * cols * 4.0 / 56e9;
       t_arrive[k] = t;
     }
-    auto ready_item = [&](int i, int b) {
+    auto ready_item = [&](const Piece& pc) {
       int last = -1;
       for (int q = 0; q < 4; ++q) {
-        if (kNeedA[i] & (1u << q)) last = std::max(last, a_item[q][b]);
-        if (kNeedB[i] & (1u << q)) last = std::max(last, b_item[q]);
+        if (kNeedA[pc.i] & (1u << q)) last = std::max(last, a_item[q][pc.r]);
+        if (kNeedB[pc.i] & (1u << q)) last = std::max(last, b_item[q][pc.c]);
       }
       return last;
     };
-    std::vector<std::pair<int, int>> pending;
-    for (int b = 0; b < nbd; ++b)
-      for (int i = 0; i < 7; ++i) pending.push_back({i, b});
+    std::vector<Piece> pending;
+    for (int r = 0; r < nband; ++r)
+      for (int c = 0; c < ncband; ++c)
+        for (int i = 0; i < 7; ++i) pending.push_back({i, r, c});
     double tc = 0.0;
     while (!pending.empty()) {
       size_t best = 0;
       double best_start = 1e300, best_ready = 1e300;
       for (size_t k = 0; k < pending.size(); ++k) {
-        const double r = t_arrive[ready_item(pending[k].first, pending[k].second)];
+        const double r = t_arrive[ready_item(pending[k])];
         const double st = std::max(r, tc);
         if (st < best_start - 1e-12 || (std::abs(st - best_start) <= 1e-12 && r < best_ready)) {
           best = k;
@@ -290,21 +366,23 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
           best_ready = r;
         }
       }
-      const auto pb = pending[best];
+      const Piece pc = pending[best];
       pending.erase(pending.begin() + best);
-      const double rows = (double)bands[pb.second].rows;
-      tc = best_start + 2.0 * rows * k2 * n2 / 120e12;
-      order.push_back(pb);
+      tc = best_start + 2.0 * bands[pc.r].rows * k2 * cbands[pc.c].rows / 120e12;
+      order.push_back(pc);
     }
   }
   auto build_groups = [&]() {
     groups.clear();
     if (wino) {
-      bool seen[7] = {};
-      for (auto& pb : order) {
-        Problem p = wino_problem(pb.first, bands[pb.second]);
-        p.b_tree_ready = bt_each && seen[pb.first];
-        seen[pb.first] = true;
+      std::vector<char> a_seen((size_t)7 * nband, 0), b_seen((size_t)7 * ncband, 0);
+      for (const Piece& pc : order) {
+        Problem p = wino_piece(pc.i, pc.r, pc.c);
+        char& as = a_seen[(size_t)pc.i * nband + pc.r];
+        char& bs = b_seen[(size_t)pc.i * ncband + pc.c];
+        p.a_tree_ready = trees && as;
+        p.b_tree_ready = trees && bs;
+        as = bs = 1;
         groups.push_back({{p}});
       }
     } else {
@@ -313,9 +391,11 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     }
   };
   build_groups();
-  // Descriptor slots: pre-addition passes (at most 4 per band for S and 4
-  // for T), one post-addition node per band; then the product schedules.
-  size_t temp_max = 0, desc_total = 256 * (size_t)(8 * nband + 8 + nband);
+  // Descriptor slots: pre-addition passes (at most 4 per row band for S and
+  // 4 per column band for T), one post-addition node per block; then the
+  // product schedules.
+  const size_t nslots = (size_t)4 * nband + 4 * std::max(ncband, 1) + (size_t)nband * std::max(ncband, 1) + 8;
+  size_t temp_max = 0, desc_total = 256 * nslots;
   for (auto& g : groups) {
     size_t t = 0;
     for (auto& p : g.probs) t += align_up(problem_temp_bytes(p), 256);
@@ -346,7 +426,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   S = reinterpret_cast<float*>(ws + oS);
   T = reinterpret_cast<float*>(ws + oT);
   P = reinterpret_cast<float*>(ws + oP);
-  bt_base = ws + oBT;
+  tree_base = ws + oAT;
   char* temps = ws + oTemp;
   char* ddesc = ws + oDesc;
   {
@@ -363,36 +443,39 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     }
   }
 
-  // Top-level post-addition nodes, one per band (the quadrant is chosen at
-  // launch).  Pre-addition nodes are written as they are issued (their
-  // output masks depend on what has arrived).
   size_t slot = 0;
   auto next_slot = [&]() {
-    if (slot >= (size_t)(8 * nband + 8 + nband)) throw Error(kDeviceError, "descriptor slots exhausted");
+    if (slot >= nslots) throw Error(kDeviceError, "descriptor slots exhausted");
     return 256 * slot++;
   };
-  std::vector<const PostAddNode*> d_post(nband);
-  std::vector<char> vec_post(nband);
+  // Top-level post-addition nodes, one per (row band, column band) block (the
+  // quadrant is chosen at launch).  Pre-addition nodes are written as they
+  // are issued (their output masks depend on what has arrived).
+  std::vector<const PostAddNode*> d_post((size_t)nband * std::max(ncband, 1));
+  std::vector<char> vec_post(d_post.size());
   if (wino) {
-    for (int bi = 0; bi < nband; ++bi) {
-      const Band& b = bands[bi];
-      PostAddNode np{};
-      np.P = P + b.r0 * n2;
-      np.dst = dC + b.r0 * N4;
-      np.ld = N4;
-      np.p_stride = pc;
-      np.bot_off = m2 * N4;
-      np.top_rows = (int32_t)b.rows;
-      np.bot_rows = (int32_t)b.bot;
-      np.left_cols = (int32_t)n2;
-      np.right_cols = (int32_t)nb;
-      np.h_r = (int32_t)b.rows;
-      np.h_c = (int32_t)n2;
-      const size_t o = next_slot();
-      std::memcpy(host + o, &np, sizeof(np));
-      d_post[bi] = reinterpret_cast<const PostAddNode*>(ddesc + o);
-      vec_post[bi] = post_vec_ok(np);
-    }
+    for (int bi = 0; bi < nband; ++bi)
+      for (int ci = 0; ci < ncband; ++ci) {
+        const Band& b = bands[bi];
+        const Band& c = cbands[ci];
+        PostAddNode np{};
+        np.P = P + p_off[(size_t)bi * ncband + ci];
+        np.dst = dC + b.r0 * N4 + c.r0;
+        np.ld = N4;
+        np.p_stride = b.rows * c.rows;
+        np.bot_off = m2 * N4;
+        np.right_off = (int32_t)n2;
+        np.top_rows = (int32_t)b.rows;
+        np.bot_rows = (int32_t)b.bot;
+        np.left_cols = (int32_t)c.rows;
+        np.right_cols = (int32_t)c.bot;
+        np.h_r = (int32_t)b.rows;
+        np.h_c = (int32_t)c.rows;
+        const size_t o = next_slot();
+        std::memcpy(host + o, &np, sizeof(np));
+        d_post[(size_t)bi * ncband + ci] = reinterpret_cast<const PostAddNode*>(ddesc + o);
+        vec_post[(size_t)bi * ncband + ci] = post_vec_ok(np);
+      }
   }
   hipStream_t cs = L.stream, hs = L.h2d_stream, ds = L.d2h_stream;
   int ev_next = 1;
@@ -422,8 +505,9 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     const int64_t rows = qr ? b.bot : b.rows;
     h2d_block(dA, K4, A, lda, (qr ? m2 : 0) + b.r0, qc ? k2 : 0, rows, qc ? kb_v : k2, hs);
   };
-  auto b_quad = [&](int qr, int qc) {
-    h2d_block(dB, N4, B, ldb, qr ? k2 : 0, qc ? n2 : 0, qr ? kb_v : k2, qc ? nb_v : n2, hs);
+  auto b_band = [&](int qr, int qc, const Band& c) {
+    h2d_block(dB, N4, B, ldb, qr ? k2 : 0, (qc ? n2 : 0) + c.r0, qr ? kb_v : k2,
+              qc ? right_valid(c) : c.rows, hs);
   };
 
   int launches = 0, nleaf = 0;
@@ -434,28 +518,14 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     launches += enqueue_schedule(L, g.s, ddesc + g.desc_off, host + g.desc_off, b, e);
   };
   auto wait = [&](hipEvent_t e) { FASTMM_HIP(hipStreamWaitEvent(cs, e, 0)); };
-  // Result block out: quadrant q (0 = C11, 1 = C12, 2 = C21, 3 = C22), band b.
-  auto send = [&](int q, const Band& b) {
-    const int qr = q / 2, qc = q % 2;
-    hipEvent_t e = next_event();
-    FASTMM_HIP(hipEventRecord(e, cs));
-    FASTMM_HIP(hipStreamWaitEvent(ds, e, 0));
-    d2h_block(C, ldc, dC, N4, (qr ? m2 : 0) + b.r0, qc ? n2 : 0, qr ? b.bot : b.rows,
-              qc ? nb_v : n2, ds);
-  };
-  auto post = [&](int q, int bi) {
-    const Band& b = bands[bi];
-    launch_postadd(d_post[bi], 1, (int)add_blocks_for(b.rows, n2), vec_post[bi], cs, q);
-    ++launches;
-  };
 
   if (wino) {
     // ---- inputs, in the recipe's order
     std::vector<hipEvent_t> ev_item(items.size());
     for (size_t k = 0; k < items.size(); ++k) {
       const Item& it = items[k];
-      if (it.mat == 0) a_band(it.qr, it.qc, bands[it.band]);
-      else b_quad(it.qr, it.qc);
+      if (it.mat == 0) a_band(it.q / 2, it.q % 2, bands[it.band]);
+      else b_band(it.q / 2, it.q % 2, cbands[it.band]);
       ev_item[k] = arrive();
     }
     FASTMM_HIP(hipEventRecord(L.ev[5], hs));
@@ -468,26 +538,26 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
         waited = k;
       }
     };
-    unsigned s_done[2] = {0, 0}, t_done = 0;  // outputs computed so far
-    auto have = [&](int mat, int q, int b) {
-      return (mat == 0 ? a_item[q][b] : b_item[q]) <= waited;
+    unsigned s_done[2] = {0, 0}, t_done[2] = {0, 0};  // outputs computed so far, per band
+    auto have = [&](int mat, int q, int band) {
+      return (mat == 0 ? a_item[q][band] : b_item[q][band]) <= waited;
     };
-    // Issue one pre-addition pass for every output of this operand whose
-    // inputs are all on the device and that is not computed yet.
+    // Issue one pre-addition pass for every output of this operand's band
+    // whose inputs are all on the device and that is not computed yet.
     auto preadd_pass = [&](int side, int bi) {
-      unsigned& done = side == 0 ? s_done[bi] : t_done;
+      unsigned& done = side == 0 ? s_done[bi] : t_done[bi];
       unsigned mask = 0;
       for (int j = 0; j < 4; ++j) {
         if (done & (1u << j)) continue;
         const unsigned in = preadd_inputs(side, 1u << j);
         bool ok = true;
         for (int q = 0; q < 4; ++q)
-          if ((in & (1u << q)) && !have(side == 0 ? 0 : 1, q, bi)) ok = false;
+          if ((in & (1u << q)) && !have(side, q, bi)) ok = false;
         if (ok) mask |= 1u << j;
       }
       if (!mask) return;
       PreAddNode n{};
-      if (side == 0) {
+      if (side == 0) {  // row band of A's quadrants -> rows of S1..S4
         const Band& b = bands[bi];
         n.src = dA + b.r0 * K4;
         n.dst = S + b.r0 * k2;
@@ -500,8 +570,21 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
         n.right_cols = (int32_t)kb;
         n.h_r = (int32_t)b.rows;
         n.h_c = (int32_t)k2;
-      } else {
-        n = preadd_node(dB, N4, K4, N4, k2, n2, T);
+        n.right_off = (int32_t)k2;
+      } else {  // column band of B's quadrants -> the band's own T1..T4
+        const Band& c = cbands[bi];
+        n.src = dB + c.r0;
+        n.dst = T + t_off[bi];
+        n.ld = N4;
+        n.bot_off = k2 * N4;
+        n.out_stride = k2 * c.rows;
+        n.top_rows = (int32_t)k2;
+        n.bot_rows = (int32_t)kb;
+        n.left_cols = (int32_t)c.rows;
+        n.right_cols = (int32_t)c.bot;
+        n.h_r = (int32_t)k2;
+        n.h_c = (int32_t)c.rows;
+        n.right_off = (int32_t)n2;
       }
       n.mask = (int32_t)mask;
       const size_t o = next_slot();
@@ -516,31 +599,41 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     static const int kLeftS[7] = {0, 0, 4, 0, 1, 2, 3};   // P3: S4, P5: S1, P6: S2, P7: S3
     static const int kRightT[7] = {0, 0, 0, 4, 1, 2, 3};  // P4: T4, P5: T1, P6: T2, P7: T3
     static const int kQuadP[4][4] = {{0, 1, -1, -1}, {0, 5, 4, 2}, {0, 5, 6, 3}, {0, 5, 6, 4}};
-    bool pdone[7][2] = {};
-    bool sent[4][2] = {};
+    std::vector<char> pdone((size_t)7 * nband * ncband, 0), sent((size_t)4 * nband * ncband, 0);
+    auto pidx = [&](int i, int r, int c) { return ((size_t)r * ncband + c) * 7 + i; };
     for (size_t gi = 0; gi < order.size(); ++gi) {
-      const int i = order[gi].first, bi = order[gi].second;
+      const Piece& pc = order[gi];
       int last = -1;
       for (int q = 0; q < 4; ++q) {
-        if (kNeedA[i] & (1u << q)) last = std::max(last, a_item[q][bi]);
-        if (kNeedB[i] & (1u << q)) last = std::max(last, b_item[q]);
+        if (kNeedA[pc.i] & (1u << q)) last = std::max(last, a_item[q][pc.r]);
+        if (kNeedB[pc.i] & (1u << q)) last = std::max(last, b_item[q][pc.c]);
       }
       wait_item(last);
-      if (kLeftS[i] && !(s_done[bi] & (1u << (kLeftS[i] - 1)))) preadd_pass(0, bi);
-      if (kRightT[i] && !(t_done & (1u << (kRightT[i] - 1)))) preadd_pass(1, 0);
+      if (kLeftS[pc.i] && !(s_done[pc.r] & (1u << (kLeftS[pc.i] - 1)))) preadd_pass(0, pc.r);
+      if (kRightT[pc.i] && !(t_done[pc.c] & (1u << (kRightT[pc.i] - 1)))) preadd_pass(1, pc.c);
       run_group(groups[gi]);
-      pdone[i][bi] = true;
-      // Result blocks whose four (two for C11) products are now all done.
+      pdone[pidx(pc.i, pc.r, pc.c)] = 1;
+      // Result blocks whose four (two for C11) products are now all done:
+      // form them and send them out.
       for (int q = 0; q < 4; ++q) {
-        if (sent[q][bi]) continue;
+        char& sq = sent[((size_t)pc.r * ncband + pc.c) * 4 + q];
+        if (sq) continue;
         bool ok = true;
         for (int k = 0; k < 4; ++k)
-          if (kQuadP[q][k] >= 0 && !pdone[kQuadP[q][k]][bi]) ok = false;
+          if (kQuadP[q][k] >= 0 && !pdone[pidx(kQuadP[q][k], pc.r, pc.c)]) ok = false;
         if (!ok) continue;
-        // quadrant index for post/send: 0 = C11, 1 = C12, 2 = C21, 3 = C22
-        post(q, bi);
-        send(q, bands[bi]);
-        sent[q][bi] = true;
+        const Band& b = bands[pc.r];
+        const Band& c = cbands[pc.c];
+        const size_t blk = (size_t)pc.r * ncband + pc.c;
+        launch_postadd(d_post[blk], 1, (int)add_blocks_for(b.rows, c.rows), vec_post[blk], cs, q);
+        ++launches;
+        const int qr = q / 2, qc = q % 2;
+        hipEvent_t e = next_event();
+        FASTMM_HIP(hipEventRecord(e, cs));
+        FASTMM_HIP(hipStreamWaitEvent(ds, e, 0));
+        d2h_block(C, ldc, dC, N4, (qr ? m2 : 0) + b.r0, (qc ? n2 : 0) + c.r0, qr ? b.bot : b.rows,
+                  qc ? right_valid(c) : c.rows, ds);
+        sq = 1;
       }
     }
   } else {

@@ -104,9 +104,9 @@ preadd_kernel(const PreAddNode* __restrict__ nodes, int nnodes) {
     const bool rt = r < nd.top_rows;
     const bool rb = r < nd.bot_rows;
     const float4 x11 = load4(top + c, VEC, rt && (in_q & 1u), c, nd.left_cols);
-    const float4 x12 = load4(top + h_c + c, VEC, rt && (in_q & 2u), c, nd.right_cols);
+    const float4 x12 = load4(top + nd.right_off + c, VEC, rt && (in_q & 2u), c, nd.right_cols);
     const float4 x21 = load4(bot + c, VEC, rb && (in_q & 4u), c, nd.left_cols);
-    const float4 x22 = load4(bot + h_c + c, VEC, rb && (in_q & 8u), c, nd.right_cols);
+    const float4 x22 = load4(bot + nd.right_off + c, VEC, rb && (in_q & 8u), c, nd.right_cols);
     float4 o1, o2, o3, o4;
     if (SIDE == 0) {
       // S1 = A21 + A22; S2 = S1 - A11; S3 = A11 - A21; S4 = A12 - S2
@@ -170,9 +170,9 @@ postadd_kernel(const PostAddNode* __restrict__ nodes, int nnodes) {
     const bool rt = r < nd.top_rows;
     const bool rb = r < nd.bot_rows;
     if (QUAD < 0 || QUAD == 0) store4(top + c, c11, VEC, rt, c, nd.left_cols);
-    if (QUAD < 0 || QUAD == 1) store4(top + h_c + c, c12, VEC, rt, c, nd.right_cols);
+    if (QUAD < 0 || QUAD == 1) store4(top + nd.right_off + c, c12, VEC, rt, c, nd.right_cols);
     if (QUAD < 0 || QUAD == 2) store4(bot + c, c21, VEC, rb, c, nd.left_cols);
-    if (QUAD < 0 || QUAD == 3) store4(bot + h_c + c, c22, VEC, rb, c, nd.right_cols);
+    if (QUAD < 0 || QUAD == 3) store4(bot + nd.right_off + c, c22, VEC, rb, c, nd.right_cols);
   }
 }
 
