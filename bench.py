@@ -40,11 +40,12 @@ PEAK_HBM_GBS = 8000.0
 # each scaled by its reading for a 1 GiB calibration copy (fetch x2.000,
 # write x1.000).  HBM-resident depth-3 call: one grouped launch of 343 leaves
 # of 2432 x 2432 x 2432 (profiles/leaf_gemm_n19456_d3_device_hbm_traffic.md).
-# Pinned-host depth-3 call: None until the counters are taken for the
-# current pipelined schedule.  Valid for leaf_gemm_kernel<128,128,16,2,2> in
-# those configurations only.
+# Pinned-host depth-3 call: 28 launches of 49 leaves of (1280 | 1152) x 2432
+# x (1280 | 1152), mean per launch
+# (profiles/leaf_gemm_n19456_d3_pinned_hbm_traffic.md).  Valid for
+# leaf_gemm_kernel<128,128,16,2,2> in those configurations only.
 TRAFFIC_DEVICE_BYTES_PER_LAUNCH = 37642619.6 * 1024 * 2.000 + 7924672.0 * 1024 * 1.000
-TRAFFIC_PINNED_BYTES_PER_LAUNCH = None
+TRAFFIC_PINNED_BYTES_PER_LAUNCH = 1485667.6 * 1024 * 2.000 + 288748.7 * 1024 * 1.000
 
 
 def cpu_model():
