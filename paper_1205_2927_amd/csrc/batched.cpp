@@ -64,6 +64,7 @@ std::string signature(const Schedule& s) {
     o << "t" << t.kind << ',' << t.level << ',' << t.levels << ',' << t.width << ',' << t.clip << ','
       << (const void*)t.d_nodes << ','
       << t.nodes.size() << ',' << t.blocks << ';';
+  o << "f" << (int)s.fused_post << ';';
   for (int fmt = 0; fmt < 2; ++fmt)
     for (int side = 0; side < 2; ++side)
       o << "k" << fmt << side << (const void*)s.d_pack[fmt][side] << ',' << s.pack[fmt][side].size()

@@ -40,6 +40,18 @@ struct GemmDesc {
   void* pb;
   int32_t* ea;
   int32_t* eb;
+  // Last-level post-additions fused into the epilogue (FP32 leaves, 128x128
+  // tiles, FASTMM_FUSED_POST=1; else e_mask = 0): the leaf is product P_i of
+  // a node whose result (E, leading dimension e_ld; C21 / C22 at e_bot_off,
+  // C12 / C22 at e_right_off from C11 / C21) it writes into directly.  Bit
+  // q of e_mask (C11, C12, C21, C22) marks the quadrants this product enters:
+  // stored where e_first has the bit, subtracted where e_sub has it, else
+  // added.  Valid rows of the top / bottom quadrants e_rows[0 / 1], valid
+  // columns of the left / right ones e_cols[0 / 1].
+  float* E;
+  int64_t e_ld, e_bot_off;
+  int32_t e_right_off, e_mask, e_first, e_sub;
+  int32_t e_rows[2], e_cols[2];
 };
 
 // One node of a pre-addition launch: reads the four quadrants of a parent
@@ -292,7 +304,8 @@ __device__ __forceinline__ int leaf_tile_of_block(int bid, int nblocks, int chun
 // persistent launch (workgroups take tiles from a counter; the kernel leaves
 // the counters zeroed), or nullptr for one workgroup per tile.
 void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
-                      hipStream_t stream, int xcd_chunk = 0, int* queue = nullptr);
+                      hipStream_t stream, int xcd_chunk = 0, int* queue = nullptr,
+                      bool fused_post = false);
 void launch_leaf_bf16x3(const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
                         hipStream_t stream, int xcd_chunk = 0);
 // Split-precision leaves on packed operands (tile kTileBf16x3 or

@@ -239,8 +239,25 @@ size_t problem_temp_bytes(const Problem& p) {
   return floats * sizeof(float);
 }
 
+// Order in which the seven products of a node enter its result when the
+// last level's post-additions are fused into the leaves: every quadrant's
+// chain (C11 = P1 + P2; C12 = ((P1 + P6) + P5) + P3; C21 = ((P1 + P6) + P7)
+// - P4; C22 = ((P1 + P6) + P7) + P5) then takes its operands in the
+// post-addition kernel's order, so the result is bit for bit the same.
+// Per product (P1..P7): quadrants entered (bit 0 C11, 1 C12, 2 C21, 3 C22),
+// stored (first operand of the chain), subtracted.
+constexpr int kFusedPostOrder[7] = {0, 5, 6, 4, 1, 2, 3};
+constexpr int kFusedMask[7] = {0xF, 0x1, 0x2, 0x4, 0xA, 0xE, 0xC};
+constexpr int kFusedFirst[7] = {0xF, 0, 0, 0, 0, 0, 0};
+constexpr int kFusedSub[7] = {0, 0, 0, 0x4, 0, 0, 0};
+
 void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
   s = Schedule();
+  {
+    const char* fp = std::getenv("FASTMM_FUSED_POST");
+    s.fused_post = fp && fp[0] == '1' && probs.size() == 1 && probs[0].depth >= 1 &&
+                   probs[0].tile == kTile128x128;
+  }
   // Split-BF16 leaves take the last level's pre-additions and the pack pass
   // in one fused pass (FASTMM_FUSED_PACK=0: the two passes, for comparison).
   const char* fe = std::getenv("FASTMM_FUSED_PACK");
@@ -427,9 +444,11 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     };
     if (!p.a_tree_ready) pre_side(0, lvA, Sb, byA, s.preA);
     if (!p.b_tree_ready) pre_side(1, lvB, Tb, byB, s.preB);
-    // Product buffers P[l] (l = 1..d), 7^l blocks of m_l x n_l.
+    // Product buffers P[l] (l = 1..d), 7^l blocks of m_l x n_l (the leaves'
+    // own, P[d], not when they write into their nodes' results).
     std::vector<float*> P(d + 1, nullptr);
-    for (int l = 1; l <= d; ++l) P[l] = carve((size_t)pow7(l) * dims[l].m * dims[l].n);
+    for (int l = 1; l <= d; ++l)
+      if (!(s.fused_post && l == d)) P[l] = carve((size_t)pow7(l) * dims[l].m * dims[l].n);
     // Leaves.
     const Dims lf = dims[d];
     const int64_t nleaves = pow7(d);
@@ -464,6 +483,28 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
         g.ldc = p.ldc;
         g.c_rows = (int32_t)p.cr();
         g.c_cols = (int32_t)p.cc();
+      } else if (s.fused_post) {
+        // Product i of node x / 7 of the last level, straight into the
+        // node's result (the root's C, clipped, or a level d-1 product).
+        const int i = (int)(x % 7);
+        const int64_t nd = x / 7;
+        const bool root = d == 1;
+        const int64_t rows = root ? p.cr() : dims[d - 1].m, cols = root ? p.cc() : dims[d - 1].n;
+        g.E = root ? p.C : P[d - 1] + nd * dims[d - 1].m * dims[d - 1].n;
+        g.e_ld = root ? p.ldc : dims[d - 1].n;
+        g.e_bot_off = lf.m * g.e_ld;
+        g.e_right_off = (int32_t)lf.n;
+        g.e_rows[0] = clamp_extent(rows, lf.m);
+        g.e_rows[1] = clamp_extent(rows - lf.m, lf.m);
+        g.e_cols[0] = clamp_extent(cols, lf.n);
+        g.e_cols[1] = clamp_extent(cols - lf.n, lf.n);
+        g.e_mask = kFusedMask[i];
+        g.e_first = kFusedFirst[i];
+        g.e_sub = kFusedSub[i];
+        g.C = g.E;
+        g.ldc = g.e_ld;
+        g.c_rows = (int32_t)lf.m;
+        g.c_cols = (int32_t)lf.n;
       } else {
         g.C = P[d] + x * lf.m * lf.n;
         g.ldc = lf.n;
@@ -520,9 +561,17 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     // A clipped C (the root's product) keeps the root's level to itself.
     const bool c_clipped = d > 0 && (lvP[0][0].top_rows + lvP[0][0].bot_rows < 2 * lvP[0][0].h_r ||
                                      lvP[0][0].left_cols + lvP[0][0].right_cols < 2 * lvP[0][0].h_c);
-    const std::vector<int> gp = group_levels(d, [&](int l, int L) {
+    // With the last level fused into the leaves, the launches cover levels
+    // 0 .. d-2 only.
+    const int post_top = s.fused_post ? d - 1 : d;
+    std::vector<int> gp = group_levels(post_top, [&](int l, int L) {
       return exact(l, l + L, 2) && !(l == 0 && c_clipped);
     });
+    if (s.fused_post) {
+      gp[d - 1] = 0;
+      const Dims c = dims[d];
+      s.add_bytes += (double)pow7(d - 1) * 96.0 * c.m * c.n;  // 24 reads or writes per node
+    }
     for (int l = d - 1; l >= 0; --l) {
       const Dims c = dims[l + 1];
       if (gp[l] == 1) {
@@ -609,13 +658,31 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
     // round-robin runs, so that no XCD is left with the long tail.
     auto& lv = s.leaf[t];
     s.xcd_chunk[t] = 0;
-    for (auto& g : lv)
-      if (g.kmax != lv[0].kmax) s.xcd_chunk[t] = 8;
+    const bool phased = s.fused_post && t == kTile128x128;
+    if (!phased)
+      for (auto& g : lv)
+        if (g.kmax != lv[0].kmax) s.xcd_chunk[t] = 8;
     if (s.xcd_chunk[t])
       std::stable_sort(lv.begin(), lv.end(),
                        [](const GemmDesc& a, const GemmDesc& b) { return a.kmax > b.kmax; });
+    if (phased) {  // leaf x is product x % 7 of its node: group by launch
+      std::vector<GemmDesc> by[7];
+      for (size_t x = 0; x < lv.size(); ++x) by[x % 7].push_back(lv[x]);
+      lv.clear();
+      for (int j = 0; j < 7; ++j) {
+        s.phase_begin[j] = (int)lv.size();
+        lv.insert(lv.end(), by[kFusedPostOrder[j]].begin(), by[kFusedPostOrder[j]].end());
+      }
+      s.phase_begin[7] = (int)lv.size();
+    }
     int64_t total = 0;
-    for (auto& g : s.leaf[t]) {
+    int phase = 0;
+    for (size_t x = 0; x < s.leaf[t].size(); ++x) {
+      GemmDesc& g = s.leaf[t][x];
+      if (phased) {
+        while (phase < 7 && (int)x >= s.phase_begin[phase + 1]) ++phase;
+        if ((int)x == s.phase_begin[phase]) total = 0;  // numbering restarts per launch
+      }
       g.tile_begin = (int32_t)total;
       total += (int64_t)((g.c_rows + ts.bm - 1) / ts.bm) * g.tiles_n;
       // 16-byte loads need aligned rows and float4 groups that are either
@@ -625,9 +692,16 @@ void build_schedule(const std::vector<Problem>& probs, char* ws, Schedule& s) {
         s.vec_leaf[t] = false;
       if (g.lda > kMaxLeadingDimA || g.ldb > kMaxLeadingDimB)
         throw Error(kNotSupported, "leading dimension too large for the leaf kernel");
+      if (total > INT32_MAX) throw Error(kNotSupported, "leaf launch too large");
+      if (phased) s.phase_tiles[phase] = (int)total;
     }
-    if (total > INT32_MAX) throw Error(kNotSupported, "leaf launch too large");
     s.leaf_tiles_total[t] = (int)total;
+    if (phased) {
+      int64_t all = 0;
+      for (int j = 0; j < 7; ++j) all += s.phase_tiles[j];
+      if (all > INT32_MAX) throw Error(kNotSupported, "leaf launch too large");
+      s.leaf_tiles_total[t] = (int)all;
+    }
   }
 }
 
@@ -742,6 +816,14 @@ int launch_schedule(Library& L, Schedule& s, hipEvent_t leaf_begin, hipEvent_t l
                          L.stream, s.xcd_chunk[t], ext);
       // scale passes (FP16), the pack pass unless every operand is prepacked, the leaf
       launches += (t == kTileFp16x3 ? 2 : 0) + (ext.any_unpacked ? 1 : 0) + 1;
+    } else if (s.fused_post && t == kTile128x128) {
+      for (int j = 0; j < 7; ++j) {
+        const int n = s.phase_begin[j + 1] - s.phase_begin[j];
+        if (n <= 0) continue;
+        launch_leaf_gemm(t, s.d_leaf[t] + s.phase_begin[j], n, s.phase_tiles[j], s.vec_leaf[t], L.stream,
+                         0, nullptr, true);
+        ++launches;
+      }
     } else {
       launch_leaf_gemm(t, s.d_leaf[t], (int)s.leaf[t].size(), s.leaf_tiles_total[t], s.vec_leaf[t],
                        L.stream, s.xcd_chunk[t], s.persistent ? L.leaf_queue : nullptr);

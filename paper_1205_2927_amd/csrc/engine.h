@@ -125,6 +125,14 @@ struct Schedule {
   };
   std::vector<TreeLaunch> trees;
   bool vec_leaf[kNumTiles] = {};  // set in build_schedule
+  // Last-level post-additions fused into the leaf epilogue
+  // (FASTMM_FUSED_POST=1, one problem of depth >= 1, 128x128 tiles): its
+  // leaves run in seven launches, launch j holding product kFusedPostOrder[j]
+  // of every last-level node (s.leaf[kTile128x128][phase_begin[j] ..
+  // phase_begin[j + 1]), tile numbers restarting at 0, phase_tiles[j] tiles).
+  bool fused_post = false;
+  int phase_begin[8] = {};
+  int phase_tiles[7] = {};
   int xcd_chunk[kNumTiles] = {};  // leaf launch tile -> XCD mapping (leaf_tile_of_block)
   bool persistent = false;        // leaf launches take tiles from L.leaf_queue
   int max_depth = 0;

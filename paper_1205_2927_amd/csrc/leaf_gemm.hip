@@ -55,7 +55,7 @@ constexpr int leaf_waves_per_simd() {
   return VEC && (BM / WGM / 32) * (BN / WGN / 32) <= 4 ? 4 : 1;
 }
 
-template <int BM, int BN, int BK, int WGM, int WGN, bool VEC, bool PERSIST>
+template <int BM, int BN, int BK, int WGM, int WGN, bool VEC, bool PERSIST, bool EPI = false>
 __global__ void __launch_bounds__(64 * WGM * WGN, (leaf_waves_per_simd<BM, BN, WGM, WGN, VEC>()))
 leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles, int xcd_chunk,
                  int* __restrict__ queue) {
@@ -330,6 +330,35 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
 
   // Epilogue: register r of block (i, j) holds row 8*(r/4) + 4*(lane/32) + r%4
   // and column lane%32 of that 32x32 block.
+  if constexpr (EPI) {
+    // Fused post-additions: this product's element enters up to three
+    // quadrants of its node's result, each by the next operation of that
+    // quadrant's chain (the launches run the node's products in an order
+    // that makes every chain the post-addition kernel's).
+    const int emask = d.e_mask, efirst = d.e_first, esub = d.e_sub;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!((emask >> q) & 1)) continue;
+      float* __restrict__ Eq = d.E + ((q >> 1) ? d.e_bot_off : 0) + ((q & 1) ? d.e_right_off : 0);
+      const int vr = d.e_rows[q >> 1], vc = d.e_cols[q & 1];
+      const bool first = (efirst >> q) & 1, neg = (esub >> q) & 1;
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int col = tn + wn + 32 * j + lr;
+          if (col >= vc) continue;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) {
+            const int row = tm + wm + 32 * i + 8 * (r >> 2) + 4 * lh + (r & 3);
+            if (row < vr) {
+              float* cp = Eq + (int64_t)row * d.e_ld + col;
+              *cp = first ? acc[i][j][r] : (neg ? *cp - acc[i][j][r] : *cp + acc[i][j][r]);
+            }
+          }
+        }
+    }
+  } else {
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -345,6 +374,7 @@ leaf_gemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int total_tiles,
         }
       }
     }
+  }
   if (!PERSIST) break;
   }
   if (PERSIST && threadIdx.x == 0) {
@@ -391,7 +421,20 @@ static void launch_t(const GemmDesc* d, int ndesc, int total, bool vec, hipStrea
 }
 
 void launch_leaf_gemm(int tile, const GemmDesc* d_descs, int ndesc, int total_tiles, bool vec,
-                      hipStream_t stream, int xcd_chunk, int* queue) {
+                      hipStream_t stream, int xcd_chunk, int* queue, bool fused_post) {
+  if (fused_post) {  // 128x128 tiles, one workgroup per tile
+    if (tile != kTile128x128 || queue) throw Error(kNotSupported, "fused post-additions need 128x128 tiles");
+    if (total_tiles <= 0) return;
+    dim3 grid(total_tiles), block(256);
+    if (vec)
+      hipLaunchKernelGGL((leaf_gemm_kernel<128, 128, 16, 2, 2, true, false, true>), grid, block, 0, stream,
+                         d_descs, ndesc, total_tiles, xcd_chunk, nullptr);
+    else
+      hipLaunchKernelGGL((leaf_gemm_kernel<128, 128, 16, 2, 2, false, false, true>), grid, block, 0,
+                         stream, d_descs, ndesc, total_tiles, xcd_chunk, nullptr);
+    FASTMM_HIP(hipGetLastError());
+    return;
+  }
   switch (tile) {
     case kTile128x128: launch_t<128, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
     case kTile256x128: launch_t<256, 128, 16, 2, 2>(d_descs, ndesc, total_tiles, vec, stream, xcd_chunk, queue); break;
