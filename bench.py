@@ -166,6 +166,34 @@ def batched_context(fastmm, torch, with_planner=True):
     return out
 
 
+def hbm_probe(torch):
+    """Practical HBM ceilings on this device, from the vendor's own kernels
+    (torch's copy, fill, sum and add on 1 GiB float32 buffers), each the
+    best of 10 launches timed with events on torch's stream: the roofs the
+    addition kernels (streams of reads and writes) are compared with."""
+    n = 1 << 28
+    a = torch.ones(n, device="cuda")
+    b = torch.ones(n, device="cuda")
+    c = torch.empty(n, device="cuda")
+    cases = {"copy (1 read + 1 write)": (lambda: c.copy_(a), 8.0 * n),
+             "fill (1 write)": (lambda: c.fill_(1.0), 4.0 * n),
+             "sum (1 read)": (lambda: a.sum(), 4.0 * n),
+             "add (2 reads + 1 write)": (lambda: torch.add(a, b, out=c), 12.0 * n)}
+    for name, (fn, nbytes) in cases.items():
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        print(json.dumps({"hbm_probe": name, "ms": best, "GBps": nbytes / (best * 1e-3) / 1e9,
+                          "frac_of_peak": nbytes / (best * 1e-3) / 1e9 / PEAK_HBM_GBS}), flush=True)
+
+
 def sweep(fastmm, torch, sizes):
     """Dense n-sweep, device-resident, one JSON line per n: the plain MFMA
     SGEMM, Winograd at the planner's default depth, and the paper's classic
@@ -253,6 +281,9 @@ def main():
     ap.add_argument("--precision-config", action="store_true",
                     help="instead of the headline: the precision forms at n = 8192 and 16384, "
                          "depth 2, uniform and log-uniform inputs, one JSON line each")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="instead of the headline: practical HBM ceilings (torch copy, fill, sum, add "
+                         "on 1 GiB), one JSON line each")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline: n-sweep of plain, Winograd and the classic "
                          "recursion, one JSON line per n")
@@ -269,6 +300,9 @@ def main():
     from paper_1205_2927_amd import fastmm
 
     fastmm.load()
+    if args.hbm_probe:
+        hbm_probe(torch)
+        return
     if args.precision_config:
         precision_config(fastmm, torch)
         return

@@ -9,8 +9,9 @@
 // Here the top level of the recursion runs as a sequence of steps on a
 // compute stream while one copy stream brings operand blocks in and a second
 // copy stream sends result blocks back as soon as they are final.  The top
-// quadrants are cut into two row bands (A side) and two column bands (B
-// side): piece (i, r, c) of top-level product i, P_i[r, c] = L_i[r] R_i[:, c],
+// quadrants are cut into two row bands (A side) and, where B's quadrants are
+// at least 4096 wide, two column bands (B side): piece (i, r, c) of
+// top-level product i, P_i[r, c] = L_i[r] R_i[:, c],
 // needs only row band r of its left operand and column band c of its right
 // operand, and is itself a Winograd product of depth d - 1.  The pieces of
 // one product and row band (column band) share the inner recursion's
@@ -34,6 +35,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <functional>
 #include <vector>
@@ -149,7 +151,12 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   std::vector<Band> bands, cbands;
   if (wino) {
     bands = make_bands(m2, mb, 2, (int64_t)ts.bm << (depth - 1));
-    cbands = make_bands(n2, nb, 2, (int64_t)ts.bn << (depth - 1));
+    // Column bands only where B's quadrants are wide: for narrow ones (one
+    // GPU's column panel of a sharded product, 19456 x 19456 x 2432) they
+    // bring no earlier start worth the smaller leaf launches (33.9 against
+    // 38.4 ms for that panel, 25.1 against 28.9 ms for a 9728 x 19456 x
+    // 4864 block).
+    cbands = make_bands(n2, nb, n2 >= 4096 ? 2 : 1, (int64_t)ts.bn << (depth - 1));
   } else {
     // Quarters of M, rounded to whole tiles when M allows (at most 6 bands).
     int64_t q = (M + 3) / 4;
@@ -317,7 +324,18 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
                                        {1, 1, 1}, {0, 2, 1}, {1, 3, 1}, {0, 3, 1},
                                        {1, 1, 0}, {1, 3, 0}, {1, 2, 0}, {0, 3, 0},
                                        {0, 1, 0}, {0, 2, 0}, {1, 2, 1}, {0, 1, 1}};
-    for (const auto& x : kRecipe) {
+    // With whole B quadrants (one column band) the same search gave:
+    // A11[r0] B11 A22[r0] A11[r1] A21[r0] B12 B22 B21 A22[r1] A21[r1]
+    // A12[r0] A12[r1].
+    static const int kRecipeB1[12][3] = {{0, 0, 0}, {1, 0, 0}, {0, 3, 0}, {0, 0, 1},
+                                         {0, 2, 0}, {1, 1, 0}, {1, 3, 0}, {1, 2, 0},
+                                         {0, 3, 1}, {0, 2, 1}, {0, 1, 0}, {0, 1, 1}};
+    std::vector<std::array<int, 3>> recipe;
+    if (ncband > 1)
+      for (const auto& x : kRecipe) recipe.push_back({x[0], x[1], x[2]});
+    else
+      for (const auto& x : kRecipeB1) recipe.push_back({x[0], x[1], x[2]});
+    for (const auto& x : recipe) {
       const int mat = x[0], q = x[1], band = x[2];
       if (band >= (mat == 0 ? nband : ncband)) continue;
       items.push_back({mat, q, band});
