@@ -230,10 +230,33 @@ def test_split_depth_first_fallback_bitwise(fastmm, monkeypatch, tile):
     assert done >= 1
 
 
+def _engine_split(x, d):
+    # The library's split of an extent x with d levels left (the leaf extent
+    # ceil(x / 2^d), rounded up to a multiple of 4 from 64 on and of 2 from 32
+    # on below the top, times 2^(d-1)), restated from its documentation.
+    leaf = -(-x // 2 ** d)
+    g = 4 if leaf >= 64 else (2 if d >= 2 and leaf >= 32 else 1)
+    return (-(-leaf // g) * g) << (d - 1)
+
+
+def _splits_follow_eq1(x, depth):
+    # True when every level of the library's recursion splits x where
+    # equation (1) does (at ceil(x / 2)), so that the oracle's emulation and
+    # the library take the same quadrants.
+    for d in range(depth, 0, -1):
+        h = (x + 1) // 2
+        if _engine_split(x, d) != h:
+            return False
+        x = h
+    return True
+
+
+EMU_SHAPES = [(512, 512, 512, 0), (768, 768, 768, 1), (512, 512, 512, 2), (640, 896, 384, 1)]
+
+
 @pytest.mark.parametrize("tile", [BF, FP])
 @pytest.mark.parametrize("dist", ["uniform", "loguniform"])
-@pytest.mark.parametrize("m,k,n,depth", [(512, 512, 512, 0), (768, 768, 768, 1), (512, 512, 512, 2),
-                                         (640, 896, 384, 1)])
+@pytest.mark.parametrize("m,k,n,depth", EMU_SHAPES)
 def test_split_matches_oracle_emulation(fastmm, tile, dist, m, k, n, depth):
     # Against the oracle's emulation of the same arithmetic (hi/lo splits,
     # three products summed in FP64 per leaf, FP32 additions): only the
@@ -241,6 +264,8 @@ def test_split_matches_oracle_emulation(fastmm, tile, dist, m, k, n, depth):
     # form's own error against the exact product -- a dropped term, a wrong
     # rounding or a wrong scale would show.  Sizes whose halves are
     # multiples of 4, where the engine splits exactly at ceil(m/2).
+    # The comparison is only meaningful where the two splits agree.
+    assert all(_splits_follow_eq1(x, depth) for x in (m, k, n)), (m, k, n, depth)
     gen = synthgen.uniform_pm1 if dist == "uniform" else synthgen.loguniform
     A, B = gen(3801 + m, m, k), gen(3802 + n, k, n)
     C = empty_dev(m, n)
