@@ -385,3 +385,26 @@ def test_depth_first_fallback_first_call_in_fresh_process(fastmm, tmp_path):
     assert launches > fastmm.get_stats()["launches"]  # it did run depth first
     assert np.array_equal(got, host(C0))
     assert checks.rel_frob(got, classic.gemm(A, B)) <= TOL_WINOGRAD
+
+
+@pytest.mark.parametrize("M,K,N,depth", [(3000, 2000, 8195, 2), (4100, 1030, 8203, 3), (2051, 4097, 9001, 1)])
+def test_host_pipeline_column_bands_odd_exact(fastmm, M, K, N, depth):
+    # Host operands wide enough for the pipelined path's column bands of B
+    # (B's quadrants at least 4096 wide), with odd extents: clipped right
+    # and bottom quadrants, padded device copies.  Entries in {-1, 0, 1} keep
+    # every FP32 step exact (|intermediates| far below 2^24 for K <= 4097
+    # and depth <= 3), so sampled rows and Freivalds' check must be exact.
+    import torch
+    say(f"pipelined column bands {M}x{K}x{N} depth={depth}")
+    A = ints(151 + M, M, K)
+    B = ints(152 + N, K, N)
+    Cp = torch.full((M, N), float("nan")).pin_memory()
+    fastmm.gemm(M, N, K, torch.from_numpy(A).pin_memory(), torch.from_numpy(B).pin_memory(), Cp,
+                depth=depth, leaf=1)
+    assert fastmm.get_stats()["depth"] == depth
+    C = Cp.numpy()
+    assert np.isfinite(C).all()
+    rows = synthgen.row_sample(153 + M, M, 16)
+    assert np.array_equal(C[rows].astype(np.float64), classic.gemm_rows(A, B, rows))
+    x = synthgen.signs_pm1(154 + N, N)
+    assert np.array_equal(classic.gemv(C, x), classic.gemv(A, classic.gemv(B, x)))
