@@ -316,7 +316,11 @@ int plan_choose_batched(Library& L, int64_t M, int64_t N, int64_t K, int mode, f
         (c.first == def ||
          (leaf_tiles_128(M, N, c.first) >= 1024 && std::min(std::min(M, N), K) >> c.first >= 1024)))
       cand.push_back(c);
-  if (cand.size() <= 1) return kSuccess;
+  // The rule's own depth must be among them (beyond the candidates' depth
+  // limit the rule stands).
+  bool has_def = false;
+  for (const auto& c : cand) has_def = has_def || c.first == def;
+  if (cand.size() <= 1 || !has_def) return kSuccess;
   int best = -1;
   if (mode == FASTMM_PLAN_MODEL && P.trained) {
     const std::vector<double> pred = model_predict(L, M, N, K, cand);
