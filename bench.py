@@ -44,8 +44,8 @@ PEAK_HBM_GBS = 8000.0
 # x (1280 | 1152), mean per launch
 # (profiles/leaf_gemm_n19456_d3_pinned_hbm_traffic.md).  Valid for
 # leaf_gemm_kernel<128,128,16,2,2> in those configurations only.
-TRAFFIC_DEVICE_BYTES_PER_LAUNCH = 37642619.6 * 1024 * 2.000 + 7924672.0 * 1024 * 1.000
-TRAFFIC_PINNED_BYTES_PER_LAUNCH = 1485667.6 * 1024 * 2.000 + 288748.7 * 1024 * 1.000
+TRAFFIC_DEVICE_BYTES_PER_LAUNCH = 37626398.4 * 1024 * 2.000 + 7924672.0 * 1024 * 1.000
+TRAFFIC_PINNED_BYTES_PER_LAUNCH = 1481106.4 * 1024 * 2.000 + 287906.9 * 1024 * 1.000
 
 
 def cpu_model():
@@ -404,17 +404,22 @@ def main():
     log(f"bench: parity {parity}")
 
     # Dominant kernel: the grouped leaf GEMM.  Its launches are timed with
-    # HIP events recorded by the library on the stream it launches them on.
+    # HIP events recorded by the library on the stream it launches each on;
+    # the library reports the union of the launches' intervals (with host
+    # operands consecutive launches overlap on two compute streams, so the
+    # union, not the sum, is the time the leaf work took), and a launch's
+    # duration is that union over the launches.
     def leaf_roofline(leaf_list, launch_list, stats, traffic, kernel):
         n_launch = max(1, int(np.mean(launch_list)))
-        leaf_sum = float(np.mean(leaf_list))          # ms per step, all leaf launches
+        leaf_sum = float(np.mean(leaf_list))          # ms per step, union of all leaf launches
         avg_launch = leaf_sum / n_launch
         flops_launch = stats["leaf_flops"] / n_launch
         tf = flops_launch / (avg_launch * 1e-3) / 1e12
         peak = PEAK_16BIT_TFLOPS / 3 if split else PEAK_FP32_TFLOPS
         return {"bound": "mfma", "kernel": kernel, "achieved": tf, "peak": peak, "unit": "TFLOP/s",
                 "frac": tf / peak, "traffic": traffic, "flops_per_launch": flops_launch,
-                "avg_launch_ms": avg_launch, "launches_per_step": n_launch}, leaf_sum
+                "avg_launch_ms": avg_launch, "launches_per_step": n_launch,
+                "launch_ms_is": "union of the step's leaf launch intervals / launches"}, leaf_sum
 
     split = SPLIT_FORMS.get(args.tile)
     if split and st["depth"] >= 1:  # the scale and pack passes run fused with the last pre-additions

@@ -22,10 +22,14 @@
  *     untouched.
  *   - Every call is synchronous: it is enqueued on the library stream
  *     (fastmm_set_stream) and returns after that stream has drained.  With
- *     host operands the top recursion level runs product by product while
- *     two copy streams move operand quadrants in and result quadrants out
- *     (set FASTMM_PIPELINE=0 to copy everything first instead); the result
- *     is bit for bit the same either way.
+ *     host operands the top recursion level runs piece by piece, alternating
+ *     between the library stream and a second compute stream of the
+ *     library's (FASTMM_PIPE_STREAMS=1: the library stream alone), while two
+ *     copy streams move operand blocks in and result blocks out (set
+ *     FASTMM_PIPELINE=0 to copy everything first instead); the result is bit
+ *     for bit the same either way.  The other streams start after the work
+ *     queued on the library stream before the call, and the library stream
+ *     waits for them before the call returns.
  *   - The caller owns A, B and C; the library never keeps them.  The library
  *     owns its workspace (device memory for the recursion's temporaries and
  *     for staging host operands), which grows on demand and is released by
@@ -115,10 +119,14 @@ typedef struct {
   double transfer_bytes;   /* host<->device bytes moved */
   int launches;            /* kernel launches issued */
   size_t workspace_bytes;  /* device workspace in use */
-  /* Phase times of the last call from HIP events on the library stream, in
-   * milliseconds; -1 when profiling is off (fastmm_set_profiling). */
+  /* Phase times of the last call from HIP events on the library's streams,
+   * in milliseconds; -1 when profiling is off (fastmm_set_profiling) or the
+   * phase is not timed on that path.  leaf_ms is the time during which at
+   * least one leaf launch of the call ran: the union of the launches'
+   * intervals (host operands: the pieces' launches on the two compute
+   * streams overlap). */
   double h2d_ms, preadd_ms, leaf_ms, postadd_ms, d2h_ms, total_ms;
-  int leaf_launches;       /* grouped leaf launches leaf_ms is summed over */
+  int leaf_launches;       /* grouped leaf launches of the call */
   int graph_replayed;      /* batched: 1 if a cached HIP graph was replayed */
 } fastmm_stats_t;
 

@@ -89,6 +89,7 @@ void ensure_init(Library& L) {
   // compute stream by events).
   FASTMM_HIP(hipStreamCreateWithFlags(&L.h2d_stream, hipStreamNonBlocking));
   FASTMM_HIP(hipStreamCreateWithFlags(&L.d2h_stream, hipStreamNonBlocking));
+  FASTMM_HIP(hipStreamCreateWithFlags(&L.aux_stream, hipStreamNonBlocking));
   for (auto& e : L.sync_ev) FASTMM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (auto& e : L.leaf_ev) FASTMM_HIP(hipEventCreate(&e));
   for (auto& e : L.tune_ev) FASTMM_HIP(hipEventCreate(&e));
@@ -1418,6 +1419,9 @@ void fastmm_finalize(void) {
   std::lock_guard<std::mutex> g(L.mu);
   if (!L.initialised) return;
   (void)hipStreamSynchronize(L.stream);
+  if (L.h2d_stream) (void)hipStreamSynchronize(L.h2d_stream);
+  if (L.d2h_stream) (void)hipStreamSynchronize(L.d2h_stream);
+  if (L.aux_stream) (void)hipStreamSynchronize(L.aux_stream);
   destroy_graphs();
   if (L.arena) (void)hipFree(L.arena);
   if (L.pinned) (void)hipHostFree(L.pinned);
@@ -1429,11 +1433,10 @@ void fastmm_finalize(void) {
     if (e) (void)hipEventDestroy(e);
   for (auto& e : L.tune_ev)
     if (e) (void)hipEventDestroy(e);
-  if (L.h2d_stream) (void)hipStreamSynchronize(L.h2d_stream);
-  if (L.d2h_stream) (void)hipStreamSynchronize(L.d2h_stream);
   if (L.h2d_stream) (void)hipStreamDestroy(L.h2d_stream);
   if (L.d2h_stream) (void)hipStreamDestroy(L.d2h_stream);
-  L.h2d_stream = L.d2h_stream = nullptr;
+  if (L.aux_stream) (void)hipStreamDestroy(L.aux_stream);
+  L.h2d_stream = L.d2h_stream = L.aux_stream = nullptr;
   for (auto& e : L.sync_ev) e = nullptr;
   for (auto& e : L.leaf_ev) e = nullptr;
   for (auto& e : L.tune_ev) e = nullptr;

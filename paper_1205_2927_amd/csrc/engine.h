@@ -173,7 +173,8 @@ struct Library {
   hipEvent_t ev[8] = {};
   hipStream_t h2d_stream = nullptr;  // host->device staging copies
   hipStream_t d2h_stream = nullptr;  // device->host result copies
-  static constexpr int kSyncEvents = 64;
+  hipStream_t aux_stream = nullptr;  // second compute stream of the staged path
+  static constexpr int kSyncEvents = 160;
   hipEvent_t sync_ev[kSyncEvents] = {};  // ordering between the streams
   static constexpr int kLeafEvents = 128;
   hipEvent_t leaf_ev[kLeafEvents] = {};  // timing of leaf launches

@@ -36,6 +36,7 @@
 
 #include <algorithm>
 #include <array>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <vector>
@@ -77,6 +78,7 @@ struct Group {
   std::vector<Problem> probs;
   Schedule s;
   size_t desc_off = 0, desc_bytes = 0;
+  int x = 0;  // compute stream (index)
 };
 
 // Row bands [r0, r0 + rows) of the top quadrants (rows of the bottom
@@ -133,6 +135,16 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   const int64_t mb = M - m2, kb = K4 - k2, nb = N4 - n2;
   const int64_t kb_v = std::max<int64_t>(0, K - k2), nb_v = std::max<int64_t>(0, N - n2);
   const TileShape ts = tile_shape(tile);
+  // Compute streams of a Winograd product's pieces: the caller's stream
+  // and the library's second one, the pieces alternating between them (each
+  // stream with its own temporaries), so that one piece's additions and
+  // leaf launch fill the partial last round of workgroups of the previous
+  // piece's leaf launch (FASTMM_PIPE_STREAMS=1: the caller's stream alone).
+  int ncs = 1;
+  if (wino) {
+    const char* e = std::getenv("FASTMM_PIPE_STREAMS");
+    ncs = (e && e[0] == '1') ? 1 : 2;
+  }
 
   // ---- workspace layout (byte offsets into the arena)
   size_t off = 0;
@@ -402,6 +414,12 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
         p.b_tree_ready = trees && bs;
         as = bs = 1;
         groups.push_back({{p}});
+        // The last piece follows the one before it on the same stream: the
+        // result blocks that one completes are then formed and on their way
+        // out while the last piece runs, instead of waiting for workgroup
+        // slots behind its leaf launch.
+        const size_t gi = std::min(groups.size() - 1, order.size() >= 2 ? order.size() - 2 : 0);
+        groups.back().x = (int)(gi % ncs);
       }
     } else {
       for (auto& b : bands) groups.push_back({{plain_problem(b, 0)}});
@@ -429,7 +447,8 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     g.desc_off = desc_total;
     desc_total += g.desc_bytes;
   }
-  const size_t oTemp = take(temp_max);
+  const size_t temp_stride = align_up(temp_max, 256);
+  const size_t oTemp = take(temp_stride * ncs);
   const size_t oDesc = take(desc_total);
   if (!L.initialised) {  // sizing only
     g_dry_need = off;
@@ -457,7 +476,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     for (size_t i = 0; i < groups.size(); ++i) {
       groups[i].desc_off = doff[i];
       groups[i].desc_bytes = dbytes[i];
-      build_schedule(groups[i].probs, temps, groups[i].s);
+      build_schedule(groups[i].probs, temps + groups[i].x * temp_stride, groups[i].s);
     }
   }
 
@@ -496,6 +515,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       }
   }
   hipStream_t cs = L.stream, hs = L.h2d_stream, ds = L.d2h_stream;
+  hipStream_t xs[2] = {cs, ncs > 1 ? L.aux_stream : cs};
   int ev_next = 1;
   auto next_event = [&]() {
     if (ev_next >= Library::kSyncEvents) throw Error(kDeviceError, "pipeline event pool exhausted");
@@ -512,6 +532,11 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   }
   if (N4 > N) FASTMM_HIP(hipMemset2DAsync(dB + N, N4 * 4, 0, (N4 - N) * 4, K, hs));
   if (slot) FASTMM_HIP(hipMemcpyAsync(ddesc, host, 256 * slot, hipMemcpyHostToDevice, cs));
+  if (ncs > 1) {  // the second stream starts after the caller's work and that upload
+    hipEvent_t e = next_event();
+    FASTMM_HIP(hipEventRecord(e, cs));
+    FASTMM_HIP(hipStreamWaitEvent(xs[1], e, 0));
+  }
 
   // ---- inputs
   auto arrive = [&]() {  // event after the copies queued so far
@@ -533,9 +558,18 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     if (2 * nleaf + 1 >= Library::kLeafEvents) throw Error(kDeviceError, "leaf event pool exhausted");
     hipEvent_t b = L.leaf_ev[2 * nleaf], e = L.leaf_ev[2 * nleaf + 1];
     ++nleaf;
-    launches += enqueue_schedule(L, g.s, ddesc + g.desc_off, host + g.desc_off, b, e);
+    // enqueue_schedule launches on L.stream: point it at the group's stream.
+    const hipStream_t keep = L.stream;
+    L.stream = xs[g.x];
+    try {
+      launches += enqueue_schedule(L, g.s, ddesc + g.desc_off, host + g.desc_off, b, e);
+    } catch (...) {
+      L.stream = keep;
+      throw;
+    }
+    L.stream = keep;
   };
-  auto wait = [&](hipEvent_t e) { FASTMM_HIP(hipStreamWaitEvent(cs, e, 0)); };
+  auto wait = [&](int x, hipEvent_t e) { FASTMM_HIP(hipStreamWaitEvent(xs[x], e, 0)); };
 
   if (wino) {
     // ---- inputs, in the recipe's order
@@ -549,20 +583,30 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     FASTMM_HIP(hipEventRecord(L.ev[5], hs));
 
     // ---- compute
-    int waited = -1;  // inputs 0..waited are on the device (stream order)
-    auto wait_item = [&](int k) {
-      if (k > waited) {
-        wait(ev_item[k]);
-        waited = k;
+    int waited[2] = {-1, -1};  // per compute stream: inputs 0..waited are on the device
+    auto wait_item = [&](int x, int k) {
+      if (k > waited[x]) {
+        wait(x, ev_item[k]);
+        waited[x] = k;
       }
     };
     unsigned s_done[2] = {0, 0}, t_done[2] = {0, 0};  // outputs computed so far, per band
-    auto have = [&](int mat, int q, int band) {
-      return (mat == 0 ? a_item[q][band] : b_item[q][band]) <= waited;
+    // Which stream computed each S / T output, and the event after its pass.
+    struct Made {
+      hipEvent_t e = nullptr;
+      int x = -1;
     };
-    // Issue one pre-addition pass for every output of this operand's band
-    // whose inputs are all on the device and that is not computed yet.
-    auto preadd_pass = [&](int side, int bi) {
+    Made s_made[2][4], t_made[2][4];
+    auto after = [&](int x, const Made& m) {
+      if (m.x >= 0 && m.x != x) wait(x, m.e);
+    };
+    auto have = [&](int x, int mat, int q, int band) {
+      return (mat == 0 ? a_item[q][band] : b_item[q][band]) <= waited[x];
+    };
+    // Issue, on stream x, one pre-addition pass for every output of this
+    // operand's band whose inputs are all on the device and that is not
+    // computed yet.
+    auto preadd_pass = [&](int x, int side, int bi) {
       unsigned& done = side == 0 ? s_done[bi] : t_done[bi];
       unsigned mask = 0;
       for (int j = 0; j < 4; ++j) {
@@ -570,7 +614,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
         const unsigned in = preadd_inputs(side, 1u << j);
         bool ok = true;
         for (int q = 0; q < 4; ++q)
-          if ((in & (1u << q)) && !have(side, q, bi)) ok = false;
+          if ((in & (1u << q)) && !have(x, side, q, bi)) ok = false;
         if (ok) mask |= 1u << j;
       }
       if (!mask) return;
@@ -607,30 +651,65 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       n.mask = (int32_t)mask;
       const size_t o = next_slot();
       std::memcpy(host + o, &n, sizeof(n));
-      FASTMM_HIP(hipMemcpyAsync(ddesc + o, host + o, sizeof(n), hipMemcpyHostToDevice, cs));
+      FASTMM_HIP(hipMemcpyAsync(ddesc + o, host + o, sizeof(n), hipMemcpyHostToDevice, xs[x]));
       launch_preadd(side, reinterpret_cast<const PreAddNode*>(ddesc + o), 1,
-                    (int)add_blocks_for(n.h_r, n.h_c), pre_vec_ok(n), cs);
+                    (int)add_blocks_for(n.h_r, n.h_c), pre_vec_ok(n), xs[x]);
       ++launches;
       done |= mask;
+      if (ncs > 1) {
+        const Made m{next_event(), x};
+        FASTMM_HIP(hipEventRecord(m.e, xs[x]));
+        for (int j = 0; j < 4; ++j)
+          if (mask & (1u << j)) (side == 0 ? s_made : t_made)[bi][j] = m;
+      }
     };
     // Left / right operand: which S / T output product i reads (0 = none).
     static const int kLeftS[7] = {0, 0, 4, 0, 1, 2, 3};   // P3: S4, P5: S1, P6: S2, P7: S3
     static const int kRightT[7] = {0, 0, 0, 4, 1, 2, 3};  // P4: T4, P5: T1, P6: T2, P7: T3
     static const int kQuadP[4][4] = {{0, 1, -1, -1}, {0, 5, 4, 2}, {0, 5, 6, 3}, {0, 5, 6, 4}};
-    std::vector<char> pdone((size_t)7 * nband * ncband, 0), sent((size_t)4 * nband * ncband, 0);
+    std::vector<int> pgi((size_t)7 * nband * ncband, -1);  // piece -> its position in `order`
+    std::vector<char> sent((size_t)4 * nband * ncband, 0);
     auto pidx = [&](int i, int r, int c) { return ((size_t)r * ncband + c) * 7 + i; };
+    // Per piece: its first leaf event (recorded once its pre-additions, the
+    // shared inner temporaries included, are done) and, with two streams, an
+    // event after its last launch.  First piece of each (product, row band)
+    // and (product, column band): the one that computes the shared
+    // temporaries.
+    std::vector<int> piece_leaf(order.size(), -1);
+    std::vector<hipEvent_t> piece_end(order.size(), nullptr);
+    std::vector<int> a_first((size_t)7 * nband, -1), b_first((size_t)7 * ncband, -1);
     for (size_t gi = 0; gi < order.size(); ++gi) {
       const Piece& pc = order[gi];
+      const int x = groups[gi].x;
       int last = -1;
       for (int q = 0; q < 4; ++q) {
         if (kNeedA[pc.i] & (1u << q)) last = std::max(last, a_item[q][pc.r]);
         if (kNeedB[pc.i] & (1u << q)) last = std::max(last, b_item[q][pc.c]);
       }
-      wait_item(last);
-      if (kLeftS[pc.i] && !(s_done[pc.r] & (1u << (kLeftS[pc.i] - 1)))) preadd_pass(0, pc.r);
-      if (kRightT[pc.i] && !(t_done[pc.c] & (1u << (kRightT[pc.i] - 1)))) preadd_pass(1, pc.c);
+      wait_item(x, last);
+      if (kLeftS[pc.i]) {
+        const int j = kLeftS[pc.i] - 1;
+        if (!(s_done[pc.r] & (1u << j))) preadd_pass(x, 0, pc.r);
+        else after(x, s_made[pc.r][j]);
+      }
+      if (kRightT[pc.i]) {
+        const int j = kRightT[pc.i] - 1;
+        if (!(t_done[pc.c] & (1u << j))) preadd_pass(x, 1, pc.c);
+        else after(x, t_made[pc.c][j]);
+      }
+      int& af = a_first[(size_t)pc.i * nband + pc.r];
+      int& bf = b_first[(size_t)pc.i * ncband + pc.c];
+      if (trees && af >= 0 && groups[af].x != x) wait(x, L.leaf_ev[2 * piece_leaf[af]]);
+      if (trees && bf >= 0 && groups[bf].x != x) wait(x, L.leaf_ev[2 * piece_leaf[bf]]);
+      if (af < 0) af = (int)gi;
+      if (bf < 0) bf = (int)gi;
+      piece_leaf[gi] = nleaf;
       run_group(groups[gi]);
-      pdone[pidx(pc.i, pc.r, pc.c)] = 1;
+      if (ncs > 1) {
+        piece_end[gi] = next_event();
+        FASTMM_HIP(hipEventRecord(piece_end[gi], xs[x]));
+      }
+      pgi[pidx(pc.i, pc.r, pc.c)] = (int)gi;
       // Result blocks whose four (two for C11) products are now all done:
       // form them and send them out.
       for (int q = 0; q < 4; ++q) {
@@ -638,16 +717,21 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
         if (sq) continue;
         bool ok = true;
         for (int k = 0; k < 4; ++k)
-          if (kQuadP[q][k] >= 0 && !pdone[pidx(kQuadP[q][k], pc.r, pc.c)]) ok = false;
+          if (kQuadP[q][k] >= 0 && pgi[pidx(kQuadP[q][k], pc.r, pc.c)] < 0) ok = false;
         if (!ok) continue;
+        for (int k = 0; k < 4; ++k) {  // products finished on the other stream
+          if (kQuadP[q][k] < 0) continue;
+          const int j = pgi[pidx(kQuadP[q][k], pc.r, pc.c)];
+          if (groups[j].x != x) wait(x, piece_end[j]);
+        }
         const Band& b = bands[pc.r];
         const Band& c = cbands[pc.c];
         const size_t blk = (size_t)pc.r * ncband + pc.c;
-        launch_postadd(d_post[blk], 1, (int)add_blocks_for(b.rows, c.rows), vec_post[blk], cs, q);
+        launch_postadd(d_post[blk], 1, (int)add_blocks_for(b.rows, c.rows), vec_post[blk], xs[x], q);
         ++launches;
         const int qr = q / 2, qc = q % 2;
         hipEvent_t e = next_event();
-        FASTMM_HIP(hipEventRecord(e, cs));
+        FASTMM_HIP(hipEventRecord(e, xs[x]));
         FASTMM_HIP(hipStreamWaitEvent(ds, e, 0));
         d2h_block(C, ldc, dC, N4, (qr ? m2 : 0) + b.r0, (qc ? n2 : 0) + c.r0, qr ? b.bot : b.rows,
                   qc ? right_valid(c) : c.rows, ds);
@@ -680,11 +764,11 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       d2h_block(C, ldc, dC, N4, b.r0, half ? n2 : 0, b.rows, half ? nb_v : n2, ds);
     };
     for (int bi = 0; bi < nband; ++bi) {
-      wait(ea[bi]);
+      wait(0, ea[bi]);
       run_group(groups[bi]);  // C[b, left]
       block_out(bi, 0);
       if (bi == pivot) {
-        wait(eBR);
+        wait(0, eBR);
         for (int bj = 0; bj <= bi; ++bj) {
           run_group(groups[nband + bj]);  // C[bj, right]
           block_out(bj, 1);
@@ -694,6 +778,11 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
         block_out(bi, 1);
       }
     }
+  }
+  if (ncs > 1) {  // the caller's stream waits for the second one
+    hipEvent_t e = next_event();
+    FASTMM_HIP(hipEventRecord(e, xs[1]));
+    wait(0, e);
   }
   FASTMM_HIP(hipEventRecord(L.ev[7], ds));
   FASTMM_HIP(hipStreamSynchronize(ds));
@@ -719,14 +808,26 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   st.transfer_bytes = 4.0 * ((double)M * K + (double)K * N + (double)M * N);
   st.launches = launches;
   st.workspace_bytes = L.arena_bytes;
+  // Leaf time: the union of the leaf launches' intervals (the launches of
+  // the two compute streams overlap).
   double leaf = 0.0;
+  std::vector<std::pair<double, double>> iv;
   for (int i = 0; i < nleaf; ++i) {
-    const double t = ev_ms(L.leaf_ev[2 * i], L.leaf_ev[2 * i + 1]);
-    if (t < 0) {
+    const double a = ev_ms(L.ev[0], L.leaf_ev[2 * i]), b = ev_ms(L.ev[0], L.leaf_ev[2 * i + 1]);
+    if (a < 0 || b < 0) {
       leaf = -1.0;
       break;
     }
-    leaf += t;
+    iv.push_back({a, b});
+  }
+  if (leaf >= 0) {
+    std::sort(iv.begin(), iv.end());
+    double end = -1.0;
+    for (const auto& x : iv) {
+      if (x.second <= end) continue;
+      leaf += x.second - std::max(x.first, end);
+      end = x.second;
+    }
   }
   st.leaf_ms = leaf;
   st.h2d_ms = ev_ms(L.ev[0], L.ev[5]);

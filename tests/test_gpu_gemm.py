@@ -408,3 +408,33 @@ def test_host_pipeline_column_bands_odd_exact(fastmm, M, K, N, depth):
     assert np.array_equal(C[rows].astype(np.float64), classic.gemm_rows(A, B, rows))
     x = synthgen.signs_pm1(154 + N, N)
     assert np.array_equal(classic.gemv(C, x), classic.gemv(A, classic.gemv(B, x)))
+
+
+@pytest.mark.parametrize("M,K,N,depth", [(333, 201, 257, 3), (1024, 512, 768, 3), (3000, 2000, 8195, 2),
+                                         (4100, 1030, 8203, 3), (2051, 4097, 9001, 1)])
+def test_host_pipeline_two_streams_bitwise(fastmm, monkeypatch, M, K, N, depth):
+    # The pipelined path's pieces alternate between two compute streams by
+    # default; every piece computes the same values in the same order either
+    # way, so the result equals the one-stream schedule's bit for bit, on
+    # every one of repeated calls (a missing cross-stream wait would show as
+    # a result that changes from call to call), and the oracle's.
+    import torch
+    say(f"two compute streams {M}x{K}x{N} depth={depth}")
+    A = uniform(161 + M, M, K)
+    B = uniform(162 + N, K, N)
+    Ap = torch.from_numpy(A).pin_memory()
+    Bp = torch.from_numpy(B).pin_memory()
+    monkeypatch.setenv("FASTMM_PIPE_STREAMS", "1")
+    C1 = torch.full((M, N), float("nan")).pin_memory()
+    fastmm.gemm(M, N, K, Ap, Bp, C1, depth=depth, leaf=1)
+    one = fastmm.get_stats()
+    monkeypatch.delenv("FASTMM_PIPE_STREAMS")
+    for rep in range(3):
+        C2 = torch.full((M, N), float("nan")).pin_memory()
+        fastmm.gemm(M, N, K, Ap, Bp, C2, depth=depth, leaf=1)
+        st = fastmm.get_stats()
+        assert st["leaf_launches"] == one["leaf_launches"] and st["leaves"] == one["leaves"]
+        assert np.array_equal(C2.numpy(), C1.numpy()), f"call {rep}"
+    rows = synthgen.row_sample(163 + M, M, 8)
+    assert checks.sampled_rows_rel(C1.numpy(), A, B, rows) <= TOL_WINOGRAD
+    assert checks.freivalds_rel(C1.numpy(), A, B, synthgen.signs_pm1(164 + N, N)) <= TOL_WINOGRAD
