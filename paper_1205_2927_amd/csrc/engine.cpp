@@ -85,11 +85,21 @@ void ensure_init(Library& L) {
   FASTMM_HIP(hipStreamCreate(&L.own_stream));
   if (!L.stream) L.stream = L.own_stream;
   for (auto& e : L.ev) FASTMM_HIP(hipEventCreate(&e));
-  // Copy streams for the staged path (default priority, ordered against the
-  // compute stream by events).
-  FASTMM_HIP(hipStreamCreateWithFlags(&L.h2d_stream, hipStreamNonBlocking));
-  FASTMM_HIP(hipStreamCreateWithFlags(&L.d2h_stream, hipStreamNonBlocking));
-  FASTMM_HIP(hipStreamCreateWithFlags(&L.aux_stream, hipStreamNonBlocking));
+  // The staged path's copy streams and second compute stream (default
+  // priority, ordered against the library stream by events) run alongside
+  // the library stream, so each needs a hardware queue of its own.  HIP
+  // hands a new stream a queue that other streams already use once
+  // GPU_MAX_HW_QUEUES queues exist (4 by default; the caller's default
+  // stream usually holds one), and a compute stream that shared a queue with
+  // the copy-in stream would wait for every copy queued before its work.
+  // A stream created with a CU mask gets a queue of its own; the mask here
+  // enables every CU.
+  {
+    std::vector<uint32_t> mask(((size_t)prop.multiProcessorCount + 31) / 32, 0u);
+    for (int cu = 0; cu < prop.multiProcessorCount; ++cu) mask[cu / 32] |= 1u << (cu % 32);
+    for (hipStream_t* sp : {&L.h2d_stream, &L.d2h_stream, &L.aux_stream})
+      FASTMM_HIP(hipExtStreamCreateWithCUMask(sp, (uint32_t)mask.size(), mask.data()));
+  }
   for (auto& e : L.sync_ev) FASTMM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (auto& e : L.leaf_ev) FASTMM_HIP(hipEventCreate(&e));
   for (auto& e : L.tune_ev) FASTMM_HIP(hipEventCreate(&e));
