@@ -6,9 +6,10 @@
 // (Section 4.2).  On MI355X the same holds in proportion: at n = 19456 the
 // copies of A, B and C take about as long as the whole Winograd product.
 //
-// Here the top level of the recursion runs as a sequence of steps on a
-// compute stream while one copy stream brings operand blocks in and a second
-// copy stream sends result blocks back as soon as they are final.  The top
+// Here the top level of the recursion runs as a sequence of pieces,
+// alternating between two compute streams, while one copy stream brings
+// operand blocks in and a second copy stream sends result blocks back as
+// soon as they are final.  The top
 // quadrants are cut into two row bands (A side) and, where B's quadrants are
 // at least 4096 wide, two column bands (B side): piece (i, r, c) of
 // top-level product i, P_i[r, c] = L_i[r] R_i[:, c],
