@@ -1153,7 +1153,16 @@ void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
   const bool pipelined = !(pipe && pipe[0] == '0');
   if (!on_dev && pipelined && std::min(std::min(M, N), K) >= 2 &&
       pipelined_need(M, N, K, p.depth, tile) <= workspace_budget(L)) {
-    gemm_host_pipelined(L, M, N, K, A, lda, B, ldb, C, ldc, p.depth, tile, st);
+    try {
+      gemm_host_pipelined(L, M, N, K, A, lda, B, ldb, C, ldc, p.depth, tile, st);
+    } catch (...) {
+      // Work already queued on the staged path's streams must not outlive
+      // the call: the next one reuses the workspace it reads and writes.
+      for (hipStream_t x : {L.stream, L.aux_stream, L.h2d_stream, L.d2h_stream})
+        if (x) (void)hipStreamSynchronize(x);
+      (void)hipGetLastError();
+      throw;
+    }
     if (!L.profiling) {
       st.h2d_ms = st.preadd_ms = st.leaf_ms = st.postadd_ms = st.d2h_ms = st.total_ms = -1.0;
     }
