@@ -28,8 +28,8 @@
  *     copy streams move operand blocks in and result blocks out (set
  *     FASTMM_PIPELINE=0 to copy everything first instead); the result is bit
  *     for bit the same either way.  The other streams start after the work
- *     queued on the library stream before the call, and the library stream
- *     waits for them before the call returns.
+ *     queued on the library stream before the call, and the call returns
+ *     once all of them have drained.
  *   - The caller owns A, B and C; the library never keeps them.  The library
  *     owns its workspace (device memory for the recursion's temporaries and
  *     for staging host operands), which grows on demand and is released by

@@ -780,13 +780,13 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       }
     }
   }
-  if (ncs > 1) {  // the caller's stream waits for the second one
-    hipEvent_t e = next_event();
-    FASTMM_HIP(hipEventRecord(e, xs[1]));
-    wait(0, e);
-  }
   FASTMM_HIP(hipEventRecord(L.ev[7], ds));
+  // Every stream of the call has drained when it returns.  (The second
+  // compute stream is joined on the host: a final wait of the caller's
+  // stream for it would leave that stream reporting unfinished work to the
+  // first query after the return.)
   FASTMM_HIP(hipStreamSynchronize(ds));
+  if (ncs > 1) FASTMM_HIP(hipStreamSynchronize(xs[1]));
   FASTMM_HIP(hipStreamSynchronize(cs));
   FASTMM_HIP(hipStreamSynchronize(hs));
 

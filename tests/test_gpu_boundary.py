@@ -84,3 +84,34 @@ def test_finalize_then_fresh_calls(fastmm):
     Ch = torch.full((n, n), float("nan")).pin_memory()
     fastmm.gemm(n, n, n, Ah, Bh, Ch, depth=3, leaf=64)
     assert checks.rel_frob(Ch.numpy(), classic.gemm(A, B)) <= 1e-4
+
+
+def test_set_stream_host_operands_two_compute_streams(fastmm):
+    # Host operands on a caller's side stream: the staged path's other
+    # streams (copies in and out, the second compute stream) start after the
+    # work queued on it and it waits for them, so the call returns with the
+    # side stream drained and the result equals the default stream's.
+    import torch
+    M, K, N = 3000, 2000, 8195
+    A = uniform(8241, M, K)
+    B = uniform(8242, K, N)
+    Ah = torch.from_numpy(A).pin_memory()
+    Bh = torch.from_numpy(B).pin_memory()
+    ref = torch.full((M, N), float("nan")).pin_memory()
+    fastmm.gemm(M, N, K, Ah, Bh, ref, depth=2, leaf=1)
+    big = torch.ones(1 << 26, device="cuda")
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    Ch = torch.full((M, N), float("nan")).pin_memory()
+    try:
+        with torch.cuda.stream(s):
+            for _ in range(40):
+                big.mul_(1.0)
+        say("pinned gemm on a caller's side stream after queued work")
+        fastmm.set_stream(s)
+        fastmm.gemm(M, N, K, Ah, Bh, Ch, depth=2, leaf=1)
+        assert s.query()
+    finally:
+        fastmm.set_stream(None)
+    assert np.array_equal(Ch.numpy(), ref.numpy())
+    assert checks.rel_frob(Ch.numpy()[:64], classic.gemm(A[:64], B)) <= 1e-4
