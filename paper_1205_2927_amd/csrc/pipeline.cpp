@@ -32,6 +32,9 @@
 // its four products (C11: P1 P2; C12: P1 P6 P5 P3; C21: P1 P6 P7 P4; C22: P1
 // P6 P7 P5) are done, so one block of one quadrant (about 1.5 ms of copy at
 // n = 19456) remains after the last piece.
+//// A plain product (depth 0) streams A's rows and B's columns in quarters,
+// alternately, and computes each block C[r, c] as a piece once its two
+// bands are in.
 //
 #include <hip/hip_runtime.h>
 
@@ -136,16 +139,14 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   const int64_t mb = M - m2, kb = K4 - k2, nb = N4 - n2;
   const int64_t kb_v = std::max<int64_t>(0, K - k2), nb_v = std::max<int64_t>(0, N - n2);
   const TileShape ts = tile_shape(tile);
-  // Compute streams of a Winograd product's pieces: the caller's stream
-  // and the library's second one, the pieces alternating between them (each
-  // stream with its own temporaries), so that one piece's additions and
-  // leaf launch fill the partial last round of workgroups of the previous
-  // piece's leaf launch (FASTMM_PIPE_STREAMS=1: the caller's stream alone).
-  int ncs = 1;
-  if (wino) {
-    const char* e = std::getenv("FASTMM_PIPE_STREAMS");
-    ncs = (e && e[0] == '1') ? 1 : 2;
-  }
+  // Compute streams of the pieces: the caller's stream and the library's
+  // second one, the pieces alternating between them (each stream with its
+  // own temporaries), so that one piece's additions and leaf launch fill the
+  // partial last round of workgroups of the previous piece's leaf launch
+  // (FASTMM_PIPE_STREAMS=1: the caller's stream alone).
+  int ncs = 2;
+  if (const char* e = std::getenv("FASTMM_PIPE_STREAMS"))
+    if (e[0] == '1') ncs = 1;
 
   // ---- workspace layout (byte offsets into the arena)
   size_t off = 0;
@@ -160,7 +161,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   // ---- bands.  Winograd: row bands of the top quadrants' rows (m2) and
   // column bands of their columns (n2); a band of the bottom (right)
   // quadrants keeps only its valid rows (columns).  Plain product: A's rows
-  // in quarters.
+  // and B's columns in quarters.
   std::vector<Band> bands, cbands;
   if (wino) {
     bands = make_bands(m2, mb, 2, (int64_t)ts.bm << (depth - 1));
@@ -171,13 +172,25 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     // 4864 block).
     cbands = make_bands(n2, nb, n2 >= 4096 ? 2 : 1, (int64_t)ts.bn << (depth - 1));
   } else {
-    // Quarters of M, rounded to whole tiles when M allows (at most 6 bands).
-    int64_t q = (M + 3) / 4;
-    if (q >= ts.bm) q = (q + ts.bm / 2) / ts.bm * ts.bm;
-    for (int64_t r0 = 0; r0 < M; r0 += q) bands.push_back({r0, std::min(q, M - r0), 0});
+    // Quarters of M and of the padded width N4, rounded to whole tiles where
+    // the extent allows (at most 6 bands each); column bands start at
+    // multiples of 4, so that B's and C's rows in a band stay 16-byte
+    // aligned.
+    auto quarters = [](int64_t x, int64_t t, int64_t a) {
+      std::vector<Band> v;
+      int64_t q = (x + 3) / 4;
+      if (q >= t) q = (q + t / 2) / t * t;
+      q = (q + a - 1) / a * a;
+      for (int64_t r0 = 0; r0 < x; r0 += q) v.push_back({r0, std::min(q, x - r0), 0});
+      return v;
+    };
+    bands = quarters(M, ts.bm, 1);
+    cbands = quarters(N4, ts.bn, 4);
   }
   const int nband = (int)bands.size(), ncband = (int)cbands.size();
-  // Valid host columns of column band c of the right quadrants.
+  // Valid host columns of a column band of B (plain product) or of the right
+  // quadrants (Winograd).
+  auto plain_valid = [&](const Band& c) { return std::max<int64_t>(0, std::min(c.rows, N - c.r0)); };
   auto right_valid = [&](const Band& c) {
     return std::max<int64_t>(0, std::min(c.rows, nb_v - c.r0));
   };
@@ -293,16 +306,16 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     }
     return p;
   };
-  auto plain_problem = [&](const Band& b, int half) {
+  auto plain_problem = [&](const Band& b, const Band& c) {
     Problem p;
     p.M = b.rows;
     p.K = K4;
-    p.N = half == 0 ? n2 : nb;
+    p.N = c.rows;
     p.A = dA + b.r0 * K4;
     p.lda = K4;
-    p.B = dB + (half ? n2 : 0);
+    p.B = dB + c.r0;
     p.ldb = N4;
-    p.C = dC + b.r0 * N4 + (half ? n2 : 0);
+    p.C = dC + b.r0 * N4 + c.r0;
     p.ldc = N4;
     p.depth = 0;
     p.tile = tile;
@@ -322,6 +335,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     int i, r, c;
   };
   std::vector<Piece> order;  // pieces in compute order
+  std::vector<int> plain_ready;  // plain product: last input item each piece needs
   int a_item[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
   int b_item[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
   // Quadrants each product reads (bit 0 = X11, 1 = X12, 2 = X21, 3 = X22).
@@ -402,6 +416,30 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       tc = best_start + 2.0 * bands[pc.r].rows * k2 * cbands[pc.c].rows / 120e12;
       order.push_back(pc);
     }
+  } else {
+    // Plain product: B's first column band and A's first row band, then A's
+    // and B's further bands in turn, so that every band that arrives
+    // completes a row or column of pieces; pieces in order of the later of
+    // their two bands.
+    const int nmax = std::max(nband, ncband);
+    for (int i = 0; i < nmax; ++i) {
+      if (i == 0) {
+        items.push_back({1, 0, 0});
+        items.push_back({0, 0, 0});
+        continue;
+      }
+      if (i < nband) items.push_back({0, 0, i});
+      if (i < ncband) items.push_back({1, 0, i});
+    }
+    std::vector<int> ia(nband), ib(ncband);
+    for (size_t k = 0; k < items.size(); ++k) (items[k].mat == 0 ? ia : ib)[items[k].band] = (int)k;
+    for (int r = 0; r < nband; ++r)
+      for (int c = 0; c < ncband; ++c) order.push_back({0, r, c});
+    std::stable_sort(order.begin(), order.end(), [&](const Piece& x, const Piece& y) {
+      return std::max(ia[x.r], ib[x.c]) < std::max(ia[y.r], ib[y.c]);
+    });
+    plain_ready.resize(order.size());
+    for (size_t g = 0; g < order.size(); ++g) plain_ready[g] = std::max(ia[order[g].r], ib[order[g].c]);
   }
   auto build_groups = [&]() {
     groups.clear();
@@ -415,17 +453,16 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
         p.b_tree_ready = trees && bs;
         as = bs = 1;
         groups.push_back({{p}});
-        // The last piece follows the one before it on the same stream: the
-        // result blocks that one completes are then formed and on their way
-        // out while the last piece runs, instead of waiting for workgroup
-        // slots behind its leaf launch.
-        const size_t gi = std::min(groups.size() - 1, order.size() >= 2 ? order.size() - 2 : 0);
-        groups.back().x = (int)(gi % ncs);
       }
     } else {
-      for (auto& b : bands) groups.push_back({{plain_problem(b, 0)}});
-      for (auto& b : bands) groups.push_back({{plain_problem(b, 1)}});
+      for (const Piece& pc : order) groups.push_back({{plain_problem(bands[pc.r], cbands[pc.c])}});
     }
+    // Pieces alternate between the compute streams.  The last piece follows
+    // the one before it on the same stream: the result blocks that one
+    // completes are then formed and on their way out while the last piece
+    // runs, instead of waiting for workgroup slots behind its leaf launch.
+    for (size_t g = 0; g < groups.size(); ++g)
+      groups[g].x = (int)(std::min(g, groups.size() >= 2 ? groups.size() - 2 : 0) % ncs);
   };
   build_groups();
   // Descriptor slots: pre-addition passes (at most 4 per row band for S and
@@ -571,10 +608,17 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     L.stream = keep;
   };
   auto wait = [&](int x, hipEvent_t e) { FASTMM_HIP(hipStreamWaitEvent(xs[x], e, 0)); };
+  std::vector<hipEvent_t> ev_item(items.size());  // after each input item's copy
+  int waited[2] = {-1, -1};  // per compute stream: inputs 0..waited are on the device
+  auto wait_item = [&](int x, int k) {
+    if (k > waited[x]) {
+      wait(x, ev_item[k]);
+      waited[x] = k;
+    }
+  };
 
   if (wino) {
     // ---- inputs, in the recipe's order
-    std::vector<hipEvent_t> ev_item(items.size());
     for (size_t k = 0; k < items.size(); ++k) {
       const Item& it = items[k];
       if (it.mat == 0) a_band(it.q / 2, it.q % 2, bands[it.band]);
@@ -584,13 +628,6 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     FASTMM_HIP(hipEventRecord(L.ev[5], hs));
 
     // ---- compute
-    int waited[2] = {-1, -1};  // per compute stream: inputs 0..waited are on the device
-    auto wait_item = [&](int x, int k) {
-      if (k > waited[x]) {
-        wait(x, ev_item[k]);
-        waited[x] = k;
-      }
-    };
     unsigned s_done[2] = {0, 0}, t_done[2] = {0, 0};  // outputs computed so far, per band
     // Which stream computed each S / T output, and the event after its pass.
     struct Made {
@@ -740,44 +777,30 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       }
     }
   } else {
-    // Plain product.  In: B's left half and A's first band, A's second band,
-    // B's right half, then the remaining bands.  Run C[b, left] as each band
-    // arrives; once the right half is in, the right halves of the bands so
-    // far, then both halves of each later band.
-    const int pivot = std::min(1, nband - 1);
-    std::vector<hipEvent_t> ea(nband);
-    hipEvent_t eBR = nullptr;
-    h2d_block(dB, N4, B, ldb, 0, 0, K, n2, hs);
-    for (int bi = 0; bi < nband; ++bi) {
-      h2d_block(dA, K4, A, lda, bands[bi].r0, 0, bands[bi].rows, K, hs);
-      ea[bi] = arrive();
-      if (bi == pivot) {
-        h2d_block(dB, N4, B, ldb, 0, n2, K, nb_v, hs);
-        eBR = arrive();
+    // Plain product: the bands in the order of `items`, each piece C[r, c]
+    // once its two bands are in, each result block sent out once computed.
+    for (size_t k = 0; k < items.size(); ++k) {
+      const Item& it = items[k];
+      if (it.mat == 0) {
+        const Band& b = bands[it.band];
+        h2d_block(dA, K4, A, lda, b.r0, 0, b.rows, K, hs);
+      } else {
+        const Band& c = cbands[it.band];
+        h2d_block(dB, N4, B, ldb, 0, c.r0, K, plain_valid(c), hs);
       }
+      ev_item[k] = arrive();
     }
     FASTMM_HIP(hipEventRecord(L.ev[5], hs));
-    auto block_out = [&](int bi, int half) {
-      const Band& b = bands[bi];
+    for (size_t gi = 0; gi < order.size(); ++gi) {
+      const int x = groups[gi].x;
+      const Band& b = bands[order[gi].r];
+      const Band& c = cbands[order[gi].c];
+      wait_item(x, plain_ready[gi]);
+      run_group(groups[gi]);
       hipEvent_t e = next_event();
-      FASTMM_HIP(hipEventRecord(e, cs));
+      FASTMM_HIP(hipEventRecord(e, xs[x]));
       FASTMM_HIP(hipStreamWaitEvent(ds, e, 0));
-      d2h_block(C, ldc, dC, N4, b.r0, half ? n2 : 0, b.rows, half ? nb_v : n2, ds);
-    };
-    for (int bi = 0; bi < nband; ++bi) {
-      wait(0, ea[bi]);
-      run_group(groups[bi]);  // C[b, left]
-      block_out(bi, 0);
-      if (bi == pivot) {
-        wait(0, eBR);
-        for (int bj = 0; bj <= bi; ++bj) {
-          run_group(groups[nband + bj]);  // C[bj, right]
-          block_out(bj, 1);
-        }
-      } else if (bi > pivot) {
-        run_group(groups[nband + bi]);
-        block_out(bi, 1);
-      }
+      d2h_block(C, ldc, dC, N4, b.r0, c.r0, b.rows, plain_valid(c), ds);
     }
   }
   FASTMM_HIP(hipEventRecord(L.ev[7], ds));
