@@ -32,7 +32,8 @@
 // its four products (C11: P1 P2; C12: P1 P6 P5 P3; C21: P1 P6 P7 P4; C22: P1
 // P6 P7 P5) are done, so one block of one quadrant (about 1.5 ms of copy at
 // n = 19456) remains after the last piece.
-//// A plain product (depth 0) streams A's rows and B's columns in quarters,
+//
+// A plain product (depth 0) streams A's rows and B's columns in quarters,
 // alternately, and computes each block C[r, c] as a piece once its two
 // bands are in.
 //
