@@ -151,6 +151,29 @@ def test_poisoned_workspace(fastmm, monkeypatch):
         assert checks.rel_frob(got, classic.gemm(A, B)) < TOL_WINOGRAD
 
 
+@pytest.mark.parametrize("m,k,n,d", [(333, 201, 257, 3), (3000, 2000, 8195, 2), (4100, 1030, 8203, 3),
+                                     (1500, 700, 900, 0), (2051, 4097, 9001, 0)])
+def test_poisoned_workspace_host_pipeline(fastmm, monkeypatch, m, k, n, d):
+    # The same with host operands: the pipelined path's device copies of A,
+    # B and C, its temporaries and its padding all live in the poisoned
+    # workspace, so a piece that read an operand block, an S / T band or a
+    # shared inner temporary before the stream that writes it had done so
+    # would leave NaN in C.
+    import torch
+    monkeypatch.setenv("FASTMM_POISON", "1")
+    say(f"poisoned host pipeline {m}x{k}x{n} depth={d}")
+    A = uniform(99 + m, m, k)
+    B = uniform(100 + n, k, n)
+    Cp = torch.full((m, n), float("nan")).pin_memory()
+    fastmm.gemm(m, n, k, torch.from_numpy(A).pin_memory(), torch.from_numpy(B).pin_memory(), Cp,
+                depth=d, leaf=1)
+    got = Cp.numpy()
+    assert np.isfinite(got).all()
+    rows = synthgen.row_sample(101 + m, m, 8)
+    assert checks.sampled_rows_rel(got, A, B, rows) <= TOL_WINOGRAD
+    assert checks.freivalds_rel(got, A, B, synthgen.signs_pm1(102 + n, n)) <= TOL_WINOGRAD
+
+
 def test_empty_and_k0(fastmm):
     import torch
     C = torch.full((4, 5), 9.0, device="cuda")
