@@ -174,9 +174,9 @@ struct Library {
   hipStream_t h2d_stream = nullptr;  // host->device staging copies
   hipStream_t d2h_stream = nullptr;  // device->host result copies
   hipStream_t aux_stream = nullptr;  // second compute stream of the staged path
-  static constexpr int kSyncEvents = 160;
+  static constexpr int kSyncEvents = 512;
   hipEvent_t sync_ev[kSyncEvents] = {};  // ordering between the streams
-  static constexpr int kLeafEvents = 128;
+  static constexpr int kLeafEvents = 256;
   hipEvent_t leaf_ev[kLeafEvents] = {};  // timing of leaf launches
   hipEvent_t tune_ev[2] = {};            // planner's candidate timing
   int* leaf_queue = nullptr;             // two counters for persistent leaf launches

@@ -93,21 +93,83 @@ struct Band {
 };
 
 // Also column bands of the left quadrants' n2 columns (r0, rows: first
-// column and width; bot: valid columns of the right quadrants' band).  The
-// split is a multiple of `align` near the middle, else of 4 (16-byte aligned
-// band starts), else the middle.
+// column and width; bot: valid columns of the right quadrants' band).  Two
+// bands split at a multiple of `align` near the middle, else of 4 (16-byte
+// aligned band starts), else the middle.  More bands (where m2 holds at
+// least one unit of `align` per band): whole units each, the first bands
+// one unit longer where the units do not divide evenly, the last band also
+// taking the rows beyond the last whole unit.
 std::vector<Band> make_bands(int64_t m2, int64_t mb, int nb, int64_t align) {
-  std::vector<Band> v;
-  int64_t split = m2;
-  if (nb >= 2 && m2 >= 2) {
-    split = (m2 / 2 + align / 2) / align * align;
+  std::vector<int64_t> starts{0};
+  if (nb >= 3 && align > 0 && m2 / align >= nb) {
+    const int64_t units = m2 / align, base = units / nb, rem = units % nb;
+    int64_t r = 0;
+    for (int i = 0; i + 1 < nb; ++i) {
+      r += (base + (i < rem ? 1 : 0)) * align;
+      starts.push_back(r);
+    }
+  } else if (nb >= 2 && m2 >= 2) {
+    int64_t split = (m2 / 2 + align / 2) / align * align;
     if (split <= 0 || split >= m2) split = (m2 / 2 + 3) / 4 * 4;
     if (split <= 0 || split >= m2) split = (m2 + 1) / 2;
+    starts.push_back(split);
   }
-  v.push_back({0, split, std::min(split, mb)});
-  if (split < m2) v.push_back({split, m2 - split, std::max<int64_t>(0, std::min(m2 - split, mb - split))});
+  std::vector<Band> v;
+  for (size_t i = 0; i < starts.size(); ++i) {
+    const int64_t r0 = starts[i], r1 = i + 1 < starts.size() ? starts[i + 1] : m2;
+    v.push_back({r0, r1 - r0, std::max<int64_t>(0, std::min(r1 - r0, mb - r0))});
+  }
   return v;
 }
+
+// Input orders of the Winograd pipeline per band layout (row bands x column
+// bands), each block as {matrix (0: A, 1: B), quadrant (0: X11, 1: X12, 2:
+// X21, 3: X22), band}.  Found by simulating the copies (at the PCIe rate)
+// and the pieces (at the leaf rate) for n = 19456 and searching over orders.
+struct Recipe {
+  int nr, nc;
+  std::vector<std::array<int, 3>> items;
+};
+
+const std::vector<Recipe>& recipes() {
+  static const std::vector<Recipe> r = {
+      // Two row and two column bands: B quadrants before A ones within a
+      // pair, the first row and column bands of the X11 quadrants first, A12
+      // last.
+      {2, 2, {{1, 0, 0}, {0, 0, 0}, {1, 0, 1}, {0, 0, 1}, {1, 1, 1}, {0, 2, 1}, {1, 3, 1}, {0, 3, 1},
+              {1, 1, 0}, {1, 3, 0}, {1, 2, 0}, {0, 3, 0}, {0, 1, 0}, {0, 2, 0}, {1, 2, 1}, {0, 1, 1}}},
+      // Whole B quadrants (one column band): A11[r0] B11 A22[r0] A11[r1]
+      // A21[r0] B12 B22 B21 A22[r1] A21[r1] A12[r0] A12[r1].
+      {2, 1, {{0, 0, 0}, {1, 0, 0}, {0, 3, 0}, {0, 0, 1}, {0, 2, 0}, {1, 1, 0}, {1, 3, 0}, {1, 2, 0},
+              {0, 3, 1}, {0, 2, 1}, {0, 1, 0}, {0, 1, 1}}},
+      // Finer layouts (the same search, pieces priced at the two-stream rate).
+      {4, 2, {{1, 0, 0}, {0, 0, 1}, {1, 0, 1}, {0, 2, 3}, {0, 0, 3}, {0, 0, 2}, {1, 3, 1}, {0, 0, 0},
+              {1, 1, 1}, {0, 3, 3}, {0, 2, 1}, {0, 3, 1}, {0, 2, 0}, {0, 1, 3}, {0, 1, 1}, {0, 3, 0},
+              {1, 1, 0}, {1, 3, 0}, {1, 2, 0}, {0, 2, 2}, {0, 3, 2}, {0, 1, 0}, {0, 1, 2}, {1, 2, 1}}},
+      {6, 2, {{0, 2, 3}, {1, 0, 1}, {0, 0, 3}, {0, 0, 1}, {0, 0, 0}, {1, 0, 0}, {0, 0, 2}, {0, 0, 5},
+              {0, 0, 4}, {1, 1, 1}, {0, 3, 3}, {1, 3, 1}, {0, 2, 4}, {0, 3, 4}, {0, 2, 5}, {0, 2, 0},
+              {0, 3, 0}, {0, 3, 5}, {0, 1, 4}, {0, 1, 0}, {1, 1, 0}, {0, 1, 2}, {1, 2, 0}, {0, 1, 1},
+              {1, 3, 0}, {0, 3, 1}, {0, 3, 2}, {1, 2, 1}, {0, 2, 2}, {0, 2, 1}, {0, 1, 3}, {0, 1, 5}}},
+      {8, 2, {{0, 0, 6}, {1, 0, 1}, {0, 0, 3}, {0, 3, 5}, {0, 0, 7}, {1, 0, 0}, {0, 0, 4}, {0, 0, 1},
+              {0, 0, 5}, {0, 0, 0}, {1, 1, 1}, {0, 2, 5}, {0, 0, 2}, {1, 3, 1}, {0, 2, 2}, {0, 3, 2},
+              {0, 2, 3}, {0, 1, 4}, {0, 2, 7}, {0, 3, 7}, {0, 2, 6}, {0, 3, 4}, {0, 3, 3}, {0, 2, 4},
+              {0, 2, 0}, {0, 3, 0}, {0, 1, 0}, {0, 1, 2}, {1, 2, 1}, {0, 1, 1}, {0, 2, 1}, {1, 2, 0},
+              {0, 3, 6}, {1, 3, 0}, {1, 1, 0}, {0, 1, 7}, {0, 1, 3}, {0, 1, 6}, {0, 3, 1}, {0, 1, 5}}},
+      {4, 4, {{1, 2, 0}, {0, 1, 3}, {1, 2, 1}, {1, 2, 3}, {0, 1, 2}, {0, 1, 0}, {0, 1, 1}, {1, 2, 2},
+              {0, 0, 1}, {1, 0, 3}, {0, 0, 2}, {1, 0, 2}, {0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 0, 3},
+              {1, 0, 1}, {0, 2, 3}, {1, 3, 0}, {0, 3, 3}, {0, 3, 1}, {0, 2, 1}, {1, 1, 2}, {0, 2, 0},
+              {0, 3, 0}, {0, 2, 2}, {1, 3, 1}, {0, 3, 2}, {1, 3, 2}, {1, 1, 1}, {1, 3, 3}, {1, 1, 3}}},
+  };
+  return r;
+}
+
+const Recipe* find_recipe(int nr, int nc) {
+  for (const auto& r : recipes())
+    if (r.nr == nr && r.nc == nc) return &r;
+  return nullptr;
+}
+
+constexpr int kMaxBands = 8;
 
 }  // namespace
 
@@ -165,13 +227,26 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   // and B's columns in quarters.
   std::vector<Band> bands, cbands;
   if (wino) {
-    bands = make_bands(m2, mb, 2, (int64_t)ts.bm << (depth - 1));
     // Column bands only where B's quadrants are wide: for narrow ones (one
     // GPU's column panel of a sharded product, 19456 x 19456 x 2432) they
     // bring no earlier start worth the smaller leaf launches (33.9 against
     // 38.4 ms for that panel, 25.1 against 28.9 ms for a 9728 x 19456 x
-    // 4864 block).
-    cbands = make_bands(n2, nb, n2 >= 4096 ? 2 : 1, (int64_t)ts.bn << (depth - 1));
+    // 4864 block).  With column bands, four row bands where the top rows
+    // hold at least two leaf-tile units per band.  FASTMM_PIPE_ROWBANDS and
+    // FASTMM_PIPE_COLBANDS choose another layout that has an input order of
+    // its own (2 x 1, 2 x 2, 4 x 2, 6 x 2, 8 x 2, 4 x 4).
+    const int64_t ra = (int64_t)ts.bm << (depth - 1), ca = (int64_t)ts.bn << (depth - 1);
+    const bool colb = n2 >= 4096;
+    int nrb = colb && m2 / ra >= 8 ? 4 : 2, ncb = colb ? 2 : 1;
+    if (const char* e = std::getenv("FASTMM_PIPE_ROWBANDS")) nrb = std::atoi(e);
+    if (const char* e = std::getenv("FASTMM_PIPE_COLBANDS")) ncb = std::atoi(e);
+    if (!find_recipe(nrb, ncb) || (nrb > 2 && m2 / ra < nrb) || (ncb > 2 && n2 / ca < ncb) ||
+        (ncb > 1 && !colb)) {
+      nrb = 2;
+      ncb = colb ? 2 : 1;
+    }
+    bands = make_bands(m2, mb, nrb, ra);
+    cbands = make_bands(n2, nb, ncb, ca);
   } else {
     // Quarters of M and of the padded width N4, rounded to whole tiles where
     // the extent allows (at most 6 bands each); column bands start at
@@ -337,32 +412,21 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   };
   std::vector<Piece> order;  // pieces in compute order
   std::vector<int> plain_ready;  // plain product: last input item each piece needs
-  int a_item[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
-  int b_item[4][2] = {{-1, -1}, {-1, -1}, {-1, -1}, {-1, -1}};
+  int a_item[4][kMaxBands], b_item[4][kMaxBands];  // input item of quadrant q, band
+  for (int q = 0; q < 4; ++q)
+    for (int b = 0; b < kMaxBands; ++b) a_item[q][b] = b_item[q][b] = -1;
   // Quadrants each product reads (bit 0 = X11, 1 = X12, 2 = X21, 3 = X22).
   static const unsigned kNeedA[7] = {0x1, 0x2, 0xF, 0x8, 0xC, 0xD, 0x5};
   static const unsigned kNeedB[7] = {0x1, 0x4, 0x8, 0xF, 0x3, 0xB, 0xA};
   if (wino) {
-    // Input order, found by simulating the copies (at the PCIe rate) and the
-    // pieces (at the leaf rate) for n = 19456 and searching over orders: B
-    // quadrants before A ones within a pair, the first row and column bands
-    // of the X11 quadrants first, A12 last.  Blocks of a band that does not
-    // exist are skipped.
-    static const int kRecipe[16][3] = {{1, 0, 0}, {0, 0, 0}, {1, 0, 1}, {0, 0, 1},
-                                       {1, 1, 1}, {0, 2, 1}, {1, 3, 1}, {0, 3, 1},
-                                       {1, 1, 0}, {1, 3, 0}, {1, 2, 0}, {0, 3, 0},
-                                       {0, 1, 0}, {0, 2, 0}, {1, 2, 1}, {0, 1, 1}};
-    // With whole B quadrants (one column band) the same search gave:
-    // A11[r0] B11 A22[r0] A11[r1] A21[r0] B12 B22 B21 A22[r1] A21[r1]
-    // A12[r0] A12[r1].
-    static const int kRecipeB1[12][3] = {{0, 0, 0}, {1, 0, 0}, {0, 3, 0}, {0, 0, 1},
-                                         {0, 2, 0}, {1, 1, 0}, {1, 3, 0}, {1, 2, 0},
-                                         {0, 3, 1}, {0, 2, 1}, {0, 1, 0}, {0, 1, 1}};
-    std::vector<std::array<int, 3>> recipe;
-    if (ncband > 1)
-      for (const auto& x : kRecipe) recipe.push_back({x[0], x[1], x[2]});
-    else
-      for (const auto& x : kRecipeB1) recipe.push_back({x[0], x[1], x[2]});
+    // Input order: the layout's own (recipes()).
+    // (A layout with a single row band takes the two-band order, its
+    // missing band's blocks skipped.)
+    const Recipe* rc = find_recipe(nband, ncband);
+    if (!rc) rc = find_recipe(2, ncband > 1 ? 2 : 1);
+    if (!rc || nband > kMaxBands || ncband > kMaxBands)
+      throw Error(kDeviceError, "no input order for this band layout");
+    const auto& recipe = rc->items;
     for (const auto& x : recipe) {
       const int mat = x[0], q = x[1], band = x[2];
       if (band >= (mat == 0 ? nband : ncband)) continue;
@@ -629,13 +693,13 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     FASTMM_HIP(hipEventRecord(L.ev[5], hs));
 
     // ---- compute
-    unsigned s_done[2] = {0, 0}, t_done[2] = {0, 0};  // outputs computed so far, per band
+    unsigned s_done[kMaxBands] = {}, t_done[kMaxBands] = {};  // outputs computed so far, per band
     // Which stream computed each S / T output, and the event after its pass.
     struct Made {
       hipEvent_t e = nullptr;
       int x = -1;
     };
-    Made s_made[2][4], t_made[2][4];
+    Made s_made[kMaxBands][4], t_made[kMaxBands][4];
     auto after = [&](int x, const Made& m) {
       if (m.x >= 0 && m.x != x) wait(x, m.e);
     };

@@ -65,9 +65,9 @@ def test_plain_square_19456_device(fastmm):
 def test_headline_square_19456_depth3_pinned(fastmm):
     st = _check(fastmm, 19456, 19456, 19456, 3, 1024, 1001 + 3, 2001 + 3)
     assert st["depth"] == 3
-    # 7 top-level products in two row bands x two column bands, each piece a
-    # depth-2 product of 49 leaves, one grouped leaf launch per piece
-    assert st["leaves"] == 4 * 7 * 49 and st["leaf_launches"] == 28
+    # 7 top-level products in four row bands x two column bands, each piece
+    # a depth-2 product of 49 leaves, one grouped leaf launch per piece
+    assert st["leaves"] == 8 * 7 * 49 and st["leaf_launches"] == 56
     assert abs(st["leaf_flops"] - 2 * 19456**3 * (7 / 8) ** 3) < 1e-6 * 2 * 19456**3
 
 
