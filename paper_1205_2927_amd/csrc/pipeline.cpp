@@ -44,6 +44,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <string>
 #include <vector>
 
 #include "engine.h"
@@ -178,10 +180,25 @@ size_t g_dry_need = 0;
 }
 
 size_t pipelined_need(int64_t M, int64_t N, int64_t K, int depth, int tile) {
+  // The need depends on the shape, the plan and the layout switches only:
+  // kept per key, so that repeated calls skip the sizing pass.
+  auto env = [](const char* n) {
+    const char* e = std::getenv(n);
+    return std::string(e ? e : "-");
+  };
+  const std::string key = std::to_string(M) + ',' + std::to_string(N) + ',' + std::to_string(K) + ',' +
+                          std::to_string(depth) + ',' + std::to_string(tile) + ',' +
+                          env("FASTMM_PIPE_ROWBANDS") + ',' + env("FASTMM_PIPE_COLBANDS") + ',' +
+                          env("FASTMM_PIPE_STREAMS");
+  static std::map<std::string, size_t> cache;  // calls are serialised by the library lock
+  const auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
   Library dummy;
   fastmm_stats_t st{};
   g_dry_need = 0;
   gemm_host_pipelined(dummy, M, N, K, nullptr, 0, nullptr, 0, nullptr, 0, depth, tile, st);
+  if (cache.size() >= 64) cache.clear();
+  cache.emplace(key, g_dry_need);
   return g_dry_need;
 }
 
@@ -569,6 +586,57 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   tree_base = ws + oAT;
   char* temps = ws + oTemp;
   char* ddesc = ws + oDesc;
+  hipStream_t cs = L.stream, hs = L.h2d_stream, ds = L.d2h_stream;
+  hipStream_t xs[2] = {cs, ncs > 1 ? L.aux_stream : cs};
+  int ev_next = 1;
+  auto next_event = [&]() {
+    if (ev_next >= Library::kSyncEvents) throw Error(kDeviceError, "pipeline event pool exhausted");
+    return L.sync_ev[ev_next++];
+  };
+  FASTMM_HIP(hipEventRecord(L.ev[0], cs));
+  FASTMM_HIP(hipEventRecord(L.sync_ev[0], cs));
+  FASTMM_HIP(hipStreamWaitEvent(hs, L.sync_ev[0], 0));
+  FASTMM_HIP(hipStreamWaitEvent(ds, L.sync_ev[0], 0));
+  // Zero padding of the device copies, ahead of the copies on their stream.
+  if (K4 > K) {
+    FASTMM_HIP(hipMemset2DAsync(dA + K, K4 * 4, 0, (K4 - K) * 4, M, hs));
+    FASTMM_HIP(hipMemsetAsync(dB + K * N4, 0, (K4 - K) * N4 * 4, hs));
+  }
+  if (N4 > N) FASTMM_HIP(hipMemset2DAsync(dB + N, N4 * 4, 0, (N4 - N) * 4, K, hs));
+  auto arrive = [&]() {  // event after the copies queued so far
+    hipEvent_t e = next_event();
+    FASTMM_HIP(hipEventRecord(e, hs));
+    return e;
+  };
+  auto a_band = [&](int qr, int qc, const Band& b) {
+    const int64_t rows = qr ? b.bot : b.rows;
+    h2d_block(dA, K4, A, lda, (qr ? m2 : 0) + b.r0, qc ? k2 : 0, rows, qc ? kb_v : k2, hs);
+  };
+  auto b_band = [&](int qr, int qc, const Band& c) {
+    h2d_block(dB, N4, B, ldb, qr ? k2 : 0, (qc ? n2 : 0) + c.r0, qr ? kb_v : k2,
+              qc ? right_valid(c) : c.rows, hs);
+  };
+
+  // ---- inputs, in the order of `items`, queued before the schedules are
+  // built so that the host's work overlaps the first copies
+  std::vector<hipEvent_t> ev_item(items.size());  // after each input item's copy
+  for (size_t k = 0; k < items.size(); ++k) {
+    const Item& it = items[k];
+    if (wino) {
+      if (it.mat == 0) a_band(it.q / 2, it.q % 2, bands[it.band]);
+      else b_band(it.q / 2, it.q % 2, cbands[it.band]);
+    } else if (it.mat == 0) {
+      const Band& b = bands[it.band];
+      h2d_block(dA, K4, A, lda, b.r0, 0, b.rows, K, hs);
+    } else {
+      const Band& c = cbands[it.band];
+      h2d_block(dB, N4, B, ldb, 0, c.r0, K, plain_valid(c), hs);
+    }
+    ev_item[k] = arrive();
+  }
+  FASTMM_HIP(hipEventRecord(L.ev[5], hs));
+
+  // ---- the pieces' schedules and the top-level post-addition nodes
   {
     std::vector<size_t> doff, dbytes;
     for (auto& g : groups) {
@@ -582,7 +650,6 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       build_schedule(groups[i].probs, temps + groups[i].x * temp_stride, groups[i].s);
     }
   }
-
   size_t slot = 0;
   auto next_slot = [&]() {
     if (slot >= nslots) throw Error(kDeviceError, "descriptor slots exhausted");
@@ -617,44 +684,12 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
         vec_post[(size_t)bi * ncband + ci] = post_vec_ok(np);
       }
   }
-  hipStream_t cs = L.stream, hs = L.h2d_stream, ds = L.d2h_stream;
-  hipStream_t xs[2] = {cs, ncs > 1 ? L.aux_stream : cs};
-  int ev_next = 1;
-  auto next_event = [&]() {
-    if (ev_next >= Library::kSyncEvents) throw Error(kDeviceError, "pipeline event pool exhausted");
-    return L.sync_ev[ev_next++];
-  };
-  FASTMM_HIP(hipEventRecord(L.ev[0], cs));
-  FASTMM_HIP(hipEventRecord(L.sync_ev[0], cs));
-  FASTMM_HIP(hipStreamWaitEvent(hs, L.sync_ev[0], 0));
-  FASTMM_HIP(hipStreamWaitEvent(ds, L.sync_ev[0], 0));
-  // Zero padding of the device copies, ahead of the copies on their stream.
-  if (K4 > K) {
-    FASTMM_HIP(hipMemset2DAsync(dA + K, K4 * 4, 0, (K4 - K) * 4, M, hs));
-    FASTMM_HIP(hipMemsetAsync(dB + K * N4, 0, (K4 - K) * N4 * 4, hs));
-  }
-  if (N4 > N) FASTMM_HIP(hipMemset2DAsync(dB + N, N4 * 4, 0, (N4 - N) * 4, K, hs));
   if (slot) FASTMM_HIP(hipMemcpyAsync(ddesc, host, 256 * slot, hipMemcpyHostToDevice, cs));
   if (ncs > 1) {  // the second stream starts after the caller's work and that upload
     hipEvent_t e = next_event();
     FASTMM_HIP(hipEventRecord(e, cs));
     FASTMM_HIP(hipStreamWaitEvent(xs[1], e, 0));
   }
-
-  // ---- inputs
-  auto arrive = [&]() {  // event after the copies queued so far
-    hipEvent_t e = next_event();
-    FASTMM_HIP(hipEventRecord(e, hs));
-    return e;
-  };
-  auto a_band = [&](int qr, int qc, const Band& b) {
-    const int64_t rows = qr ? b.bot : b.rows;
-    h2d_block(dA, K4, A, lda, (qr ? m2 : 0) + b.r0, qc ? k2 : 0, rows, qc ? kb_v : k2, hs);
-  };
-  auto b_band = [&](int qr, int qc, const Band& c) {
-    h2d_block(dB, N4, B, ldb, qr ? k2 : 0, (qc ? n2 : 0) + c.r0, qr ? kb_v : k2,
-              qc ? right_valid(c) : c.rows, hs);
-  };
 
   int launches = 0, nleaf = 0;
   auto run_group = [&](Group& g) {
@@ -673,7 +708,6 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     L.stream = keep;
   };
   auto wait = [&](int x, hipEvent_t e) { FASTMM_HIP(hipStreamWaitEvent(xs[x], e, 0)); };
-  std::vector<hipEvent_t> ev_item(items.size());  // after each input item's copy
   int waited[2] = {-1, -1};  // per compute stream: inputs 0..waited are on the device
   auto wait_item = [&](int x, int k) {
     if (k > waited[x]) {
@@ -683,15 +717,6 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   };
 
   if (wino) {
-    // ---- inputs, in the recipe's order
-    for (size_t k = 0; k < items.size(); ++k) {
-      const Item& it = items[k];
-      if (it.mat == 0) a_band(it.q / 2, it.q % 2, bands[it.band]);
-      else b_band(it.q / 2, it.q % 2, cbands[it.band]);
-      ev_item[k] = arrive();
-    }
-    FASTMM_HIP(hipEventRecord(L.ev[5], hs));
-
     // ---- compute
     unsigned s_done[kMaxBands] = {}, t_done[kMaxBands] = {};  // outputs computed so far, per band
     // Which stream computed each S / T output, and the event after its pass.
@@ -842,20 +867,8 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
       }
     }
   } else {
-    // Plain product: the bands in the order of `items`, each piece C[r, c]
-    // once its two bands are in, each result block sent out once computed.
-    for (size_t k = 0; k < items.size(); ++k) {
-      const Item& it = items[k];
-      if (it.mat == 0) {
-        const Band& b = bands[it.band];
-        h2d_block(dA, K4, A, lda, b.r0, 0, b.rows, K, hs);
-      } else {
-        const Band& c = cbands[it.band];
-        h2d_block(dB, N4, B, ldb, 0, c.r0, K, plain_valid(c), hs);
-      }
-      ev_item[k] = arrive();
-    }
-    FASTMM_HIP(hipEventRecord(L.ev[5], hs));
+    // Plain product: each piece C[r, c] once its two bands are in, each
+    // result block sent out once computed.
     for (size_t gi = 0; gi < order.size(); ++gi) {
       const int x = groups[gi].x;
       const Band& b = bands[order[gi].r];
