@@ -40,12 +40,12 @@ PEAK_HBM_GBS = 8000.0
 # each scaled by its reading for a 1 GiB calibration copy (fetch x2.000,
 # write x1.000).  HBM-resident depth-3 call: one grouped launch of 343 leaves
 # of 2432 x 2432 x 2432 (profiles/leaf_gemm_n19456_d3_device_hbm_traffic.md).
-# Pinned-host depth-3 call: 28 launches of 49 leaves of (1280 | 1152) x 2432
+# Pinned-host depth-3 call: 56 launches of 49 leaves of (640 | 512) x 2432
 # x (1280 | 1152), mean per launch
 # (profiles/leaf_gemm_n19456_d3_pinned_hbm_traffic.md).  Valid for
 # leaf_gemm_kernel<128,128,16,2,2> in those configurations only.
 TRAFFIC_DEVICE_BYTES_PER_LAUNCH = 37626398.4 * 1024 * 2.000 + 7924672.0 * 1024 * 1.000
-TRAFFIC_PINNED_BYTES_PER_LAUNCH = 1481106.4 * 1024 * 2.000 + 287906.9 * 1024 * 1.000
+TRAFFIC_PINNED_BYTES_PER_LAUNCH = 674390.6 * 1024 * 2.000 + 142322.4 * 1024 * 1.000
 
 
 def cpu_model():
@@ -602,6 +602,10 @@ def main():
         "parity": parity,
     }
     print(json.dumps(out), flush=True)
+    # Release the library's streams, workspace and staging while the runtime
+    # is fully up, rather than leaving them to process teardown.
+    torch.cuda.synchronize()
+    fastmm.finalize()
 
 
 if __name__ == "__main__":
