@@ -157,6 +157,17 @@ const std::vector<Recipe>& recipes() {
               {0, 2, 3}, {0, 1, 4}, {0, 2, 7}, {0, 3, 7}, {0, 2, 6}, {0, 3, 4}, {0, 3, 3}, {0, 2, 4},
               {0, 2, 0}, {0, 3, 0}, {0, 1, 0}, {0, 1, 2}, {1, 2, 1}, {0, 1, 1}, {0, 2, 1}, {1, 2, 0},
               {0, 3, 6}, {1, 3, 0}, {1, 1, 0}, {0, 1, 7}, {0, 1, 3}, {0, 1, 6}, {0, 3, 1}, {0, 1, 5}}},
+      {3, 2, {{0, 0, 2}, {1, 0, 1}, {1, 0, 0}, {0, 0, 1}, {0, 2, 1}, {0, 3, 1}, {0, 0, 0}, {1, 1, 1},
+              {1, 3, 1}, {0, 2, 2}, {0, 2, 0}, {0, 3, 0}, {0, 1, 2}, {0, 3, 2}, {1, 3, 0}, {0, 1, 0},
+              {1, 2, 1}, {1, 1, 0}, {1, 2, 0}, {0, 1, 1}}},
+      {5, 2, {{0, 2, 4}, {0, 0, 3}, {1, 0, 0}, {1, 0, 1}, {0, 0, 2}, {0, 0, 0}, {0, 0, 1}, {0, 3, 4},
+              {1, 1, 1}, {0, 0, 4}, {1, 3, 1}, {0, 2, 1}, {0, 2, 2}, {0, 3, 2}, {0, 1, 2}, {0, 3, 1},
+              {1, 2, 1}, {0, 3, 3}, {0, 1, 3}, {1, 1, 0}, {1, 3, 0}, {0, 1, 0}, {0, 2, 3}, {0, 1, 1},
+              {0, 3, 0}, {1, 2, 0}, {0, 2, 0}, {0, 1, 4}}},
+      {4, 3, {{1, 2, 1}, {0, 1, 3}, {1, 2, 2}, {0, 1, 2}, {0, 1, 0}, {0, 0, 2}, {1, 2, 0}, {0, 1, 1},
+              {0, 0, 0}, {1, 0, 1}, {0, 0, 1}, {1, 0, 0}, {1, 1, 2}, {0, 0, 3}, {1, 0, 2}, {0, 2, 3},
+              {1, 3, 2}, {0, 3, 3}, {0, 3, 1}, {0, 2, 1}, {0, 2, 0}, {0, 2, 2}, {1, 3, 0}, {0, 3, 0},
+              {0, 3, 2}, {1, 3, 1}, {1, 1, 0}, {1, 1, 1}}},
       {4, 4, {{1, 2, 0}, {0, 1, 3}, {1, 2, 1}, {1, 2, 3}, {0, 1, 2}, {0, 1, 0}, {0, 1, 1}, {1, 2, 2},
               {0, 0, 1}, {1, 0, 3}, {0, 0, 2}, {1, 0, 2}, {0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {0, 0, 3},
               {1, 0, 1}, {0, 2, 3}, {1, 3, 0}, {0, 3, 3}, {0, 3, 1}, {0, 2, 1}, {1, 1, 2}, {0, 2, 0},
@@ -251,7 +262,8 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     // 4864 block).  With column bands, four row bands where the top rows
     // hold at least two leaf-tile units per band.  FASTMM_PIPE_ROWBANDS and
     // FASTMM_PIPE_COLBANDS choose another layout that has an input order of
-    // its own (2 x 1, 2 x 2, 4 x 2, 6 x 2, 8 x 2, 4 x 4).
+    // its own (2 x 1, 2 x 2, 3 x 2, 4 x 2, 5 x 2, 6 x 2, 8 x 2, 4 x 3,
+    // 4 x 4).
     const int64_t ra = (int64_t)ts.bm << (depth - 1), ca = (int64_t)ts.bn << (depth - 1);
     const bool colb = n2 >= 4096;
     int nrb = colb && m2 / ra >= 8 ? 4 : 2, ncb = colb ? 2 : 1;
