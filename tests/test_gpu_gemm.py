@@ -461,3 +461,28 @@ def test_host_pipeline_two_streams_bitwise(fastmm, monkeypatch, M, K, N, depth):
     rows = synthgen.row_sample(163 + M, M, 8)
     assert checks.sampled_rows_rel(C1.numpy(), A, B, rows) <= TOL_WINOGRAD
     assert checks.freivalds_rel(C1.numpy(), A, B, synthgen.signs_pm1(164 + N, N)) <= TOL_WINOGRAD
+
+
+@pytest.mark.parametrize("rows,cols", [(2, 2), (3, 2), (4, 2), (5, 2), (6, 2), (8, 2), (4, 3), (4, 4)])
+def test_host_pipeline_band_layouts_exact(fastmm, monkeypatch, rows, cols):
+    # Every band layout with an input order of its own (the top quadrants'
+    # rows in `rows` bands, B's columns in `cols` bands): pieces, shared
+    # inner temporaries, banded S / T passes and result blocks must still
+    # give the exact product on certified integers.
+    import torch
+    M, K, N, depth = 4096, 1030, 8200, 2
+    monkeypatch.setenv("FASTMM_PIPE_ROWBANDS", str(rows))
+    monkeypatch.setenv("FASTMM_PIPE_COLBANDS", str(cols))
+    say(f"band layout {rows}x{cols}: {M}x{K}x{N} depth={depth}")
+    A = ints(171 + rows, M, K)
+    B = ints(172 + cols, K, N)
+    Cp = torch.full((M, N), float("nan")).pin_memory()
+    fastmm.gemm(M, N, K, torch.from_numpy(A).pin_memory(), torch.from_numpy(B).pin_memory(), Cp,
+                depth=depth, leaf=1)
+    st = fastmm.get_stats()
+    assert st["depth"] == depth and st["leaf_launches"] == 7 * rows * cols
+    C = Cp.numpy()
+    rows_s = synthgen.row_sample(173, M, 16)
+    assert np.array_equal(C[rows_s].astype(np.float64), classic.gemm_rows(A, B, rows_s))
+    x = synthgen.signs_pm1(174, N)
+    assert np.array_equal(classic.gemv(C, x), classic.gemv(A, classic.gemv(B, x)))
