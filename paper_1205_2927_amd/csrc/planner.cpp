@@ -237,6 +237,7 @@ std::pair<int, int> default_choice(int64_t M, int64_t N, int64_t K) {
 // spread: on held-out shapes it took the three networks' mean regret from
 // 1.4% to 1.1%).
 constexpr double kModelMargin = 1.01;
+constexpr double kBatchMargin = 1.05;
 
 // Mean predicted log2 time of the networks for each candidate.
 std::vector<double> model_predict(Library& L, int64_t M, int64_t N, int64_t K,
@@ -299,8 +300,10 @@ int64_t default_leaf() { return kDefaultLeaf; }
 // single-product depth wherever the product fills the device alone made
 // the batch 6% slower under EXHAUSTIVE and 22% slower under MODEL than the
 // fixed rule).  So the mode's choice is taken among those candidates,
-// against the fixed rule's depth, which stays unless one of them is faster
-// (for MODEL, predicted at least 1% faster).
+// against the fixed rule's depth, which stays unless one of them is at
+// least kBatchMargin faster alone (measured or, for MODEL, predicted): a
+// product's own timing overstates what a Winograd level saves inside the
+// batch, whose one persistent leaf launch keeps the device full anyway.
 int plan_choose_batched(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out) {
   if (mode < FASTMM_PLAN_DEFAULT || mode > FASTMM_PLAN_EXHAUSTIVE)
     throw Error(kInvalidValue, "unknown planner mode");
@@ -329,16 +332,19 @@ int plan_choose_batched(Library& L, int64_t M, int64_t N, int64_t K, int mode, f
       if (best < 0 || pred[i] < pred[best]) best = i;
       if (cand[i].first == def) di = i;
     }
-    if (pred[di] <= pred[best] + std::log2(kModelMargin)) best = di;
+    if (pred[di] <= pred[best] + std::log2(kBatchMargin)) best = di;
   } else {
     fastmm_plan_t ex{};
     plan_choose(L, M, N, K, FASTMM_PLAN_EXHAUSTIVE, &ex);  // fills the timing table
     const auto& t = P.table[std::make_tuple(M, N, K)];
+    int di = -1;
     for (int i = 0; i < (int)cand.size(); ++i) {
       auto f = t.find(cand[i]);
       if (f == t.end()) continue;
+      if (cand[i].first == def) di = i;
       if (best < 0 || f->second < t.at(cand[best])) best = i;
     }
+    if (di >= 0 && best >= 0 && t.at(cand[di]) <= t.at(cand[best]) * kBatchMargin) best = di;
   }
   if (best >= 0 && cand[best].first != def) {
     *out = make_plan(cand[best].first, kTile128x128, -1.0, mode);
