@@ -143,7 +143,7 @@ def batched_context(fastmm, torch, with_planner=True):
         t = time.perf_counter()
         fastmm.gemm_batched(As, Bs, Cs)  # first call: plans (EXHAUSTIVE times every candidate), capture
         first = time.perf_counter() - t
-        med, best = timed(lambda: fastmm.gemm_batched(As, Bs, Cs), 5)
+        med, best = timed(lambda: fastmm.gemm_batched(As, Bs, Cs), 11)
         st = fastmm.get_stats()
         out["modes"][name] = {"ms": 1e3 * med, "ms_min": 1e3 * best, "TFLOPS": flops / med / 1e12,
                               "first_call_s": first, "max_depth": st["depth"], "leaves": st["leaves"],
@@ -153,7 +153,7 @@ def batched_context(fastmm, torch, with_planner=True):
     if with_planner:
         out["model_regret_vs_exhaustive"] = out["modes"]["model"]["ms"] / out["modes"]["exhaustive"]["ms"] - 1
         out["model_gain_vs_default"] = out["modes"]["default"]["ms"] / out["modes"]["model"]["ms"]
-    med, best = timed(lambda: fastmm.gemm_batched(As, Bs, Cs, depth=[0] * len(As)), 5)
+    med, best = timed(lambda: fastmm.gemm_batched(As, Bs, Cs, depth=[0] * len(As)), 11)
     out["plain_batched"] = {"ms": 1e3 * med, "TFLOPS": flops / med / 1e12, "parity_worst_rel": parity()}
 
     def singles():
