@@ -410,7 +410,8 @@ def test_depth_first_fallback_first_call_in_fresh_process(fastmm, tmp_path):
     assert checks.rel_frob(got, classic.gemm(A, B)) <= TOL_WINOGRAD
 
 
-@pytest.mark.parametrize("M,K,N,depth", [(3000, 2000, 8195, 2), (4100, 1030, 8203, 3), (2051, 4097, 9001, 1)])
+@pytest.mark.parametrize("M,K,N,depth", [(3000, 2000, 8195, 2), (4100, 1030, 8203, 3), (2051, 4097, 9001, 1),
+                                         (8195, 1030, 8203, 2), (9001, 515, 8199, 1)])
 def test_host_pipeline_column_bands_odd_exact(fastmm, M, K, N, depth):
     # Host operands wide enough for the pipelined path's column bands of B
     # (B's quadrants at least 4096 wide), with odd extents: clipped right
