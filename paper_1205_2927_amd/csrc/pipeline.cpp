@@ -9,28 +9,29 @@
 // Here the top level of the recursion runs as a sequence of pieces,
 // alternating between two compute streams, while one copy stream brings
 // operand blocks in and a second copy stream sends result blocks back as
-// soon as they are final.  The top
-// quadrants are cut into two row bands (A side) and, where B's quadrants are
-// at least 4096 wide, two column bands (B side): piece (i, r, c) of
-// top-level product i, P_i[r, c] = L_i[r] R_i[:, c],
-// needs only row band r of its left operand and column band c of its right
-// operand, and is itself a Winograd product of depth d - 1.  The pieces of
-// one product and row band (column band) share the inner recursion's
-// A-side (B-side) temporaries, computed by the first of them.
+// soon as they are final.  The top quadrants are cut into row bands (A
+// side; four where the rows hold at least two leaf-tile units per band,
+// else two) and, where B's quadrants are at least 4096 wide, two column
+// bands (B side): piece (i, r, c) of top-level product i,
+// P_i[r, c] = L_i[r] R_i[:, c], needs only row band r of its left operand
+// and column band c of its right operand, and is itself a Winograd product
+// of depth d - 1.  The pieces of one product and row band (column band)
+// share the inner recursion's A-side (B-side) temporaries, computed by the
+// first of them.
 //
 // Input order.  Every product needs a different subset of the eight
 // quadrants (P1: A11 B11; P7: A11 A21 B12 B22; P5: A21 A22 B11 B12; P6: A11
 // A21 A22 B11 B12 B22; P2: A12 B21; P4: A22 and all of B; P3: all of A and
-// B22).  The fixed order of the 16 band blocks (found by simulating the
-// copies and the pieces at n = 19456 and searching over orders) starts
-// with the first bands of B11 and A11 and ends with A12, so that the first
-// piece waits for about a quarter of the data the first whole-band product
-// needed and only P2 and P3 wait for the end of the transfer.  Pieces run
+// B22).  Each band layout has a fixed order of its band blocks (found by
+// simulating the copies and the pieces at n = 19456, searching over orders,
+// and measuring): it starts with bands of B11 and A11 and leaves A12 and
+// B21 for the end, so that the first piece waits for a small part of the
+// data and only P2 and P3 wait for the end of the transfer.  Pieces run
 // greedily in order of estimated readiness.  Pre-additions compute only the
 // S / T outputs of a band whose inputs have arrived (a later pass adds the
 // rest), and each result block C_q[r, c] is formed and sent out as soon as
 // its four products (C11: P1 P2; C12: P1 P6 P5 P3; C21: P1 P6 P7 P4; C22: P1
-// P6 P7 P5) are done, so one block of one quadrant (about 1.5 ms of copy at
+// P6 P7 P5) are done, so one block of one quadrant (under 1 ms of copy at
 // n = 19456) remains after the last piece.
 //
 // A plain product (depth 0) streams A's rows and B's columns in quarters,
