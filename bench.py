@@ -88,9 +88,10 @@ def batched_context(fastmm, torch, with_planner=True):
     DEFAULT (fixed rule), MODEL (the cost model, trained first on the
     exhaustive timings of 160 shapes of seed 4001) and EXHAUSTIVE (every
     candidate of every shape timed) -- against the batched plain product
-    (depth 0) and the same products as 256 single fastmm_gemm calls.  The
-    last result of each mode is checked against the oracle (2 sampled rows
-    and Freivalds' check per problem)."""
+    (depth 0) and the same products as 256 single fastmm_gemm calls; the
+    timed calls of the modes and the plain product alternate.  The result of
+    each mode is checked against the oracle (2 sampled rows and Freivalds'
+    check per problem)."""
     import synthgen
     from oracle import checks
     shapes = [tuple(int(v) for v in x) for x in synthgen.shapes_loguniform(3001, 256, lo=256, hi=6144)]
@@ -138,23 +139,49 @@ def batched_context(fastmm, torch, with_planner=True):
         out["model_training"] = {"shapes": 160, "records": fastmm.planner_records(),
                                  "loss": loss, "seconds": time.perf_counter() - t}
         modes += [("model", fastmm.PLAN_MODEL), ("exhaustive", fastmm.PLAN_EXHAUSTIVE)]
+    # Each mode's first call plans (EXHAUSTIVE times every candidate) and
+    # captures its graph; its result is checked against the oracle.  The
+    # timed calls then go round the modes and the batched plain product in
+    # turn, eleven rounds, so that the clock's drift over the run weighs on
+    # all of them alike.
+    plain_fn = lambda: fastmm.gemm_batched(As, Bs, Cs, depth=[0] * len(As))
     for name, code in modes:
         fastmm.set_plan_mode(code)
         t = time.perf_counter()
-        fastmm.gemm_batched(As, Bs, Cs)  # first call: plans (EXHAUSTIVE times every candidate), capture
+        fastmm.gemm_batched(As, Bs, Cs)
         first = time.perf_counter() - t
-        med, best = timed(lambda: fastmm.gemm_batched(As, Bs, Cs), 11)
+        fastmm.gemm_batched(As, Bs, Cs)
+        torch.cuda.synchronize()
         st = fastmm.get_stats()
-        out["modes"][name] = {"ms": 1e3 * med, "ms_min": 1e3 * best, "TFLOPS": flops / med / 1e12,
-                              "first_call_s": first, "max_depth": st["depth"], "leaves": st["leaves"],
+        out["modes"][name] = {"first_call_s": first, "max_depth": st["depth"], "leaves": st["leaves"],
                               "leaf_launches": st["leaf_launches"], "launches": st["launches"],
                               "graph_replayed": st["graph_replayed"], "parity_worst_rel": parity()}
     fastmm.set_plan_mode(fastmm.PLAN_DEFAULT)
+    plain_fn()
+    plain_fn()
+    torch.cuda.synchronize()
+    out["plain_batched"] = {"parity_worst_rel": parity()}
+    ts = {name: [] for name, _ in modes}
+    ts["plain"] = []
+    for _ in range(11):
+        for name, code in modes + [("plain", None)]:
+            if code is not None:
+                fastmm.set_plan_mode(code)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            (plain_fn if code is None else (lambda: fastmm.gemm_batched(As, Bs, Cs)))()
+            torch.cuda.synchronize()
+            ts[name].append(time.perf_counter() - t)
+    fastmm.set_plan_mode(fastmm.PLAN_DEFAULT)
+    for name, _ in modes:
+        med = float(np.median(ts[name]))
+        out["modes"][name].update({"ms": 1e3 * med, "ms_min": 1e3 * min(ts[name]),
+                                   "TFLOPS": flops / med / 1e12})
+    med = float(np.median(ts["plain"]))
+    out["plain_batched"].update({"ms": 1e3 * med, "TFLOPS": flops / med / 1e12})
     if with_planner:
         out["model_regret_vs_exhaustive"] = out["modes"]["model"]["ms"] / out["modes"]["exhaustive"]["ms"] - 1
         out["model_gain_vs_default"] = out["modes"]["default"]["ms"] / out["modes"]["model"]["ms"]
-    med, best = timed(lambda: fastmm.gemm_batched(As, Bs, Cs, depth=[0] * len(As)), 11)
-    out["plain_batched"] = {"ms": 1e3 * med, "TFLOPS": flops / med / 1e12, "parity_worst_rel": parity()}
 
     def singles():
         for (m, n, k), A, B, C in zip(shapes, As, Bs, Cs):

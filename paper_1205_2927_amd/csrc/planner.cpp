@@ -87,6 +87,10 @@ struct Planner {
   std::map<std::tuple<int64_t, int64_t, int64_t>, std::map<std::pair<int, int>, double>> table;
   bool trained = false;
   std::vector<float> params;  // host copy of the model: kModelNets x kNParams
+  // MODEL's choices per shape (0: a single product, 1: a problem of a batch),
+  // so that a repeated shape costs no inference on the device; cleared
+  // whenever the model changes.
+  std::map<std::tuple<int64_t, int64_t, int64_t, int>, fastmm_plan_t> model_cache;
 };
 
 Planner& planner() {
@@ -206,6 +210,7 @@ ModelDev& model_dev() {
 }
 
 void upload_model(Library& L) {
+  planner().model_cache.clear();
   ModelDev& D = model_dev();
   if (!D.params) FASTMM_HIP(hipMalloc(&D.params, (size_t)kModelNets * kNParams * 4));
   if (!D.buf) FASTMM_HIP(hipMalloc(&D.buf, (size_t)64 * (5 + kModelNets) * 4));
@@ -326,6 +331,12 @@ int plan_choose_batched(Library& L, int64_t M, int64_t N, int64_t K, int mode, f
   if (cand.size() <= 1 || !has_def) return kSuccess;
   int best = -1;
   if (mode == FASTMM_PLAN_MODEL && P.trained) {
+    const auto key = std::make_tuple(M, N, K, 1);
+    const auto hit = P.model_cache.find(key);
+    if (hit != P.model_cache.end()) {
+      *out = hit->second;
+      return kSuccess;
+    }
     const std::vector<double> pred = model_predict(L, M, N, K, cand);
     int di = 0;
     for (int i = 0; i < (int)cand.size(); ++i) {
@@ -349,6 +360,7 @@ int plan_choose_batched(Library& L, int64_t M, int64_t N, int64_t K, int mode, f
   if (best >= 0 && cand[best].first != def) {
     *out = make_plan(cand[best].first, kTile128x128, -1.0, mode);
   }
+  if (mode == FASTMM_PLAN_MODEL && P.trained) P.model_cache[std::make_tuple(M, N, K, 1)] = *out;
   return kSuccess;
 }
 
@@ -368,7 +380,10 @@ int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_pl
   ensure_init(L);
   Planner& P = planner();
   if (mode == FASTMM_PLAN_MODEL && P.trained) {
-    *out = plan_model(L, M, N, K);
+    const auto key = std::make_tuple(M, N, K, 0);
+    auto it = P.model_cache.find(key);
+    if (it == P.model_cache.end()) it = P.model_cache.emplace(key, plan_model(L, M, N, K)).first;
+    *out = it->second;
     return kSuccess;
   }
   auto key = std::make_tuple(M, N, K, (int)FASTMM_PLAN_EXHAUSTIVE);
