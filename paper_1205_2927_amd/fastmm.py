@@ -231,6 +231,41 @@ def gemm_batched(As, Bs, Cs, depth=None, leaf=None, check=True):
     return rc
 
 
+class Batch:
+    """fastmm_gemm_batched over fixed lists of 2-D tensors, its argument
+    arrays built once: each call passes them again as they are (for
+    repeated products on the same buffers, e.g. a serving loop; building
+    the arrays for 256 problems costs about a millisecond of Python per
+    call).  The tensors are kept alive by the object."""
+
+    def __init__(self, As, Bs, Cs, depth=None, leaf=None):
+        n = len(As)
+        I64 = ctypes.c_int64 * n
+        VP = ctypes.c_void_p * n
+        self._keep = (list(As), list(Bs), list(Cs))
+        self._n = n
+        self._M = I64(*[a.shape[0] for a in As])
+        self._K = I64(*[a.shape[1] for a in As])
+        self._N = I64(*[b.shape[1] for b in Bs])
+        self._lda = I64(*[_ld(a, None) for a in As])
+        self._ldb = I64(*[_ld(b, None) for b in Bs])
+        self._ldc = I64(*[_ld(c, None) for c in Cs])
+        self._pa = VP(*[_ptr(a) for a in As])
+        self._pb = VP(*[_ptr(b) for b in Bs])
+        self._pc = VP(*[_ptr(c) for c in Cs])
+        self._dep = (ctypes.c_int * n)(*depth) if depth is not None else None
+        self._lf = I64(*leaf) if leaf is not None else None
+        self._depp = ctypes.cast(self._dep, ctypes.c_void_p) if self._dep is not None else None
+        self._lfp = ctypes.cast(self._lf, ctypes.c_void_p) if self._lf is not None else None
+
+    def __call__(self, check=True):
+        rc = load().fastmm_gemm_batched(self._n, self._M, self._N, self._K, self._pa, self._lda,
+                                        self._pb, self._ldb, self._pc, self._ldc, self._depp, self._lfp)
+        if check:
+            _check(rc)
+        return rc
+
+
 def gemm_batched_raw(M, N, K, A, lda, B, ldb, C, ldc, depth=None, leaf=None) -> int:
     """fastmm_gemm_batched on plain lists of extents, addresses and leading
     dimensions; returns the status without raising (for error-path tests)."""

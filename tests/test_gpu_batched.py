@@ -168,3 +168,50 @@ def test_batched_loguniform_shapes_planner(fastmm):
     for i, (m, n, k) in enumerate(shapes):
         ref = classic.gemm(host(As[i]), host(Bs[i]))
         assert checks.rel_frob(host(Cs[i]), ref) < 1e-4, i
+
+
+def test_batched_exact_repeat_new_data_and_interleaved_call(fastmm):
+    # A call that repeats the last one (same problems, pointers, plans)
+    # replays its graph without planning or building again; the descriptors
+    # still go to the device on every call, so new data in the same buffers
+    # and another product run in between (which reuses that part of the
+    # workspace) must not leave a stale result.
+    import torch
+    shapes = [(384, 320, 448, 1), (1024, 512, 768, 2), (256, 768, 640, 0), (768, 768, 768, 2)]
+    As, Bs = _make(shapes, 9100)
+    Cs = [empty_dev(m, n) for (m, k, n, d) in shapes]
+    depth = [d for (_, _, _, d) in shapes]
+    leaf = [64] * len(shapes)
+    fastmm.gemm_batched(As, Bs, Cs, depth=depth, leaf=leaf)
+    first = fastmm.get_stats()
+    fastmm.gemm_batched(As, Bs, Cs, depth=depth, leaf=leaf)
+    st = fastmm.get_stats()
+    assert st["graph_replayed"] == 1
+    assert (st["leaves"], st["launches"], st["depth"]) == (first["leaves"], first["launches"], first["depth"])
+    for i, (m, k, n, d) in enumerate(shapes):
+        As[i].copy_(dev(uniform(9200 + 2 * i, m, k)))
+        Bs[i].copy_(dev(uniform(9201 + 2 * i, k, n)))
+    say("exact repeat after new data and an interleaved single product")
+    x, y = dev(uniform(9300, 512, 512)), dev(uniform(9301, 512, 512))
+    z = empty_dev(512, 512)
+    fastmm.gemm(512, 512, 512, x, y, z, depth=2, leaf=64)
+    fastmm.gemm_batched(As, Bs, Cs, depth=depth, leaf=leaf)
+    assert fastmm.get_stats()["graph_replayed"] == 1
+    for i, (m, k, n, d) in enumerate(shapes):
+        assert checks.rel_frob(host(Cs[i]), classic.gemm(host(As[i]), host(Bs[i]))) <= TOL, i
+    assert checks.rel_frob(host(z), classic.gemm(host(x), host(y))) <= TOL
+
+
+def test_batch_object_matches_gemm_batched(fastmm):
+    # fastmm.Batch builds the argument arrays once; each call must give
+    # what fastmm.gemm_batched gives on the same lists, bit for bit.
+    As, Bs = _make(SHAPES, 9400)
+    C1 = [empty_dev(m, n) for (m, k, n, d) in SHAPES]
+    C2 = [empty_dev(m, n) for (m, k, n, d) in SHAPES]
+    depth = [d for (_, _, _, d) in SHAPES]
+    fastmm.gemm_batched(As, Bs, C1, depth=depth, leaf=[1] * len(SHAPES))
+    run = fastmm.Batch(As, Bs, C2, depth=depth, leaf=[1] * len(SHAPES))
+    for _ in range(3):
+        run()
+        for a, b in zip(C1, C2):
+            assert np.array_equal(host(a), host(b))
