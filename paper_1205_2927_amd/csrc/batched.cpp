@@ -40,23 +40,26 @@ GraphCache& graphs() {
   return G;
 }
 
-// A call that repeats the last one -- the same problems (extents, operand
-// pointers, leading dimensions, requested depths and leaves), the same
-// planner mode and settings, the same workspace -- replays the graph that
-// call used without classifying, planning or building anything again.
-// Only the descriptor arrays are copied to the device again, since another
-// call may have used that part of the workspace in between.
-struct LastCall {
-  std::vector<int64_t> key;  // empty: nothing to repeat
-  std::string graph;         // its GraphCache entry
-  std::vector<char> desc;    // host image of its descriptor arrays
+// A call that repeats one of the last few -- the same problems (extents,
+// operand pointers, leading dimensions, requested depths and leaves), the
+// same planner mode, planner state and settings, the same workspace --
+// replays the graph that call used without classifying, planning or
+// building anything again.  Only the descriptor arrays are copied to the
+// device again, since another call may have used that part of the
+// workspace in between.
+struct RecentCall {
+  std::vector<int64_t> key;
+  std::string graph;       // its GraphCache entry
+  std::vector<char> desc;  // host image of its descriptor arrays
   char* desc_dev = nullptr;
   fastmm_stats_t stats{};
 };
 
-LastCall& last_call() {
-  static LastCall F;
-  return F;
+constexpr size_t kRecentCalls = 8;
+
+std::vector<RecentCall>& recent_calls() {  // most recent last
+  static std::vector<RecentCall> R;
+  return R;
 }
 
 std::vector<int64_t> call_key(const Library& L, int count, const int64_t* M, const int64_t* N,
@@ -73,6 +76,7 @@ std::vector<int64_t> call_key(const Library& L, int count, const int64_t* M, con
   k.push_back(L.plan_mode);
   k.push_back((int64_t)L.arena_generation);
   k.push_back(reinterpret_cast<int64_t>(L.stream));
+  k.push_back((int64_t)planner_epoch());
   k.push_back(env("FASTMM_PERSISTENT"));
   k.push_back(env("FASTMM_GRAPH"));
   k.push_back(env("FASTMM_TREE_ADDS"));
@@ -168,13 +172,16 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
   if (count == 0) return;
   if (!M || !N || !K || !A || !lda || !B || !ldb || !C || !ldc)
     throw Error(kInvalidValue, "NULL array argument");
-  std::vector<int64_t> key;
   if (L.initialised) {
-    key = call_key(L, count, M, N, K, A, lda, B, ldb, C, ldc, depth, leaf);
-    LastCall& F = last_call();
+    const std::vector<int64_t> key = call_key(L, count, M, N, K, A, lda, B, ldb, C, ldc, depth, leaf);
+    std::vector<RecentCall>& R = recent_calls();
     GraphCache& G = graphs();
-    const auto it = F.key == key ? G.execs.find(F.graph) : G.execs.end();
+    auto hit = R.end();
+    for (auto r = R.begin(); r != R.end(); ++r)
+      if (r->key == key) hit = r;
+    const auto it = hit != R.end() ? G.execs.find(hit->graph) : G.execs.end();
     if (it != G.execs.end()) {
+      const RecentCall& F = *hit;
       char* host = ensure_pinned(L, F.desc.size());
       std::memcpy(host, F.desc.data(), F.desc.size());
       FASTMM_HIP(hipMemcpyAsync(F.desc_dev, host, F.desc.size(), hipMemcpyHostToDevice, L.stream));
@@ -194,7 +201,7 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
       L.stats = st;
       return;
     }
-    F.key.clear();
+    if (hit != R.end()) R.erase(hit);  // its graph is gone
   }
   for (int i = 0; i < count; ++i) {
     try {
@@ -352,13 +359,21 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
   for (const auto& p : probs) outside = outside || p.K == 0;
   for (const auto& g : stg) outside = outside || g.a || g.b;
   if (on_dev == 1 && !work.empty() && !outside && !(ge && ge[0] == '0')) {
-    LastCall& F = last_call();
+    RecentCall F;
     F.key = call_key(L, count, M, N, K, A, lda, B, ldb, C, ldc, depth, leaf);
     F.graph = signature(s);
     const size_t n = schedule_desc_bytes(s);
     F.desc.assign(desc_host, desc_host + n);
     F.desc_dev = ws + stage_bytes + temp_bytes;
     F.stats = st;
+    std::vector<RecentCall>& R = recent_calls();
+    for (auto r = R.begin(); r != R.end(); ++r)
+      if (r->key == F.key) {
+        R.erase(r);
+        break;
+      }
+    if (R.size() >= kRecentCalls) R.erase(R.begin());
+    R.push_back(std::move(F));
   }
 }
 
@@ -367,7 +382,7 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
 void destroy_graphs() {
   for (auto& kv : graphs().execs) (void)hipGraphExecDestroy(kv.second.exec);
   graphs().execs.clear();
-  last_call().key.clear();
+  recent_calls().clear();
 }
 
 int64_t graph_captures() { return graphs().captures; }

@@ -255,6 +255,9 @@ int plan_choose(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_pl
 // The plan of one problem of a batched call (128x128 tiles; see planner.cpp).
 int plan_choose_batched(Library& L, int64_t M, int64_t N, int64_t K, int mode, fastmm_plan_t* out);
 int64_t default_leaf();
+// Changes whenever the planner's timings or model change (so plans taken
+// earlier may no longer be the planner's choice).
+uint64_t planner_epoch();
 
 void set_error(const std::string& msg);
 

@@ -91,6 +91,7 @@ struct Planner {
   // so that a repeated shape costs no inference on the device; cleared
   // whenever the model changes.
   std::map<std::tuple<int64_t, int64_t, int64_t, int>, fastmm_plan_t> model_cache;
+  uint64_t epoch = 0;  // bumped whenever the timings or the model change
 };
 
 Planner& planner() {
@@ -184,6 +185,7 @@ fastmm_plan_t tune_exhaustive(Library& L, int64_t M, int64_t N, int64_t K) {
         ms = std::min(ms, (double)x);
       }
       P.db.push_back({M, N, K, d, t, ms});
+      ++P.epoch;
       P.table[std::make_tuple(M, N, K)][{d, t}] = ms;
       if (ms < best_ms) {  // strict: earlier (smaller depth, tile) wins ties
         best_ms = ms;
@@ -211,6 +213,7 @@ ModelDev& model_dev() {
 
 void upload_model(Library& L) {
   planner().model_cache.clear();
+  ++planner().epoch;
   ModelDev& D = model_dev();
   if (!D.params) FASTMM_HIP(hipMalloc(&D.params, (size_t)kModelNets * kNParams * 4));
   if (!D.buf) FASTMM_HIP(hipMalloc(&D.buf, (size_t)64 * (5 + kModelNets) * 4));
@@ -292,6 +295,8 @@ int64_t leaf_tiles_128(int64_t M, int64_t N, int d) {
 }  // namespace
 
 int64_t default_leaf() { return kDefaultLeaf; }
+
+uint64_t planner_epoch() { return planner().epoch; }
 
 // A problem of a batch: its leaves join one launch with every other
 // problem's, which fills the device, so the tile is always 128x128 (the
@@ -593,7 +598,10 @@ int fastmm_planner_load(const char* db_path, const char* model_path) {
   Library& L = lib();
   std::lock_guard<std::mutex> g(L.mu);
   return run_guarded([&] {
-    if (db_path) load_db(db_path);
+    if (db_path) {
+      load_db(db_path);
+      ++planner().epoch;
+    }
     if (model_path) {
       FILE* f = std::fopen(model_path, "rb");
       if (!f) throw Error(kInvalidValue, std::string("cannot read ") + model_path);
