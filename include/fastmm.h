@@ -202,12 +202,17 @@ int fastmm_rmul(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, co
  * (the batch's shared leaf launch fills the device): DEFAULT's fixed rule,
  * or, in the MODEL and EXHAUSTIVE modes, the fastest predicted or timed
  * depth among those whose leaf launch would fill the device on its own, when
- * it beats the fixed rule's; depth != NULL: 128x128 tiles and leaf[i] (NULL:
- * the default cutoff 1280).  Every level of
+ * it is at least 5% faster than the fixed rule's; depth != NULL: 128x128
+ * tiles and leaf[i] (NULL: the default cutoff 1280).  Every level of
  * every problem is one grouped launch (or one per group of up to three levels,
  * the additions of levels that halve exactly); the launch sequence is captured once
- * per set of shapes and plans into a HIP graph and replayed.  All problems are
- * validated first: on error nothing is written. */
+ * per set of shapes and plans into a HIP graph and replayed.  A call that
+ * repeats one of the last eight device-operand calls exactly (problems,
+ * pointers, leading dimensions, depth and leaf arrays, planner mode and
+ * state, stream) replays its graph without validating, planning or
+ * building again; its descriptors are uploaded again, so the operands'
+ * contents may change between calls, not their addresses or extents.  All
+ * problems are validated first: on error nothing is written. */
 int fastmm_gemm_batched(int count, const int64_t* M, const int64_t* N, const int64_t* K,
                         const float* const* A, const int64_t* lda, const float* const* B,
                         const int64_t* ldb, float* const* C, const int64_t* ldc, const int* depth,
