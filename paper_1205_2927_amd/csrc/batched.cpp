@@ -172,7 +172,11 @@ void do_batched(Library& L, int count, const int64_t* M, const int64_t* N, const
   if (count == 0) return;
   if (!M || !N || !K || !A || !lda || !B || !ldb || !C || !ldc)
     throw Error(kInvalidValue, "NULL array argument");
-  if (L.initialised) {
+  // An exact repeat replays its graph at once, unless the workspace
+  // controls (a cap, NaN-poisoning) are set: those act on every call.
+  const char* poison = std::getenv("FASTMM_POISON");
+  const bool ws_controls = std::getenv("FASTMM_WORKSPACE_LIMIT") || (poison && poison[0] == '1');
+  if (L.initialised && !ws_controls) {
     const std::vector<int64_t> key = call_key(L, count, M, N, K, A, lda, B, ldb, C, ldc, depth, leaf);
     std::vector<RecentCall>& R = recent_calls();
     GraphCache& G = graphs();

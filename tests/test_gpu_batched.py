@@ -202,6 +202,35 @@ def test_batched_exact_repeat_new_data_and_interleaved_call(fastmm):
     assert checks.rel_frob(host(z), classic.gemm(host(x), host(y))) <= TOL
 
 
+def test_batched_exact_repeat_honours_workspace_controls(fastmm, monkeypatch):
+    # An exact repeat skips planning and building, but not the workspace
+    # controls: a cap set between two identical calls must still fail the
+    # second with OUT_OF_MEMORY, and a NaN-poisoned workspace must still give
+    # the oracle's result.
+    shapes = [(384, 320, 448, 1), (1024, 512, 768, 2), (768, 768, 768, 2)]
+    As, Bs = _make(shapes, 9500)
+    Cs = [empty_dev(m, n) for (m, k, n, d) in shapes]
+    run = fastmm.Batch(As, Bs, Cs, depth=[d for (*_, d) in shapes], leaf=[64] * len(shapes))
+    run()
+    run()
+    assert fastmm.get_stats()["graph_replayed"] == 1
+    say("exact repeat under FASTMM_WORKSPACE_LIMIT=4096")
+    monkeypatch.setenv("FASTMM_WORKSPACE_LIMIT", "4096")
+    assert run(check=False) == fastmm.ERROR_OUT_OF_MEMORY
+    assert "FASTMM_WORKSPACE_LIMIT" in fastmm.last_error()
+    monkeypatch.delenv("FASTMM_WORKSPACE_LIMIT")
+    say("exact repeat under FASTMM_POISON=1")
+    monkeypatch.setenv("FASTMM_POISON", "1")
+    for C in Cs:
+        C.fill_(float("nan"))
+    run()
+    monkeypatch.delenv("FASTMM_POISON")
+    for i, (m, k, n, d) in enumerate(shapes):
+        assert checks.rel_frob(host(Cs[i]), classic.gemm(host(As[i]), host(Bs[i]))) <= TOL, i
+    run()
+    assert fastmm.get_stats()["graph_replayed"] == 1
+
+
 def test_batch_object_matches_gemm_batched(fastmm):
     # fastmm.Batch builds the argument arrays once; each call must give
     # what fastmm.gemm_batched gives on the same lists, bit for bit.
