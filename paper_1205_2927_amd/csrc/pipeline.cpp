@@ -34,9 +34,9 @@
 // P6 P7 P5) are done, so one block of one quadrant (under 1 ms of copy at
 // n = 19456) remains after the last piece.
 //
-// A plain product (depth 0) streams A's rows and B's columns in quarters,
-// alternately, and computes each block C[r, c] as a piece once its two
-// bands are in.
+// A plain product (depth 0) streams A's rows and B's columns in fifths
+// (quarters for smaller extents), alternately, and computes each block
+// C[r, c] as a piece once its two bands are in.
 //
 #include <hip/hip_runtime.h>
 
@@ -201,7 +201,7 @@ size_t pipelined_need(int64_t M, int64_t N, int64_t K, int depth, int tile) {
   const std::string key = std::to_string(M) + ',' + std::to_string(N) + ',' + std::to_string(K) + ',' +
                           std::to_string(depth) + ',' + std::to_string(tile) + ',' +
                           env("FASTMM_PIPE_ROWBANDS") + ',' + env("FASTMM_PIPE_COLBANDS") + ',' +
-                          env("FASTMM_PIPE_STREAMS");
+                          env("FASTMM_PIPE_STREAMS") + ',' + env("FASTMM_PIPE_PLAINBANDS");
   static std::map<std::string, size_t> cache;  // calls are serialised by the library lock
   const auto it = cache.find(key);
   if (it != cache.end()) return it->second;
@@ -253,7 +253,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   // ---- bands.  Winograd: row bands of the top quadrants' rows (m2) and
   // column bands of their columns (n2); a band of the bottom (right)
   // quadrants keeps only its valid rows (columns).  Plain product: A's rows
-  // and B's columns in quarters.
+  // and B's columns in fifths or quarters.
   std::vector<Band> bands, cbands;
   if (wino) {
     // Column bands only where B's quadrants are wide: for narrow ones (one
@@ -278,20 +278,27 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     bands = make_bands(m2, mb, nrb, ra);
     cbands = make_bands(n2, nb, ncb, ca);
   } else {
-    // Quarters of M and of the padded width N4, rounded to whole tiles where
-    // the extent allows (at most 6 bands each); column bands start at
-    // multiples of 4, so that B's and C's rows in a band stay 16-byte
-    // aligned.
-    auto quarters = [](int64_t x, int64_t t, int64_t a) {
+    // Fifths of M and of the padded width N4 where both hold at least 10240
+    // (the first piece starts sooner: 123 against 129 ms at n = 19456, 71.7
+    // against 73.4 ms at 19456 x 12288 x 16384), else quarters (narrower
+    // bands lose more to small pieces and short copy rows than they gain:
+    // 28.3 ms in quarters, 31.4 in fifths for 9728 x 4864 x 19456);
+    // FASTMM_PIPE_PLAINBANDS: 1 to 8 parts instead.  Parts are rounded up
+    // to whole tiles where the extent allows, so that there are at most that
+    // many bands; column bands start at multiples of 4, so that B's and C's
+    // rows in a band stay 16-byte aligned.
+    int np = std::min(M, N4) >= 10240 ? 5 : 4;
+    if (const char* e = std::getenv("FASTMM_PIPE_PLAINBANDS")) np = std::min(8, std::max(1, std::atoi(e)));
+    auto parts = [np](int64_t x, int64_t t, int64_t a) {
       std::vector<Band> v;
-      int64_t q = (x + 3) / 4;
-      if (q >= t) q = (q + t / 2) / t * t;
+      int64_t q = (x + np - 1) / np;
+      if (q >= t) q = (q + t - 1) / t * t;
       q = (q + a - 1) / a * a;
       for (int64_t r0 = 0; r0 < x; r0 += q) v.push_back({r0, std::min(q, x - r0), 0});
       return v;
     };
-    bands = quarters(M, ts.bm, 1);
-    cbands = quarters(N4, ts.bn, 4);
+    bands = parts(M, ts.bm, 1);
+    cbands = parts(N4, ts.bn, 4);
   }
   const int nband = (int)bands.size(), ncband = (int)cbands.size();
   // Valid host columns of a column band of B (plain product) or of the right

@@ -487,3 +487,35 @@ def test_host_pipeline_band_layouts_exact(fastmm, monkeypatch, rows, cols):
     assert np.array_equal(C[rows_s].astype(np.float64), classic.gemm_rows(A, B, rows_s))
     x = synthgen.signs_pm1(174, N)
     assert np.array_equal(classic.gemv(C, x), classic.gemv(A, classic.gemv(B, x)))
+
+
+@pytest.mark.parametrize("M,K,N,parts", [(10241, 515, 10243, None), (10240, 512, 10752, None),
+                                         (1000, 300, 1003, "1"), (1000, 300, 1003, "3"),
+                                         (1000, 300, 1003, "5"), (1000, 300, 1003, "8"),
+                                         (9001, 257, 10240, None)])
+def test_host_plain_bands_bitwise(fastmm, monkeypatch, M, K, N, parts):
+    # The plain product from host memory streams A's rows and B's columns in
+    # bands (fifths where both extents hold at least 10240, else quarters, or
+    # FASTMM_PIPE_PLAINBANDS parts) and computes each block C[r, c] as a
+    # piece: every element is still the device-resident product's, bit for
+    # bit, whatever the bands.
+    import torch
+    if parts is None:
+        monkeypatch.delenv("FASTMM_PIPE_PLAINBANDS", raising=False)
+    else:
+        monkeypatch.setenv("FASTMM_PIPE_PLAINBANDS", parts)
+    say(f"plain bands {M}x{K}x{N} parts={parts}")
+    A = uniform(181 + M, M, K)
+    B = uniform(182 + N, K, N)
+    Cd = empty_dev(M, N)
+    fastmm.gemm(M, N, K, dev(A), dev(B), Cd, depth=0, leaf=1)
+    Cp = torch.full((M, N), float("nan")).pin_memory()
+    fastmm.gemm(M, N, K, torch.from_numpy(A).pin_memory(), torch.from_numpy(B).pin_memory(), Cp,
+                depth=0, leaf=1)
+    st = fastmm.get_stats()
+    assert st["depth"] == 0
+    if parts is None:  # fifths of both extents, else quarters: one leaf launch per piece
+        assert st["leaf_launches"] == (25 if min(M, N) >= 10240 else 16)
+    assert np.array_equal(Cp.numpy(), host(Cd))
+    rows = synthgen.row_sample(183, M, 8)
+    assert checks.sampled_rows_rel(Cp.numpy(), A, B, rows) <= 2e-6
