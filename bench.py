@@ -521,6 +521,23 @@ def main():
                    "depth": fastmm.get_stats()["depth"], "leaf": 3008, "operands": "HBM"}
         log(f"bench: classic recursion {classic}")
 
+    # Context: torch.matmul in FP32 (hipBLASLt, TF32 off) on the same
+    # operands in HBM -- the vendor library's plain product.
+    torch_mm = None
+    if dA is not None and not args.no_device_context:
+        prev = torch.backends.cuda.matmul.allow_tf32
+        torch.backends.cuda.matmul.allow_tf32 = False
+
+        def mm():
+            torch.matmul(dA, dB, out=dC)
+            torch.cuda.synchronize()
+
+        tot, ts = time_calls(mm, 3, 1)
+        torch.backends.cuda.matmul.allow_tf32 = prev
+        torch_mm = {"ms": stats_ms(ts), "effective_GFLOPS": flops / min(ts) / 1e9,
+                    "library": "hipBLASLt via torch.matmul", "tf32": False}
+        log(f"bench: torch.matmul FP32 {torch_mm}")
+
     # Context: the split-precision leaf forms (never the FP32 headline): split
     # BF16 (tile 8) and scaled split FP16 (tile 9) leaves, plain and at depth
     # 2 (their workload's depth), operands in HBM; sampled-row error against
@@ -628,7 +645,7 @@ def main():
         "plain_sgemm": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms_per_step) if plain else None,
         "depth_probe_ms": {str(k): 1e3 * v for k, v in probe.items()},
-        "phases": phases, "hbm_resident": hbm, "classic_recursion": classic,
+        "phases": phases, "hbm_resident": hbm, "classic_recursion": classic, "torch_matmul_fp32": torch_mm,
         "precision_forms": precision, "batched": batched, "shards": shards, "rectangular": rect,
         "parity": parity,
     }
