@@ -26,10 +26,13 @@
  *     between the library stream and a second compute stream of the
  *     library's (FASTMM_PIPE_STREAMS=1: the library stream alone), while two
  *     copy streams move operand blocks in and result blocks out (set
- *     FASTMM_PIPELINE=0 to copy everything first instead); the result is bit
- *     for bit the same either way.  The other streams start after the work
- *     queued on the library stream before the call, and the call returns
- *     once all of them have drained.
+ *     FASTMM_PIPELINE=0 to copy everything first instead).  One or two
+ *     compute streams give bit for bit the same result; the pipelined
+ *     Winograd product splits its inner recursion by bands and so differs
+ *     from the copy-first (and device-resident) one in the last bits, while
+ *     a plain product is bit for bit the same on every path.  The other
+ *     streams start after the work queued on the library stream before the
+ *     call, and the call returns once all of them have drained.
  *   - The caller owns A, B and C; the library never keeps them.  The library
  *     owns its workspace (device memory for the recursion's temporaries and
  *     for staging host operands), which grows on demand and is released by
