@@ -213,7 +213,8 @@ int fastmm_rmul(int64_t M, int64_t N, int64_t K, const float* A, int64_t lda, co
  * repeats one of the last eight device-operand calls exactly (problems,
  * pointers, leading dimensions, depth and leaf arrays, planner mode and
  * state, stream) replays its graph without validating, planning or
- * building again; its descriptors are uploaded again, so the operands'
+ * building again (unless FASTMM_WORKSPACE_LIMIT or FASTMM_POISON=1 is set:
+ * those act on every call); its descriptors are uploaded again, so the operands'
  * contents may change between calls, not their addresses or extents.  All
  * problems are validated first: on error nothing is written. */
 int fastmm_gemm_batched(int count, const int64_t* M, const int64_t* N, const int64_t* K,
