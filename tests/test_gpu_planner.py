@@ -76,7 +76,7 @@ def test_default_rule(fastmm):
 
 def test_exhaustive_model_regret_and_gain(fastmm, trained_planner, tmp_path):
     # The cost model is trained (conftest) on the exhaustive timings of 160
-    # shapes of seed 4001; it is judged on 48 held-out shapes of seed 3001
+    # shapes of seed 4001; it is evaluated on 48 held-out shapes of seed 3001
     # against exhaustive timing of every candidate: its mean regret must not
     # exceed the fixed rule's, and its choices must be at least as fast as
     # the fixed rule's (geometric mean over the shapes).
