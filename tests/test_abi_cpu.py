@@ -11,7 +11,8 @@ HEADER = os.path.join(ROOT, "include", "fastmm.h")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    with open(HEADER) as f:
+        text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(fastmm_[a-z_]+)\s*\(", text)))
 
@@ -52,7 +53,8 @@ def test_struct_layouts_match_header():
 
 def test_oracle_is_not_linked_by_the_library():
     so = os.path.join(ROOT, "paper_1205_2927_amd", "libfastmm.so")
-    data = open(so, "rb").read()
+    with open(so, "rb") as f:
+        data = f.read()
     assert b"liboracle" not in data and b"ref_gemm" not in data
     pkg = os.path.join(ROOT, "paper_1205_2927_amd")
     for dirpath, _, files in os.walk(pkg):

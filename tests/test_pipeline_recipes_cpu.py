@@ -10,7 +10,8 @@ CSRC = os.path.join(os.path.dirname(__file__), "..", "paper_1205_2927_amd", "csr
 
 
 def _recipes():
-    src = open(CSRC).read()
+    with open(CSRC) as f:
+        src = f.read()
     body = src[src.index("const std::vector<Recipe>& recipes()"):src.index("const Recipe* find_recipe")]
     out = {}
     for m in re.finditer(r"\{(\d+),\s*(\d+),\s*\{((?:\s*\{\d+,\s*\d+,\s*\d+\},?)+)\s*\}\}", body):
