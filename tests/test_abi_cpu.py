@@ -60,5 +60,6 @@ def test_oracle_is_not_linked_by_the_library():
     for dirpath, _, files in os.walk(pkg):
         for f in files:
             if f.endswith((".py", ".cpp", ".hip", ".h")):
-                src = open(os.path.join(dirpath, f)).read()
+                with open(os.path.join(dirpath, f)) as fh:
+                    src = fh.read()
                 assert "import oracle" not in src and "from oracle" not in src, f
