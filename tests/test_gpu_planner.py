@@ -96,7 +96,8 @@ def test_exhaustive_model_regret_and_gain(fastmm, trained_planner, tmp_path):
         pd = fastmm.plan(M, N, K, fastmm.PLAN_DEFAULT)
         assert pm.source == fastmm.PLAN_MODEL
         fastmm.planner_save(str(db), None)
-        recs = [r for r in json.load(open(db))["records"] if (r["M"], r["N"], r["K"]) == (M, N, K)]
+        with open(db) as f:
+            recs = [r for r in json.load(f)["records"] if (r["M"], r["N"], r["K"]) == (M, N, K)]
         table = {(r["depth"], r["tile"]): r["ms"] for r in recs}
         t_best = table[(best.depth, best.tile)]
         t_model = table[(pm.depth, pm.tile)]

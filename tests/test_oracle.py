@@ -101,7 +101,8 @@ def test_quadrant_extents_equation_1(r, c):
 # ---------------------------------------------------------------- Winograd
 
 def test_winograd_hand_worked_2x2():
-    g = json.load(open(os.path.join(GOLDEN, "winograd_2x2_by_hand.json")))
+    with open(os.path.join(GOLDEN, "winograd_2x2_by_hand.json")) as f:
+        g = json.load(f)
     A = np.array(g["A"], dtype=np.int64)
     B = np.array(g["B"], dtype=np.int64)
     A11, A12, A21, A22 = W.quadrants(A)
