@@ -248,6 +248,32 @@ def sweep(fastmm, torch, sizes):
         del A, B, C
 
 
+def sweep_pinned(fastmm, torch, sizes):
+    """n-sweep of the paper's own measurement: A, B, C in pinned host
+    memory, the transfers inside the wall-clock (Section 4), one JSON line
+    per n: the plain MFMA SGEMM (depth 0) and Winograd at the fixed rule's
+    depth, both through the pipelined host path, best of 3 calls, and the
+    depth an automatic call with host operands takes."""
+    nmax = max(sizes)
+    buf = [torch.empty(nmax * nmax, dtype=torch.float32, pin_memory=True) for _ in range(3)]
+    buf[0].uniform_(-1, 1)
+    buf[1].uniform_(-1, 1)
+    for n in sizes:
+        A, B, C = (x[:n * n].view(n, n) for x in buf)
+        flops = 2.0 * n ** 3
+        row = {"sweep_pinned_n": n}
+        pl = fastmm.plan(n, n, n, fastmm.PLAN_DEFAULT)
+        for name, d in (("plain", 0), ("winograd", pl.depth)):
+            tot, ts = time_calls(lambda: fastmm.gemm(n, n, n, A, B, C, depth=d, leaf=pl.leaf), 3, 1)
+            row[name + "_ms"] = 1e3 * min(ts)
+            row[name + "_GFLOPS"] = flops / min(ts) / 1e9
+            row[name + "_depth"] = fastmm.get_stats()["depth"]
+        row["speedup"] = row["plain_ms"] / row["winograd_ms"]
+        fastmm.gemm(n, n, n, A, B, C, depth=fastmm.AUTO)
+        row["auto_depth"] = fastmm.get_stats()["depth"]
+        print(json.dumps(row), flush=True)
+
+
 def precision_config(fastmm, torch):
     """The precision forms' own workload: n = 8192 and 16384, depth 2,
     inputs uniform[-1, 1] and log-uniform magnitudes 2^-8..2^8 with random
@@ -318,6 +344,9 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the headline: n-sweep of plain, Winograd and the classic "
                          "recursion, one JSON line per n")
+    ap.add_argument("--sweep-pinned", action="store_true",
+                    help="instead of the headline: n-sweep of plain and Winograd with A, B, C in "
+                         "pinned host memory (transfers timed), one JSON line per n")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the sharded "
@@ -340,6 +369,9 @@ def main():
     if args.sweep:
         sizes = sorted(set(range(2048, 19457, 512)) | {6004, 6015, 6016, 10004, 12031, 12032, 14004})
         sweep(fastmm, torch, sizes)
+        return
+    if args.sweep_pinned:
+        sweep_pinned(fastmm, torch, list(range(2048, 19457, 1024)))
         return
     if args.traffic_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")

@@ -1138,6 +1138,15 @@ void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
     if (depth < 0) {
       depth = pl.depth;
       leaf = pl.leaf;
+      // Host operands: below this extent the transfers bound the call, and
+      // the plain product's pipeline ends sooner than the Winograd one,
+      // whose last pieces (P2, P3) and result blocks wait for the last
+      // input blocks (pinned, best of 3: n = 6144 7.3 against 8.8 ms at the
+      // planner's depth 2, n = 8192 13.3 against 16.4 ms, n = 10240 21.9
+      // against 23.2 ms at depth 3; from n = 11264 on Winograd leads, 25.6
+      // against 32.5 ms).
+      constexpr int64_t kHostPlainBelow = 10752;
+      if (!on_dev && std::min(std::min(M, N), K) < kHostPlainBelow) depth = 0;
     }
     if (tile < 0) tile = pl.tile;
   }

@@ -34,9 +34,9 @@
 // P6 P7 P5) are done, so one block of one quadrant (under 1 ms of copy at
 // n = 19456) remains after the last piece.
 //
-// A plain product (depth 0) streams A's rows and B's columns in fifths
-// (quarters for smaller extents), alternately, and computes each block
-// C[r, c] as a piece once its two bands are in.
+// A plain product (depth 0) streams A's rows and B's columns in two to five
+// bands by size, alternately, and computes each block C[r, c] as a piece
+// once its two bands are in.
 //
 #include <hip/hip_runtime.h>
 
@@ -253,7 +253,7 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
   // ---- bands.  Winograd: row bands of the top quadrants' rows (m2) and
   // column bands of their columns (n2); a band of the bottom (right)
   // quadrants keeps only its valid rows (columns).  Plain product: A's rows
-  // and B's columns in fifths or quarters.
+  // and B's columns in two to five bands by size.
   std::vector<Band> bands, cbands;
   if (wino) {
     // Column bands only where B's quadrants are wide: for narrow ones (one
@@ -278,16 +278,23 @@ void gemm_host_pipelined(Library& L, int64_t M, int64_t N, int64_t K, const floa
     bands = make_bands(m2, mb, nrb, ra);
     cbands = make_bands(n2, nb, ncb, ca);
   } else {
-    // Fifths of M and of the padded width N4 where both hold at least 10240
-    // (the first piece starts sooner: 123 against 129 ms at n = 19456, 71.7
-    // against 73.4 ms at 19456 x 12288 x 16384), else quarters (narrower
-    // bands lose more to small pieces and short copy rows than they gain:
-    // 28.3 ms in quarters, 31.4 in fifths for 9728 x 4864 x 19456);
-    // FASTMM_PIPE_PLAINBANDS: 1 to 8 parts instead.  Parts are rounded up
-    // to whole tiles where the extent allows, so that there are at most that
-    // many bands; column bands start at multiples of 4, so that B's and C's
-    // rows in a band stay 16-byte aligned.
-    int np = std::min(M, N4) >= 10240 ? 5 : 4;
+    // A's rows and B's columns (the padded width N4) in np parts each, from
+    // measurements of the plain product on this path (best of 5 interleaved
+    // calls): halves where neither extent exceeds 4608 (3.6 against 4.7 ms
+    // in quarters at n = 4096; 12.5 against 16.6 ms for 4096 x 4096 x
+    // 16384), thirds up to 7168 (7.3 against 8.1 ms at n = 6144), fifths
+    // where both hold at least 10240 (the first piece starts sooner: 123
+    // against 129 ms at n = 19456, 71.7 against 73.4 ms at 19456 x 12288 x
+    // 16384), else quarters (13.3 ms at n = 8192 against 14.8 in thirds and
+    // 15.4 in fifths; 28.3 ms for 9728 x 4864 x 19456 against 29.5 and 31.1).
+    // Few bands delay the first piece, many bands make pieces too small to
+    // fill the device and copies of short rows slow.  FASTMM_PIPE_PLAINBANDS:
+    // 1 to 8 parts instead.  Parts are rounded up to whole tiles where the
+    // extent allows, so that there are at most np bands; column bands start
+    // at multiples of 4, so that B's and C's rows in a band stay 16-byte
+    // aligned.
+    const int64_t lo_ext = std::min(M, N4), hi_ext = std::max(M, N4);
+    int np = hi_ext <= 4608 ? 2 : hi_ext <= 7168 ? 3 : lo_ext >= 10240 ? 5 : 4;
     if (const char* e = std::getenv("FASTMM_PIPE_PLAINBANDS")) np = std::min(8, std::max(1, std::atoi(e)));
     auto parts = [np](int64_t x, int64_t t, int64_t a) {
       std::vector<Band> v;

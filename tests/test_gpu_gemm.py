@@ -489,13 +489,14 @@ def test_host_pipeline_band_layouts_exact(fastmm, monkeypatch, rows, cols):
     assert np.array_equal(classic.gemv(C, x), classic.gemv(A, classic.gemv(B, x)))
 
 
-@pytest.mark.parametrize("M,K,N,parts", [(10241, 515, 10243, None), (10240, 512, 10752, None),
-                                         (1000, 300, 1003, "1"), (1000, 300, 1003, "3"),
-                                         (1000, 300, 1003, "5"), (1000, 300, 1003, "8"),
-                                         (9001, 257, 10240, None)])
-def test_host_plain_bands_bitwise(fastmm, monkeypatch, M, K, N, parts):
+@pytest.mark.parametrize("M,K,N,parts,pieces", [(10241, 515, 10243, None, 25), (10240, 512, 10752, None, 25),
+                                                (1000, 300, 1003, "1", None), (1000, 300, 1003, "3", None),
+                                                (1000, 300, 1003, "5", None), (1000, 300, 1003, "8", None),
+                                                (9001, 257, 10240, None, 16), (4000, 300, 4100, None, 4),
+                                                (6000, 300, 5000, None, 9), (7169, 130, 3000, None, 16)])
+def test_host_plain_bands_bitwise(fastmm, monkeypatch, M, K, N, parts, pieces):
     # The plain product from host memory streams A's rows and B's columns in
-    # bands (fifths where both extents hold at least 10240, else quarters, or
+    # bands (halves, thirds, quarters or fifths by size, or
     # FASTMM_PIPE_PLAINBANDS parts) and computes each block C[r, c] as a
     # piece: every element is still the device-resident product's, bit for
     # bit, whatever the bands.
@@ -514,8 +515,8 @@ def test_host_plain_bands_bitwise(fastmm, monkeypatch, M, K, N, parts):
                 depth=0, leaf=1)
     st = fastmm.get_stats()
     assert st["depth"] == 0
-    if parts is None:  # fifths of both extents, else quarters: one leaf launch per piece
-        assert st["leaf_launches"] == (25 if min(M, N) >= 10240 else 16)
+    if pieces is not None:  # one leaf launch per piece
+        assert st["leaf_launches"] == pieces
     assert np.array_equal(Cp.numpy(), host(Cd))
     rows = synthgen.row_sample(183, M, 8)
     assert checks.sampled_rows_rel(Cp.numpy(), A, B, rows) <= 2e-6

@@ -133,6 +133,35 @@ def test_auto_depth_product_is_correct(fastmm):
     assert checks.rel_frob(host(C), classic.gemm(A, B)) < 1e-4
 
 
+def test_auto_depth_host_operands(fastmm):
+    # With host operands the automatic depth is 0 below a smallest extent of
+    # 10752 (the transfers bound the call there), and the planner's depth
+    # from it on; device operands keep the planner's depth.  The plain
+    # product from host memory is the device-resident one bit for bit.
+    import torch
+    fastmm.set_plan_mode(fastmm.PLAN_DEFAULT)
+    for n in (4096, 10752):
+        say(f"auto depth, host operands, n={n}")
+        A = uniform(931 + n, n, n)
+        B = uniform(932 + n, n, n)
+        Cp = torch.full((n, n), float("nan")).pin_memory()
+        fastmm.gemm(n, n, n, torch.from_numpy(A).pin_memory(), torch.from_numpy(B).pin_memory(), Cp,
+                    depth=fastmm.AUTO)
+        planned = fastmm.plan(n, n, n, fastmm.PLAN_DEFAULT).depth
+        got = fastmm.get_stats()["depth"]
+        Cd = torch.empty((n, n), device="cuda")
+        if n < 10752:
+            assert planned >= 1 and got == 0
+            fastmm.gemm(n, n, n, dev(A), dev(B), Cd, depth=fastmm.AUTO)
+            assert fastmm.get_stats()["depth"] == planned
+            fastmm.gemm(n, n, n, dev(A), dev(B), Cd, depth=0)
+            assert np.array_equal(Cp.numpy(), host(Cd))
+        else:
+            assert got == planned >= 1
+        rows = synthgen.row_sample(933, n, 8)
+        assert checks.sampled_rows_rel(Cp.numpy(), A, B, rows) <= 1e-4
+
+
 def test_model_file_errors(fastmm, tmp_path):
     bad = tmp_path / "short.bin"
     bad.write_bytes(b"\0" * 100)
