@@ -252,22 +252,39 @@ def sweep_pinned(fastmm, torch, sizes):
     """n-sweep of the paper's own measurement: A, B, C in pinned host
     memory, the transfers inside the wall-clock (Section 4), one JSON line
     per n: the plain MFMA SGEMM (depth 0) and Winograd at the fixed rule's
-    depth, both through the pipelined host path, best of 3 calls, and the
-    depth an automatic call with host operands takes."""
+    depth, both through the pipelined host path, and the depth an automatic
+    call with host operands takes.  The whole of each buffer is used a few
+    times first (the first device-to-host copies into freshly pinned memory
+    run at about half rate for a while); then the two are timed alternately,
+    the median of 5 calls each."""
     nmax = max(sizes)
     buf = [torch.empty(nmax * nmax, dtype=torch.float32, pin_memory=True) for _ in range(3)]
     buf[0].uniform_(-1, 1)
     buf[1].uniform_(-1, 1)
+    A, B, C = (x.view(nmax, nmax) for x in buf)
+    for _ in range(8):
+        for d in (0, 3):
+            fastmm.gemm(nmax, nmax, nmax, A, B, C, depth=d, leaf=1)
     for n in sizes:
         A, B, C = (x[:n * n].view(n, n) for x in buf)
         flops = 2.0 * n ** 3
         row = {"sweep_pinned_n": n}
         pl = fastmm.plan(n, n, n, fastmm.PLAN_DEFAULT)
-        for name, d in (("plain", 0), ("winograd", pl.depth)):
-            tot, ts = time_calls(lambda: fastmm.gemm(n, n, n, A, B, C, depth=d, leaf=pl.leaf), 3, 1)
-            row[name + "_ms"] = 1e3 * min(ts)
-            row[name + "_GFLOPS"] = flops / min(ts) / 1e9
-            row[name + "_depth"] = fastmm.get_stats()["depth"]
+        runs = {"plain": (0, 1), "winograd": (pl.depth, pl.leaf)}
+        ts = {k: [] for k in runs}
+        for k, (d, lf) in runs.items():
+            fastmm.gemm(n, n, n, A, B, C, depth=d, leaf=lf)
+        for _ in range(5):
+            for k, (d, lf) in runs.items():
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                fastmm.gemm(n, n, n, A, B, C, depth=d, leaf=lf)
+                ts[k].append(time.perf_counter() - t)
+                row[k + "_depth"] = fastmm.get_stats()["depth"]
+        for k in runs:
+            t = float(np.median(ts[k]))
+            row[k + "_ms"] = 1e3 * t
+            row[k + "_GFLOPS"] = flops / t / 1e9
         row["speedup"] = row["plain_ms"] / row["winograd_ms"]
         fastmm.gemm(n, n, n, A, B, C, depth=fastmm.AUTO)
         row["auto_depth"] = fastmm.get_stats()["depth"]

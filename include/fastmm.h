@@ -141,7 +141,7 @@ typedef struct {
  * depth >= 0: at most that many Winograd levels (0 = classic product on the
  * MFMA leaf kernel); depth < 0: the planner chooses depth, leaf and tile,
  * except that with host operands a product whose smallest extent is under
- * 10752 takes depth 0 (there the transfers bound the call, and the plain
+ * 6656 takes depth 0 (there the transfers bound the call, and the plain
  * product's pipeline finishes sooner).
  * leaf: a node (m, k, n) splits iff levels remain and
  * floor(min(m, k, n) / 2) >= max(leaf, 1) (leaf = 3008 reproduces the

@@ -1141,11 +1141,11 @@ void gemm_impl(Library& L, int64_t M, int64_t N, int64_t K, const float* A, int6
       // Host operands: below this extent the transfers bound the call, and
       // the plain product's pipeline ends sooner than the Winograd one,
       // whose last pieces (P2, P3) and result blocks wait for the last
-      // input blocks (pinned, best of 3: n = 6144 7.3 against 8.8 ms at the
-      // planner's depth 2, n = 8192 13.3 against 16.4 ms, n = 10240 21.9
-      // against 23.2 ms at depth 3; from n = 11264 on Winograd leads, 25.6
-      // against 32.5 ms).
-      constexpr int64_t kHostPlainBelow = 10752;
+      // input blocks (pinned, repeated calls, median of 6: n = 4096 3.5
+      // against 3.9 ms at the planner's depth 1, n = 6144 7.4 against 7.9 ms
+      // at depth 2; from n = 7168 on Winograd leads, 10.8 against 11.6 ms,
+      // except at 8192, 13.7 against 13.1 ms).
+      constexpr int64_t kHostPlainBelow = 6656;
       if (!on_dev && std::min(std::min(M, N), K) < kHostPlainBelow) depth = 0;
     }
     if (tile < 0) tile = pl.tile;

@@ -135,12 +135,12 @@ def test_auto_depth_product_is_correct(fastmm):
 
 def test_auto_depth_host_operands(fastmm):
     # With host operands the automatic depth is 0 below a smallest extent of
-    # 10752 (the transfers bound the call there), and the planner's depth
+    # 6656 (the transfers bound the call there), and the planner's depth
     # from it on; device operands keep the planner's depth.  The plain
     # product from host memory is the device-resident one bit for bit.
     import torch
     fastmm.set_plan_mode(fastmm.PLAN_DEFAULT)
-    for n in (4096, 10752):
+    for n in (4096, 6656):
         say(f"auto depth, host operands, n={n}")
         A = uniform(931 + n, n, n)
         B = uniform(932 + n, n, n)
@@ -150,7 +150,7 @@ def test_auto_depth_host_operands(fastmm):
         planned = fastmm.plan(n, n, n, fastmm.PLAN_DEFAULT).depth
         got = fastmm.get_stats()["depth"]
         Cd = torch.empty((n, n), device="cuda")
-        if n < 10752:
+        if n < 6656:
             assert planned >= 1 and got == 0
             fastmm.gemm(n, n, n, dev(A), dev(B), Cd, depth=fastmm.AUTO)
             assert fastmm.get_stats()["depth"] == planned
